@@ -1,0 +1,865 @@
+/*
+ * tpcref: plain CPU oracle of the TPC sector tracker.  TEST INFRASTRUCTURE:
+ * only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark use it.  It shares no code with the GPU library.
+ *
+ * Method: Rohr, LHCP 2017, Sec. 2 (sector tracker, Fig. 1a-c).  The paper
+ * gives the steps in prose; the formulas, cuts and tie-breaks below are the
+ * readings this project fixes, stated next to the code that applies them.
+ * The code favours being checkable by eye over speed: rows are kept sorted by
+ * z so that a window lookup is a binary search followed by an exact test of
+ * every hit in a slightly wider z range.
+ *
+ * Floating point: compiled without contraction (-ffp-contract=off) and without
+ * fast-math; std::fma appears exactly where the reading prescribes a fused
+ * multiply-add; / and sqrt are the correctly rounded IEEE operations.
+ */
+#include "tpcref.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <vector>
+
+namespace {
+
+/* ------------------------------------------------------------ margins --- */
+/* A decision a <= b has relative margin |a - b| / max(|a|, |b|, 1e-30).
+   Decisions closer than 1e-6 are counted: they are the ones where a
+   different rounding could flip the outcome. */
+struct Margins {
+  int64_t decisions = 0, near = 0;
+  double min_margin = std::numeric_limits<double>::infinity();
+  void note(double a, double b) {
+    double d = std::fabs(a - b);
+    double s = std::max(std::max(std::fabs(a), std::fabs(b)), 1e-30);
+    double m = d / s;
+    ++decisions;
+    if (m < 1e-6) ++near;
+    if (m < min_margin) min_margin = m;
+  }
+};
+
+/* lower-triangular index of a symmetric 5x5 matrix */
+inline int ci(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+template <typename F>
+struct Par {
+  int n_rows;
+  F wy, wz, link_chi2;
+  int min_chain;
+  F kB, ery, erz, max_sin, c22, c33, c44, r00, r11, nsig, wmax, pick_chi2;
+  int max_miss, min_hits, own_pct;
+  F inflate;
+  explicit Par(const tpcref_params_t &p)
+      : n_rows(p.n_rows), wy(p.link_wy), wz(p.link_wz), link_chi2(p.link_chi2),
+        min_chain(p.min_chain_hits), kB(p.kB), ery(p.err2_y), erz(p.err2_z),
+        max_sin(p.max_sinphi), c22(p.seed_c22), c33(p.seed_c33), c44(p.seed_c44),
+        r00(p.reset_c00), r11(p.reset_c11), nsig(p.pick_nsig), wmax(p.pick_win_max),
+        pick_chi2(p.pick_chi2), max_miss(p.max_miss), min_hits(p.min_track_hits),
+        own_pct(p.own_frac_pct), inflate(p.refit_inflate) {}
+};
+
+/* Track state at plane x: p = (y, z, sin phi, tan lambda, q/pT), cov C. */
+template <typename F>
+struct State {
+  F p[5];
+  F C[15];
+  F x;
+};
+
+/*
+ * Propagation of the state from its plane x to plane x1 in a field along z
+ * (Sec. 2: the online tracker propagates with Bz only).  In the transverse
+ * plane the trajectory is a circle of curvature k = kB * q/pT, so sin(phi)
+ * grows linearly in x; the y step over dx is dx * tan of the mean direction,
+ * which equals dx (s0 + s1) / (c0 + c1) exactly; the transverse arc length is
+ * the chord (signed like dx) times asin(u)/u with u = chord * |k| / 2,
+ * evaluated with the Maclaurin series of asin(u)/u to the u^8 term (one row
+ * step has u < 0.02).
+ *
+ * Reading of "simplified" Kalman filter: the Jacobian drops the curvature
+ * term of the arc length, i.e. dz/d(sin phi) and dz/d(q/pT) are taken as
+ * tan(lambda) * d(chord)/d(.) with d(chord) = (dy / chord) d(dy).
+ */
+template <typename F>
+bool propagate(const Par<F> &P, State<F> &s, F x1, Margins *mg) {
+  const F dx = x1 - s.x;
+  const F kk = P.kB * s.p[4];
+  const F s0 = s.p[2];
+  const F s1 = std::fma(kk, dx, s0);
+  if (mg) mg->note((double)std::fabs(s1), (double)P.max_sin);
+  if (!(std::fabs(s1) <= P.max_sin)) return false;
+  const F one = (F)1;
+  const F c0 = std::sqrt(std::fma(-s0, s0, one));
+  const F c1 = std::sqrt(std::fma(-s1, s1, one));
+  const F cc = c0 + c1;
+  const F tt = (s0 + s1) / cc;
+  const F dy = dx * tt;
+  const F ch2 = std::fma(dy, dy, dx * dx);
+  const F ch = std::sqrt(ch2);
+  const F chs = dx < (F)0 ? -ch : ch; /* the arc length has the sign of the step */
+  const F u2 = ch2 * kk * kk * (F)0.25;
+  F h = (F)(35.0 / 1152.0);
+  h = std::fma(u2, h, (F)(5.0 / 112.0));
+  h = std::fma(u2, h, (F)(3.0 / 40.0));
+  h = std::fma(u2, h, (F)(1.0 / 6.0));
+  h = std::fma(u2, h, one);
+  const F dS = chs * h;
+  const F t = s.p[3];
+
+  /* Jacobian entries (all others identity or zero) */
+  const F a = dx * ((F)2 + tt * (s0 / c0 + s1 / c1)) / cc; /* dy/ds0 */
+  const F b = dx * P.kB * dx * (one + tt * s1 / c1) / cc;  /* dy/dQ  */
+  const F g = ch > (F)0 ? t * (dy / chs) : (F)0;
+  const F cz = g * a;    /* dz/ds0 */
+  const F dzq = g * b;   /* dz/dQ  */
+  const F e = dS;        /* dz/dt  */
+  const F f = P.kB * dx; /* ds/dQ  */
+
+  s.p[0] = s.p[0] + dy;
+  s.p[1] = s.p[1] + t * dS;
+  s.p[2] = s1;
+  s.x = x1;
+
+  /* C <- F C F^T, expanded for the sparse F above. */
+  const F *C = s.C;
+  const F c00 = C[0], c10 = C[1], c11 = C[2], c20 = C[3], c21 = C[4], c22 = C[5];
+  const F c30 = C[6], c31 = C[7], c32 = C[8], c33 = C[9];
+  const F c40 = C[10], c41 = C[11], c42 = C[12], c43 = C[13], c44 = C[14];
+  /* rows 0..2 of F*C that are needed */
+  const F fc00 = c00 + a * c20 + b * c40;
+  const F fc02 = c20 + a * c22 + b * c42;
+  const F fc04 = c40 + a * c42 + b * c44;
+  const F fc10 = c10 + cz * c20 + e * c30 + dzq * c40;
+  const F fc11 = c11 + cz * c21 + e * c31 + dzq * c41;
+  const F fc12 = c21 + cz * c22 + e * c32 + dzq * c42;
+  const F fc13 = c31 + cz * c32 + e * c33 + dzq * c43;
+  const F fc14 = c41 + cz * c42 + e * c43 + dzq * c44;
+  const F fc20 = c20 + f * c40;
+  const F fc21 = c21 + f * c41;
+  const F fc22 = c22 + f * c42;
+  const F fc23 = c32 + f * c43;
+  const F fc24 = c42 + f * c44;
+  F *O = s.C;
+  O[0] = fc00 + a * fc02 + b * fc04;
+  O[1] = fc10 + a * fc12 + b * fc14;
+  O[2] = fc11 + cz * fc12 + e * fc13 + dzq * fc14;
+  O[3] = fc20 + a * fc22 + b * fc24;
+  O[4] = fc21 + cz * fc22 + e * fc23 + dzq * fc24;
+  O[5] = fc22 + f * fc24;
+  O[6] = c30 + a * c32 + b * c43;
+  O[7] = c31 + cz * c32 + e * c33 + dzq * c43;
+  O[8] = c32 + f * c43;
+  O[9] = c33;
+  O[10] = c40 + a * c42 + b * c44;
+  O[11] = c41 + cz * c42 + e * c43 + dzq * c44;
+  O[12] = c42 + f * c44;
+  O[13] = c43;
+  O[14] = c44;
+  return true;
+}
+
+/* chi^2 of measurement (ym, zm) against the state: r^T S^-1 r with
+   S = C[y,z block] + diag(err2_y, err2_z).  Returns false if S is singular. */
+template <typename F>
+bool chi2_2d(const Par<F> &P, const State<F> &s, F ym, F zm, F &chi2) {
+  const F r0 = ym - s.p[0];
+  const F r1 = zm - s.p[1];
+  const F s00 = s.C[0] + P.ery;
+  const F s10 = s.C[1];
+  const F s11 = s.C[2] + P.erz;
+  const F det = s00 * s11 - s10 * s10;
+  if (!(det > (F)0)) return false;
+  const F inv = (F)1 / det;
+  const F i00 = s11 * inv, i10 = -s10 * inv, i11 = s00 * inv;
+  const F v0 = i00 * r0 + i10 * r1;
+  const F v1 = i10 * r0 + i11 * r1;
+  chi2 = r0 * v0 + r1 * v1;
+  return true;
+}
+
+/* Kalman update with a 2-D measurement of (y, z): gain K = C H^T S^-1,
+   p += K r, C -= K H C (standard form, lower triangle kept). */
+template <typename F>
+bool update(const Par<F> &P, State<F> &s, F ym, F zm, F &chi2) {
+  const F r0 = ym - s.p[0];
+  const F r1 = zm - s.p[1];
+  const F s00 = s.C[0] + P.ery;
+  const F s10 = s.C[1];
+  const F s11 = s.C[2] + P.erz;
+  const F det = s00 * s11 - s10 * s10;
+  if (!(det > (F)0)) return false;
+  const F inv = (F)1 / det;
+  const F i00 = s11 * inv, i10 = -s10 * inv, i11 = s00 * inv;
+  const F v0 = i00 * r0 + i10 * r1;
+  const F v1 = i10 * r0 + i11 * r1;
+  chi2 = r0 * v0 + r1 * v1;
+  F k0[5], k1[5], cj0[5], cj1[5];
+  for (int k = 0; k < 5; ++k) {
+    cj0[k] = s.C[ci(k, 0)];
+    cj1[k] = s.C[ci(k, 1)];
+  }
+  for (int k = 0; k < 5; ++k) {
+    k0[k] = cj0[k] * i00 + cj1[k] * i10;
+    k1[k] = cj0[k] * i10 + cj1[k] * i11;
+  }
+  for (int k = 0; k < 5; ++k) s.p[k] = s.p[k] + k0[k] * r0 + k1[k] * r1;
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j <= i; ++j)
+      s.C[ci(i, j)] = s.C[ci(i, j)] - (k0[i] * cj0[j] + k1[i] * cj1[j]);
+  return true;
+}
+
+/* ------------------------------------------------------------- sector --- */
+template <typename F>
+struct Sector {
+  const Par<F> &P;
+  std::vector<F> rx;            /* row radii */
+  int n;
+  std::vector<F> y, z;
+  std::vector<int> row;
+  std::vector<std::vector<int>> ids; /* per row, ids sorted by (z, id) */
+  std::vector<std::vector<F>> zs;    /* per row, z in the same order */
+
+  Sector(const Par<F> &P_, const float *row_x, const float *cl, const uint8_t *rw, int n_)
+      : P(P_), rx(P_.n_rows), n(n_), y(n_), z(n_), row(n_), ids(P_.n_rows), zs(P_.n_rows) {
+    for (int r = 0; r < P.n_rows; ++r) rx[r] = (F)row_x[r];
+    for (int i = 0; i < n; ++i) {
+      y[i] = (F)cl[4 * i + 1];
+      z[i] = (F)cl[4 * i + 2];
+      row[i] = rw[i];
+      ids[row[i]].push_back(i);
+    }
+    for (int r = 0; r < P.n_rows; ++r) {
+      auto &v = ids[r];
+      std::sort(v.begin(), v.end(), [&](int a, int b) {
+        return z[a] < z[b] || (z[a] == z[b] && a < b);
+      });
+      zs[r].resize(v.size());
+      for (size_t k = 0; k < v.size(); ++k) zs[r][k] = z[v[k]];
+    }
+  }
+
+  /* All hits of row r with |y_h - yc| <= ly and |z_h - zc| <= lz.  The binary
+     search brackets a z range a little wider than the window; the exact test
+     is applied to each hit in it. */
+  template <typename Fn>
+  void window(int r, F yc, F zc, F ly, F lz, Fn &&fn) const {
+    const auto &zv = zs[r];
+    const double pad = 1e-3 + 1e-6 * std::fabs((double)zc) + 1e-3 * (double)lz;
+    const double lo = (double)zc - (double)lz - pad, hi = (double)zc + (double)lz + pad;
+    auto it = std::lower_bound(zv.begin(), zv.end(), lo,
+                               [](F a, double b) { return (double)a < b; });
+    for (size_t k = (size_t)(it - zv.begin()); k < zv.size() && (double)zv[k] <= hi; ++k) {
+      const int h = ids[r][k];
+      if (std::fabs(y[h] - yc) <= ly && std::fabs(z[h] - zc) <= lz) fn(h);
+    }
+  }
+};
+
+template <typename F>
+struct Tracklet {
+  tpcref_tracklet_t t;
+  std::vector<int> hits; /* ascending rows */
+};
+
+/*
+ * CA neighbour finding (Fig. 1a): for a hit in row i (1 <= i <= n_rows - 2)
+ * consider every pair (u in row i+1, d in row i-1) inside windows
+ * |dy| <= W dx, |dz| <= W dx around the hit.  The pair's deviation from a
+ * straight line is measured at x_i: e = (y, z)_h - interpolation of d -> u.
+ * The best pair minimises (chi2, id_u, id_d) lexicographically; it becomes
+ * the hit's (up, down) links if chi2 <= link_chi2.  Edge rows get no links.
+ */
+template <typename F>
+void find_links(const Sector<F> &S, std::vector<int> &up, std::vector<int> &dn, Margins &mg) {
+  const auto &P = S.P;
+  up.assign(S.n, -1);
+  dn.assign(S.n, -1);
+  for (int h = 0; h < S.n; ++h) {
+    const int i = S.row[h];
+    if (i < 1 || i > P.n_rows - 2) continue;
+    const F dxu = S.rx[i + 1] - S.rx[i];
+    const F dxd = S.rx[i] - S.rx[i - 1];
+    const F w = dxd / (dxd + dxu);
+    const F luy = P.wy * dxu, luz = P.wz * dxu, ldy = P.wy * dxd, ldz = P.wz * dxd;
+    const F yh = S.y[h], zh = S.z[h];
+    std::vector<int> U, D;
+    S.window(i + 1, yh, zh, luy, luz, [&](int u) { U.push_back(u); });
+    if (U.empty()) continue;
+    S.window(i - 1, yh, zh, ldy, ldz, [&](int d) { D.push_back(d); });
+    if (D.empty()) continue;
+    F best = std::numeric_limits<F>::infinity(), second = best;
+    int bu = -1, bd = -1;
+    for (int u : U)
+      for (int d : D) {
+        const F ey = yh - std::fma(S.y[u] - S.y[d], w, S.y[d]);
+        const F ez = zh - std::fma(S.z[u] - S.z[d], w, S.z[d]);
+        const F c2 = std::fma(ey, ey, ez * ez);
+        bool better = c2 < best || (c2 == best && (u < bu || (u == bu && d < bd)));
+        if (better) {
+          second = best;
+          best = c2;
+          bu = u;
+          bd = d;
+        } else if (c2 < second) {
+          second = c2;
+        }
+      }
+    mg.note((double)best, (double)P.link_chi2);
+    if (second < std::numeric_limits<F>::infinity()) mg.note((double)best, (double)second);
+    mg.note((double)std::fabs(S.y[bu] - yh), (double)luy);
+    mg.note((double)std::fabs(S.z[bu] - zh), (double)luz);
+    mg.note((double)std::fabs(S.y[bd] - yh), (double)ldy);
+    mg.note((double)std::fabs(S.z[bd] - zh), (double)ldz);
+    if (best <= P.link_chi2) {
+      up[h] = bu;
+      dn[h] = bd;
+    }
+  }
+}
+
+/*
+ * Link cleaning (Fig. 1b): a link survives only if it is reciprocal, i.e.
+ * up'[h] = u iff down[u] = h, and down'[h] = d iff up[d] = h.
+ */
+void clean_links(const std::vector<int> &up, const std::vector<int> &dn, std::vector<int> &upc,
+                 std::vector<int> &dnc) {
+  const int n = (int)up.size();
+  upc.assign(n, -1);
+  dnc.assign(n, -1);
+  for (int h = 0; h < n; ++h) {
+    if (up[h] >= 0 && dn[up[h]] == h) upc[h] = up[h];
+    if (dn[h] >= 0 && up[dn[h]] == h) dnc[h] = dn[h];
+  }
+}
+
+/* Nearest hit to the predicted (y, z) inside nsig predicted sigmas (capped),
+   by dy^2 + dz^2 with ties to the lower ID. */
+template <typename F>
+int search_row(const Sector<F> &S, const State<F> &st, int r, Margins &mg) {
+  const auto &P = S.P;
+  F wy = P.nsig * std::sqrt(st.C[0] + P.ery);
+  F wz = P.nsig * std::sqrt(st.C[2] + P.erz);
+  if (wy > P.wmax) wy = P.wmax;
+  if (wz > P.wmax) wz = P.wmax;
+  int best = -1;
+  F bd2 = std::numeric_limits<F>::infinity(), second = bd2;
+  S.window(r, st.p[0], st.p[1], wy, wz, [&](int h) {
+    const F dy = S.y[h] - st.p[0];
+    const F dz = S.z[h] - st.p[1];
+    const F d2 = std::fma(dy, dy, dz * dz);
+    if (d2 < bd2 || (d2 == bd2 && h < best)) {
+      second = bd2;
+      bd2 = d2;
+      best = h;
+    } else if (d2 < second) {
+      second = d2;
+    }
+  });
+  if (best >= 0) {
+    if (second < std::numeric_limits<F>::infinity()) mg.note((double)bd2, (double)second);
+    mg.note((double)std::fabs(S.y[best] - st.p[0]), (double)wy);
+    mg.note((double)std::fabs(S.z[best] - st.p[1]), (double)wz);
+  }
+  return best;
+}
+
+template <typename F>
+void to_out(const State<F> &s, double *p, double *C) {
+  for (int k = 0; k < 5; ++k) p[k] = (double)s.p[k];
+  if (C)
+    for (int k = 0; k < 15; ++k) C[k] = (double)s.C[k];
+}
+
+/*
+ * Track following with the Kalman filter (Fig. 1c).  Reading:
+ *  seed  at the chain's first hit: y, z measured; sin phi from the slope of
+ *        the chain's end points, tan lambda from their z slope times cos phi,
+ *        q/pT = 0; C = diag(err2_y, err2_z, c22, c33, c44).
+ *  pass 1 (outward) updates with the remaining chain hits, then visits every
+ *        further row: propagate, take the nearest hit inside the window and
+ *        accept it if chi2 <= pick_chi2; stop after max_miss rows in a row
+ *        without a hit, at the last row, or when propagation fails.
+ *  pass 2 (inward) restarts at the outermost hit from the pass-1 state and
+ *        the pass-1 covariance multiplied by refit_inflate (a soft restart:
+ *        the first hits of the refit cannot swing the direction far from the
+ *        pass-1 estimate, which keeps the linearisation honest; a hard restart
+ *        C = diag(reset_c00, reset_c11, c22, c33, c44) is used when
+ *        refit_inflate = 0), updates with all pass-1 hits in decreasing row
+ *        order (no cut), then continues below the chain start row by row as
+ *        in pass 1.
+ *  output the state after the last pass-2 update (innermost hit), the pass-2
+ *        chi2 and ndf = 2 n_hits - 5; tracklets with fewer than
+ *        min_track_hits hits are kept but flagged (status 1).
+ *  `replay`, when given, lists the hits to use instead of searching: the
+ *        pass-1 extra hits and the inward hits, each with its row.
+ */
+struct Replay {
+  std::vector<int> outward; /* pass-1 hits beyond the chain, ascending rows */
+  std::vector<int> inward;  /* inward hits, descending rows */
+};
+
+template <typename F>
+void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F> &T, Margins &mg,
+                  const Replay *rp) {
+  const auto &P = S.P;
+  tpcref_tracklet_t &o = T.t;
+  std::memset(&o, 0, sizeof(o));
+  o.start_id = chain[0];
+  o.n_chain = (int)chain.size();
+  o.status = 2;
+  const int L = (int)chain.size() - 1;
+  const int h0 = chain[0], hL = chain[L];
+  State<F> st;
+  const F one = (F)1;
+  {
+    const F x0 = S.rx[S.row[h0]], xL = S.rx[S.row[hL]];
+    const F dxs = xL - x0;
+    const F ty = (S.y[hL] - S.y[h0]) / dxs;
+    const F sn = ty / std::sqrt(std::fma(ty, ty, one));
+    const F tz = (S.z[hL] - S.z[h0]) / dxs;
+    const F tl = tz * std::sqrt(std::fma(-sn, sn, one));
+    st.p[0] = S.y[h0];
+    st.p[1] = S.z[h0];
+    st.p[2] = sn;
+    st.p[3] = tl;
+    st.p[4] = (F)0;
+    for (int k = 0; k < 15; ++k) st.C[k] = (F)0;
+    st.C[0] = P.ery;
+    st.C[2] = P.erz;
+    st.C[5] = P.c22;
+    st.C[9] = P.c33;
+    st.C[14] = P.c44;
+    st.x = x0;
+  }
+  std::vector<int> pass1(chain.begin(), chain.end());
+  F c2;
+  for (int k = 1; k <= L; ++k) {
+    const int h = chain[k];
+    if (!propagate(P, st, S.rx[S.row[h]], &mg)) return;
+    if (!update(P, st, S.y[h], S.z[h], c2)) return;
+  }
+  State<F> saved = st;
+  int row_out = S.row[hL];
+  /* pass 1: follow outward */
+  if (!rp) {
+    int miss = 0;
+    for (int r = row_out + 1; r < P.n_rows; ++r) {
+      if (!propagate(P, st, S.rx[r], &mg)) break;
+      const int h = search_row(S, st, r, mg);
+      bool took = false;
+      if (h >= 0) {
+        F c;
+        if (chi2_2d(P, st, S.y[h], S.z[h], c)) {
+          mg.note((double)c, (double)P.pick_chi2);
+          if (c <= P.pick_chi2 && update(P, st, S.y[h], S.z[h], c2)) {
+            pass1.push_back(h);
+            saved = st;
+            row_out = r;
+            took = true;
+          }
+        }
+      }
+      if (took) {
+        miss = 0;
+      } else if (++miss >= P.max_miss) {
+        break;
+      }
+    }
+  } else {
+    size_t k = 0;
+    for (int r = row_out + 1; r < P.n_rows && k < rp->outward.size(); ++r) {
+      if (!propagate(P, st, S.rx[r], nullptr)) return;
+      const int h = rp->outward[k];
+      if (S.row[h] == r) {
+        if (!update(P, st, S.y[h], S.z[h], c2)) return;
+        pass1.push_back(h);
+        saved = st;
+        row_out = r;
+        ++k;
+      }
+    }
+    if (k != rp->outward.size()) return;
+  }
+  /* pass 2: restart at the outermost hit and refit inward */
+  st = saved;
+  if (P.inflate > (F)0) {
+    for (int k = 0; k < 15; ++k) st.C[k] = st.C[k] * P.inflate;
+  } else {
+    for (int k = 0; k < 15; ++k) st.C[k] = (F)0;
+    st.C[0] = P.r00;
+    st.C[2] = P.r11;
+    st.C[5] = P.c22;
+    st.C[9] = P.c33;
+    st.C[14] = P.c44;
+  }
+  F chi2 = (F)0;
+  State<F> out_state;
+  const int n1 = (int)pass1.size();
+  for (int k = n1 - 1; k >= 0; --k) {
+    const int h = pass1[k];
+    if (k < n1 - 1 && !propagate(P, st, S.rx[S.row[h]], &mg)) return;
+    if (!update(P, st, S.y[h], S.z[h], c2)) return;
+    chi2 = chi2 + c2;
+  }
+  out_state = st;
+  std::vector<int> inward;
+  if (!rp) {
+    int miss = 0;
+    for (int r = S.row[h0] - 1; r >= 0; --r) {
+      if (!propagate(P, st, S.rx[r], &mg)) break;
+      const int h = search_row(S, st, r, mg);
+      bool took = false;
+      if (h >= 0) {
+        F c;
+        if (chi2_2d(P, st, S.y[h], S.z[h], c)) {
+          mg.note((double)c, (double)P.pick_chi2);
+          if (c <= P.pick_chi2 && update(P, st, S.y[h], S.z[h], c2)) {
+            chi2 = chi2 + c2;
+            inward.push_back(h);
+            out_state = st;
+            took = true;
+          }
+        }
+      }
+      if (took) {
+        miss = 0;
+      } else if (++miss >= P.max_miss) {
+        break;
+      }
+    }
+  } else {
+    size_t k = 0;
+    for (int r = S.row[h0] - 1; r >= 0 && k < rp->inward.size(); --r) {
+      if (!propagate(P, st, S.rx[r], nullptr)) return;
+      const int h = rp->inward[k];
+      if (S.row[h] == r) {
+        if (!update(P, st, S.y[h], S.z[h], c2)) return;
+        chi2 = chi2 + c2;
+        inward.push_back(h);
+        out_state = st;
+        ++k;
+      }
+    }
+    if (k != rp->inward.size()) return;
+  }
+  /* hits in ascending row order: inward hits reversed, then pass 1 */
+  T.hits.assign(inward.rbegin(), inward.rend());
+  T.hits.insert(T.hits.end(), pass1.begin(), pass1.end());
+  o.n_hits = (int)T.hits.size();
+  o.n_pass1 = n1;
+  o.ndf = 2 * o.n_hits - 5;
+  o.row_ref = S.row[T.hits.front()];
+  o.row_out = row_out;
+  o.x_ref = (double)out_state.x;
+  o.x_out = (double)saved.x;
+  o.chi2 = (double)chi2;
+  to_out(out_state, o.p, o.cov);
+  to_out(saved, o.p_out, o.cov_out);
+  o.status = o.n_hits < P.min_hits ? 1 : 0;
+}
+
+struct Result {
+  int n = 0;
+  std::vector<int> up, dn, upc, dnc;
+  std::vector<tpcref_tracklet_t> trk;
+  std::vector<std::vector<int>> trk_hits;
+  std::vector<int> acc_index;             /* accepted tracklet indices */
+  std::vector<std::vector<int>> acc_hits; /* won hits, ascending rows */
+  std::vector<int> assign;
+  Margins mg;
+};
+
+/*
+ * Selection (end of Sec. 2's sector tracker): every fitted tracklet claims
+ * its hits with a key ordered by more hits, then smaller chi2, then smaller
+ * start_id; a hit belongs to the largest key claiming it (one round, so the
+ * result does not depend on any order).  A tracklet is accepted if it wins at
+ * least min_track_hits hits and at least own_frac_pct percent of its hits;
+ * it keeps the hits it won, its parameters are not refitted.  Accepted tracks
+ * are listed in ascending start_id.
+ *
+ * The key packs n_hits (8 bits), the inverted FP32 bit pattern of chi2
+ * (32 bits; the bits of a non-negative float order like its value) and the
+ * inverted start_id (24 bits) into one 64-bit integer.
+ */
+uint64_t select_key(int n_hits, float chi2, int start_id) {
+  float c = chi2 > 0.0f ? chi2 : 0.0f;
+  uint32_t bits;
+  std::memcpy(&bits, &c, sizeof(bits));
+  return ((uint64_t)(uint32_t)n_hits << 56) | ((uint64_t)(0xFFFFFFFFu - bits) << 24) |
+         (uint64_t)(0xFFFFFFu - (uint32_t)start_id);
+}
+
+template <typename F>
+void select_tracks(const Sector<F> &S, Result &R) {
+  const auto &P = S.P;
+  std::vector<uint64_t> owner(S.n, 0);
+  const int T = (int)R.trk.size();
+  auto key = [&](int t) {
+    return select_key(R.trk[t].n_hits, (float)R.trk[t].chi2, R.trk[t].start_id);
+  };
+  for (int t = 0; t < T; ++t) {
+    if (R.trk[t].status != 0) continue;
+    for (int h : R.trk_hits[t]) owner[h] = std::max(owner[h], key(t));
+  }
+  R.assign.assign(S.n, -1);
+  for (int t = 0; t < T; ++t) {
+    if (R.trk[t].status != 0) continue;
+    std::vector<int> won;
+    for (int h : R.trk_hits[t])
+      if (owner[h] == key(t)) won.push_back(h);
+    const int nw = (int)won.size();
+    if (nw >= P.min_hits && nw * 100 >= P.own_pct * R.trk[t].n_hits) {
+      const int idx = (int)R.acc_index.size();
+      R.acc_index.push_back(t);
+      for (int h : won) R.assign[h] = idx;
+      R.acc_hits.push_back(std::move(won));
+    }
+  }
+}
+
+template <typename F>
+Result *run(const tpcref_params_t &pp, const float *row_x, const float *cl, const uint8_t *rw,
+            int n) {
+  Par<F> P(pp);
+  Sector<F> S(P, row_x, cl, rw, n);
+  auto R = std::make_unique<Result>();
+  R->n = n;
+  find_links(S, R->up, R->dn, R->mg);
+  clean_links(R->up, R->dn, R->upc, R->dnc);
+  /* chains start at hits with an up link and no down link (ascending ID) */
+  for (int h = 0; h < n; ++h) {
+    if (!(R->upc[h] >= 0 && R->dnc[h] < 0)) continue;
+    std::vector<int> chain;
+    for (int k = h; k >= 0; k = R->upc[k]) chain.push_back(k);
+    if ((int)chain.size() < P.min_chain) continue;
+    Tracklet<F> T;
+    fit_tracklet(S, chain, T, R->mg, nullptr);
+    R->trk.push_back(T.t);
+    R->trk_hits.push_back(std::move(T.hits));
+  }
+  select_tracks(S, *R);
+  return R.release();
+}
+
+template <typename F>
+void set_state(State<F> &s, const double *p, const double *C, double x) {
+  for (int k = 0; k < 5; ++k) s.p[k] = (F)p[k];
+  for (int k = 0; k < 15; ++k) s.C[k] = (F)C[k];
+  s.x = (F)x;
+}
+
+template <typename F>
+int32_t refit_impl(const tpcref_params_t &pp, const float *row_x, const float *cl,
+                          const uint8_t *rw, int32_t n, const int32_t *hits, int32_t nh, int32_t k0,
+                          int32_t n_chain, tpcref_tracklet_t *out) {
+  Par<F> P(pp);
+  Sector<F> S(P, row_x, cl, rw, n);
+  std::vector<int> chain(hits + k0, hits + k0 + n_chain);
+  Replay rp;
+  for (int k = k0 + n_chain; k < nh; ++k) rp.outward.push_back(hits[k]);
+  for (int k = k0 - 1; k >= 0; --k) rp.inward.push_back(hits[k]);
+  Tracklet<F> T;
+  Margins mg;
+  fit_tracklet(S, chain, T, mg, &rp);
+  *out = T.t;
+  return T.t.status == 2 ? -1 : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tpcref_params_default(tpcref_params_t *p) {
+  p->n_rows = 159;
+  p->link_wy = 2.0f;
+  p->link_wz = 2.0f;
+  p->link_chi2 = 0.2f;
+  p->min_chain_hits = 3;
+  p->kB = (float)(-0.5 * 0.299792458e-2);
+  p->err2_y = 0.01f;
+  p->err2_z = 0.01f;
+  p->max_sinphi = 0.95f;
+  p->seed_c22 = 0.25f;
+  p->seed_c33 = 0.25f;
+  p->seed_c44 = 400.0f;
+  p->reset_c00 = 1.0f;
+  p->reset_c11 = 1.0f;
+  p->pick_nsig = 3.0f;
+  p->pick_win_max = 4.0f;
+  p->pick_chi2 = 16.0f;
+  p->max_miss = 10;
+  p->min_track_hits = 10;
+  p->own_frac_pct = 90;
+  p->refit_inflate = 100.0f;
+}
+
+static bool valid_input(const tpcref_params_t *p, const float *row_x, const float *cl,
+                        const uint8_t *row, int32_t n) {
+  if (!p || !row_x || n < 0 || (n > 0 && (!cl || !row))) return false;
+  if (p->n_rows < 3 || p->n_rows > 255) return false;
+  if (n > 0xFFFFFF) return false; /* IDs must fit the 24 bits of the selection key */
+  for (int32_t i = 0; i < n; ++i) {
+    if (row[i] >= p->n_rows) return false;
+    const float *c = cl + 4 * i;
+    if (!std::isfinite(c[0]) || !std::isfinite(c[1]) || !std::isfinite(c[2])) return false;
+    if (std::fabs(c[0] - row_x[row[i]]) > 1e-3f) return false;
+  }
+  return true;
+}
+
+void *tpcref_run(const tpcref_params_t *p, const float *row_x, const float *cl, const uint8_t *row,
+                 int32_t n, int32_t precision, int32_t *err) {
+  if (err) *err = 0;
+  if (!valid_input(p, row_x, cl, row, n) || (precision != 32 && precision != 64)) {
+    if (err) *err = -1;
+    return nullptr;
+  }
+  if (precision == 32) return run<float>(*p, row_x, cl, row, n);
+  return run<double>(*p, row_x, cl, row, n);
+}
+
+void tpcref_free(void *r) { delete static_cast<Result *>(r); }
+
+int32_t tpcref_n_clusters(const void *r) { return static_cast<const Result *>(r)->n; }
+int32_t tpcref_n_tracklets(const void *r) {
+  return (int32_t) static_cast<const Result *>(r)->trk.size();
+}
+int32_t tpcref_n_tracks(const void *r) {
+  return (int32_t) static_cast<const Result *>(r)->acc_index.size();
+}
+int64_t tpcref_n_tracklet_hits(const void *r) {
+  int64_t s = 0;
+  for (auto &v : static_cast<const Result *>(r)->trk_hits) s += (int64_t)v.size();
+  return s;
+}
+int64_t tpcref_n_track_hits(const void *r) {
+  int64_t s = 0;
+  for (auto &v : static_cast<const Result *>(r)->acc_hits) s += (int64_t)v.size();
+  return s;
+}
+
+void tpcref_get_links(const void *r, int32_t which, int32_t *up, int32_t *down) {
+  const Result *R = static_cast<const Result *>(r);
+  const auto &u = which ? R->upc : R->up;
+  const auto &d = which ? R->dnc : R->dn;
+  for (int i = 0; i < R->n; ++i) {
+    if (up) up[i] = u[i];
+    if (down) down[i] = d[i];
+  }
+}
+
+void tpcref_get_tracklets(const void *r, tpcref_tracklet_t *out, int64_t *hit_begin,
+                          int32_t *hits) {
+  const Result *R = static_cast<const Result *>(r);
+  int64_t off = 0;
+  for (size_t t = 0; t < R->trk.size(); ++t) {
+    if (out) out[t] = R->trk[t];
+    if (hit_begin) hit_begin[t] = off;
+    for (int h : R->trk_hits[t]) {
+      if (hits) hits[off] = h;
+      ++off;
+    }
+  }
+  if (hit_begin) hit_begin[R->trk.size()] = off;
+}
+
+void tpcref_get_tracks(const void *r, int32_t *tracklet_index, int64_t *hit_begin, int32_t *hits) {
+  const Result *R = static_cast<const Result *>(r);
+  int64_t off = 0;
+  for (size_t t = 0; t < R->acc_index.size(); ++t) {
+    if (tracklet_index) tracklet_index[t] = R->acc_index[t];
+    if (hit_begin) hit_begin[t] = off;
+    for (int h : R->acc_hits[t]) {
+      if (hits) hits[off] = h;
+      ++off;
+    }
+  }
+  if (hit_begin) hit_begin[R->acc_index.size()] = off;
+}
+
+void tpcref_get_assignment(const void *r, int32_t *a) {
+  const Result *R = static_cast<const Result *>(r);
+  for (int i = 0; i < R->n; ++i) a[i] = R->assign[i];
+}
+
+void tpcref_get_stats(const void *r, tpcref_stats_t *s) {
+  const Result *R = static_cast<const Result *>(r);
+  s->decisions = R->mg.decisions;
+  s->near_ties = R->mg.near;
+  s->min_margin = R->mg.min_margin;
+}
+
+int32_t tpcref_refit(const tpcref_params_t *p, const float *row_x, const float *cl,
+                     const uint8_t *row, const int32_t *hits, int32_t n_hits, int32_t k0,
+                     int32_t n_chain, int32_t precision, tpcref_tracklet_t *out) {
+  if (!p || !row_x || !cl || !row || !hits || !out || n_chain < 2 || k0 < 0 ||
+      k0 + n_chain > n_hits)
+    return -1;
+  /* the sector is rebuilt from the hits only: enough for a replay */
+  std::vector<float> c(4 * (size_t)n_hits);
+  std::vector<uint8_t> r(n_hits);
+  std::vector<int32_t> local(n_hits);
+  for (int32_t k = 0; k < n_hits; ++k) {
+    std::memcpy(&c[4 * (size_t)k], cl + 4 * (size_t)hits[k], 4 * sizeof(float));
+    r[k] = row[hits[k]];
+    local[k] = k;
+  }
+  if (precision == 32)
+    return refit_impl<float>(*p, row_x, c.data(), r.data(), n_hits, local.data(), n_hits, k0,
+                             n_chain, out);
+  if (precision == 64)
+    return refit_impl<double>(*p, row_x, c.data(), r.data(), n_hits, local.data(), n_hits, k0,
+                              n_chain, out);
+  return -1;
+}
+
+int32_t tpcref_propagate(const tpcref_params_t *p, int32_t precision, double *state, double *cov,
+                         double *x, double x1) {
+  if (precision == 32) {
+    Par<float> P(*p);
+    State<float> s;
+    set_state(s, state, cov, *x);
+    bool ok = propagate(P, s, (float)x1, nullptr);
+    to_out(s, state, cov);
+    *x = s.x;
+    return ok ? 0 : -1;
+  }
+  Par<double> P(*p);
+  State<double> s;
+  set_state(s, state, cov, *x);
+  bool ok = propagate(P, s, x1, nullptr);
+  to_out(s, state, cov);
+  *x = s.x;
+  return ok ? 0 : -1;
+}
+
+int32_t tpcref_update(const tpcref_params_t *p, int32_t precision, double *state, double *cov,
+                      double ym, double zm, double *chi2) {
+  if (precision == 32) {
+    Par<float> P(*p);
+    State<float> s;
+    set_state(s, state, cov, 0.0);
+    float c = 0;
+    bool ok = update(P, s, (float)ym, (float)zm, c);
+    to_out(s, state, cov);
+    *chi2 = c;
+    return ok ? 0 : -1;
+  }
+  Par<double> P(*p);
+  State<double> s;
+  set_state(s, state, cov, 0.0);
+  double c = 0;
+  bool ok = update(P, s, ym, zm, c);
+  to_out(s, state, cov);
+  *chi2 = c;
+  return ok ? 0 : -1;
+}
+
+}  // extern "C"
