@@ -1,0 +1,295 @@
+/*
+ * tpcca.h - C ABI of the MI355X (gfx950) TPC sector tracker.
+ *
+ * The library implements the first phase of the online TPC track finder of
+ * Rohr, "Tracking performance in high multiplicities environment at ALICE"
+ * (LHCP 2017), Sec. 2: per TPC sector, a Cellular Automaton forms links of
+ * hits in adjacent pad rows that lie close to a straight line (Fig. 1a) and
+ * concatenates them into short track candidates (Fig. 1b); track following
+ * fits every candidate with a simplified Kalman filter, extrapolates through
+ * the sector and picks up further clusters (Fig. 1c); the last step selects
+ * good tracks and assigns each cluster to at most one track.  The paper gives
+ * the steps in prose; the cuts and formulas (the "readings") are fixed by the
+ * parameters below and documented with the kernels.
+ *
+ * Units of work are (slot, sector) pairs: a slot is an event or a time frame,
+ * a sector one of the 36 TPC sectors.  Several units are processed in one
+ * launch per stage; Sec. 2 notes that even a central Pb-Pb event is too small
+ * to fill a GPU, and Sec. 5 that time frames of continuous read-out will be
+ * tracked as a whole.
+ *
+ * Conventions
+ *   - Cluster IDs are positions 0..n-1 inside the unit's input array.
+ *   - Coordinates are FP32 in the sector frame (cm); x must equal the pad
+ *     row's radius row_x[row] (within 1e-3 cm).
+ *   - Every call returns a status code (TPCCA_OK or a negative error).
+ *   - A context is used by one host thread at a time; a server is thread-safe.
+ *   - Work is queued on the context's HIP stream; results are only defined
+ *     after tpcca_sync() (the get functions synchronise themselves).
+ */
+#ifndef TPCCA_H
+#define TPCCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status --- */
+#define TPCCA_OK 0
+#define TPCCA_EINVAL (-1)    /* bad argument, row >= n_rows, |x - row_x| > 1e-3, non-finite */
+#define TPCCA_ENOMEM (-2)    /* device budget exceeded */
+#define TPCCA_ECAPACITY (-3) /* output buffer too small; *_out holds the size needed */
+#define TPCCA_EDEVICE (-4)   /* HIP runtime error; text in tpcca_last_error() */
+#define TPCCA_ESTATE (-5)    /* stage called out of order, or unit not loaded */
+#define TPCCA_EBUSY (-6)     /* server queue full; retry later */
+#define TPCCA_ENOTFOUND (-7) /* unknown request id */
+
+/* where input pointers live */
+#define TPCCA_MEM_HOST 0
+#define TPCCA_MEM_DEVICE 1
+/* run_batch option: replay the stage sequence as a captured HIP graph */
+#define TPCCA_BATCH_GRAPH 2
+
+/* ------------------------------------------------------------- types --- */
+typedef struct {
+  float x, y, z, q; /* sector frame (cm); q is carried, not used */
+} tpcca_cluster_t;  /* 16 B */
+
+typedef struct {
+  int32_t n_sectors;  /* 36 */
+  int32_t n_rows;     /* pad rows, 3..255 (159) */
+  const float *row_x; /* host array of n_rows radii (cm), copied at create */
+} tpcca_geometry_t;
+
+/* Cuts and constants of the reading of Sec. 2; defaults from
+   tpcca_params_default().  Field order is part of the ABI. */
+typedef struct {
+  int32_t n_rows;          /* must equal the geometry's n_rows */
+  float link_wy, link_wz;  /* neighbour windows |dy|, |dz| <= W * row distance (2.0) */
+  float link_chi2;         /* max straight-line deviation^2 of a link triplet (0.2 cm^2) */
+  int32_t min_chain_hits;  /* shortest chain that seeds a tracklet (3) */
+  float kB;                /* curvature per q/pT: -Bz * 0.299792458e-2 (Bz = 0.5 T) */
+  float err2_y, err2_z;    /* cluster variances (0.01 cm^2) */
+  float max_sinphi;        /* propagation fails beyond |sin phi| (0.95) */
+  float seed_c22, seed_c33, seed_c44; /* seed variances of sin phi, tan lambda, q/pT */
+  float reset_c00, reset_c11;         /* hard-restart variances (refit_inflate = 0) */
+  float pick_nsig;         /* search window in predicted sigmas (3) */
+  float pick_win_max;      /* cap of the search half-window (4 cm) */
+  float pick_chi2;         /* accept a picked cluster if chi2 <= this (16) */
+  int32_t max_miss;        /* stop following after this many empty rows (10) */
+  int32_t min_track_hits;  /* minimum hits of a tracklet and won hits of a track (10) */
+  int32_t own_frac_pct;    /* a track must win this percentage of its hits (90) */
+  float refit_inflate;     /* pass-2 restart: pass-1 covariance x this (100); 0 = hard */
+  int32_t grid_hits_per_bin; /* z-bin occupancy target of the row grid (tuning only) */
+} tpcca_params_t;
+
+/* An accepted track (FP32).  Parameters at plane x_ref (the innermost hit's
+   row): y, z, sin phi, tan lambda, q/pT; cov is the lower triangle, row-major
+   (00,10,11,20,21,22,30,...,44).  hit_offset indexes the unit's hit list
+   returned with the tracks; n_hits counts the won (assigned) clusters. */
+typedef struct {
+  float x_ref;
+  float p[5];
+  float cov[15];
+  float chi2;
+  int32_t ndf;        /* 2 * (hits in the fit) - 5 */
+  int32_t n_hits;
+  int32_t hit_offset;
+  int32_t sector;
+  int32_t start_id;   /* cluster ID of the seeding chain's first hit */
+} tpcca_track_t;      /* 108 B */
+
+/* A fitted candidate before selection (parity and diagnostics). */
+typedef struct {
+  int32_t start_id, n_chain, status; /* status: 0 fitted, 1 < min_track_hits, 2 failure */
+  int32_t n_hits, n_pass1, ndf, row_ref, row_out;
+  float x_ref, chi2, x_out;
+  float p[5];
+  float cov[15];
+  float p_out[5];     /* pass-1 state at the outermost hit */
+  float cov_out[15];  /* pass-1 covariance there */
+} tpcca_tracklet_t;
+
+/* Per-unit summary of a processed batch. */
+typedef struct {
+  int32_t slot, sector, n_clusters, n_tracklets;
+  int32_t n_tracks, n_track_hits;
+  int64_t cluster_begin; /* unit's first cluster in the batch's assignment array */
+  int64_t track_begin;   /* unit's first track in the batch's track array */
+  int64_t hit_begin;     /* unit's first hit in the batch's hit array */
+} tpcca_unit_result_t;
+
+/* Many units in one call.  Unit u's clusters are cl[begin[u] .. begin[u]+n[u])
+   and rows row[begin[u] ..]; cl/row are host or device pointers (flags). */
+typedef struct {
+  int32_t n_units;
+  const int32_t *slot;   /* host arrays of n_units entries */
+  const int32_t *sector;
+  const int64_t *begin;
+  const int32_t *n;
+  const tpcca_cluster_t *cl;
+  const uint8_t *row;
+  int32_t flags;         /* TPCCA_MEM_HOST or TPCCA_MEM_DEVICE, | TPCCA_BATCH_GRAPH */
+} tpcca_batch_t;
+
+/* Device views of a processed batch (valid until the next load/reset). */
+typedef struct {
+  const tpcca_track_t *tracks; /* all units, in unit order */
+  const int32_t *hits;         /* cluster IDs (unit-local) of the tracks' won hits */
+  const int32_t *assignment;   /* per input cluster, unit-local track index or -1 */
+  const tpcca_unit_result_t *units;
+  int32_t n_units;
+} tpcca_device_results_t;
+
+typedef struct tpcca_ctx tpcca_ctx_t;
+
+/* ----------------------------------------------------------- context --- */
+void tpcca_params_default(tpcca_params_t *p);
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to
+   queue work on (e.g. torch.cuda.Stream().cuda_stream) or NULL for a
+   context-owned stream.  device_budget_bytes caps the device memory the
+   context allocates (0 = 64 GiB).  Errors: EINVAL, EDEVICE. */
+int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int device,
+                 void *hip_stream, size_t device_budget_bytes, tpcca_ctx_t **out);
+int tpcca_destroy(tpcca_ctx_t *ctx);
+
+/* Forget every loaded unit (device memory is kept for reuse). */
+int tpcca_reset(tpcca_ctx_t *ctx);
+
+/* Append unit (slot, sector) with n clusters.  flags = TPCCA_MEM_HOST: the
+   clusters are copied (asynchronously from a pinned staging buffer) and the
+   caller may reuse its buffers on return.  TPCCA_MEM_DEVICE: the pointers are
+   device addresses read in place; they must stay valid until tpcca_sync().
+   Validation of rows and coordinates happens on the device; a bad cluster
+   makes the next stage call's tpcca_sync() return EINVAL.  A (slot, sector)
+   may be loaded once per reset.  Errors: EINVAL, ENOMEM, ESTATE. */
+int tpcca_load_sector(tpcca_ctx_t *ctx, int32_t slot, int32_t sector, const tpcca_cluster_t *cl,
+                      const uint8_t *row, int32_t n, int32_t flags);
+
+/* Stages (Sec. 2).  slot / sector = -1 select every loaded value; all
+   selected units go through one launch per kernel.  Each stage requires the
+   previous one on the same units (ESTATE otherwise). */
+int tpcca_find_links(tpcca_ctx_t *ctx, int32_t slot, int32_t sector);      /* Fig. 1a */
+int tpcca_clean_links(tpcca_ctx_t *ctx, int32_t slot, int32_t sector);     /* Fig. 1b */
+int tpcca_build_tracklets(tpcca_ctx_t *ctx, int32_t slot, int32_t sector); /* Fig. 1c */
+int tpcca_select_tracks(tpcca_ctx_t *ctx, int32_t slot, int32_t sector);   /* selection */
+
+/* Wait for queued work; report deferred device-side validation errors. */
+int tpcca_sync(tpcca_ctx_t *ctx);
+
+/* Links of one unit in cluster-ID space (-1 = none).  which = 0: as found,
+   1: after cleaning.  n must equal the unit's cluster count. */
+int tpcca_get_links(tpcca_ctx_t *ctx, int32_t slot, int32_t sector, int32_t which, int32_t *up,
+                    int32_t *down, int32_t n);
+
+/* Tracklets of one unit in ascending start_id; hits (cluster IDs, ascending
+   rows) concatenated, hit_begin has n+1 entries.  ECAPACITY with the needed
+   sizes in *n_out / *n_hits_out when cap or hits_cap is too small. */
+int tpcca_get_tracklets(tpcca_ctx_t *ctx, int32_t slot, int32_t sector, tpcca_tracklet_t *out,
+                        int32_t cap, int32_t *n_out, int64_t *hit_begin, int32_t *hits,
+                        int64_t hits_cap, int64_t *n_hits_out);
+
+/* Accepted tracks of one unit (ascending start_id) and their won hits. */
+int tpcca_get_tracks(tpcca_ctx_t *ctx, int32_t slot, int32_t sector, tpcca_track_t *out,
+                     int32_t cap, int32_t *n_out, int32_t *hits, int64_t hits_cap,
+                     int64_t *n_hits_out);
+
+/* Per cluster ID: index into the unit's track list, or -1. */
+int tpcca_get_assignment(tpcca_ctx_t *ctx, int32_t slot, int32_t sector, int32_t *track_of_cluster,
+                         int32_t n);
+
+/* Reset, load every unit of the batch and run all stages on all of them in
+   one launch per kernel (TPCCA_BATCH_GRAPH: as a replayed HIP graph of
+   persistent kernels whose work counts live in device memory).  Does not
+   synchronise.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int tpcca_run_batch(tpcca_ctx_t *ctx, const tpcca_batch_t *batch);
+
+/* Copy the whole batch's results to the host: units (n_units entries),
+   tracks, hits and assignment (total clusters).  Any pointer may be NULL. */
+int tpcca_get_batch_results(tpcca_ctx_t *ctx, tpcca_unit_result_t *units, tpcca_track_t *tracks,
+                            int64_t tracks_cap, int32_t *hits, int64_t hits_cap,
+                            int32_t *assignment, int64_t n_clusters);
+int tpcca_batch_totals(tpcca_ctx_t *ctx, int32_t *n_units, int64_t *n_clusters, int64_t *n_tracks,
+                       int64_t *n_hits);
+/* Device pointers to the batch results (no copy; synchronises). */
+int tpcca_device_results(tpcca_ctx_t *ctx, tpcca_device_results_t *out);
+
+/* Error text of a status code, and the last HIP/runtime message of ctx. */
+const char *tpcca_error_string(int status);
+const char *tpcca_last_error(tpcca_ctx_t *ctx);
+
+/* Stage timing of the last run_batch / stage sequence on ctx's stream, via
+   HIP events (ms): index 0 grid, 1 links, 2 clean, 3 tracklets(chains+fit),
+   4 selection.  Returns the number of entries written. */
+int tpcca_stage_times(tpcca_ctx_t *ctx, float *ms, int32_t cap);
+/* Enable/disable per-stage event recording (off by default). */
+int tpcca_set_timing(tpcca_ctx_t *ctx, int32_t enable);
+
+/* ------------------------------------------------------------ server --- */
+/* Continuous batching of time frames (Sec. 5: time frames are tracked as a
+   whole; GPU memory is the limit, a frame larger than memory is sliced, here
+   by sector).  Requests are admitted while their bytes fit the device
+   budget; admitted units of all waiting frames are packed into batches that
+   run on n_streams streams concurrently. */
+typedef struct tpcca_server tpcca_server_t;
+
+typedef struct {
+  int32_t n_units;
+  const int32_t *sector;        /* host arrays */
+  const int64_t *begin;
+  const int32_t *n;
+  const tpcca_cluster_t *cl;    /* host memory; must stay valid until done */
+  const uint8_t *row;
+  /* outputs (host, caller-owned, valid until the request completes):
+     tracks, hits: capacity-checked; assignment: sum(n) entries */
+  tpcca_track_t *tracks;
+  int64_t tracks_cap;
+  int32_t *hits;
+  int64_t hits_cap;
+  int32_t *assignment;
+  tpcca_unit_result_t *units;   /* n_units entries */
+  double arrival_s;             /* caller's arrival stamp (steady clock, s); 0 = now */
+} tpcca_timeframe_t;
+
+typedef struct {
+  int32_t status;       /* TPCCA_OK or error of this request */
+  int32_t done;         /* 1 when complete */
+  int64_t n_tracks, n_hits;
+  double arrival_s, start_s, end_s; /* steady-clock seconds */
+} tpcca_result_t;
+
+typedef struct {
+  int64_t submitted, completed, rejected, clusters_done, tracks_done;
+  int64_t bytes_in_flight, bytes_budget;
+  int32_t queue_depth, batches_run;
+  double busy_s;        /* wall time with at least one batch in flight */
+  double p50_ms, p99_ms, mean_ms; /* latency = end - arrival over completed requests */
+} tpcca_stats_t;
+
+int tpcca_server_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int device,
+                        size_t budget_bytes, int32_t n_streams, int32_t max_queue,
+                        tpcca_server_t **out);
+/* Non-blocking; EBUSY when the queue is full, ENOMEM when one unit alone
+   exceeds the budget, EINVAL on bad descriptors. */
+int tpcca_server_submit(tpcca_server_t *srv, const tpcca_timeframe_t *tf, uint64_t *req_id);
+int tpcca_server_poll(tpcca_server_t *srv, uint64_t req_id, tpcca_result_t *res);
+/* Block until done or timeout_s elapses (returns EBUSY on timeout). */
+int tpcca_server_wait(tpcca_server_t *srv, uint64_t req_id, double timeout_s, tpcca_result_t *res);
+/* Forget a completed request's record. */
+int tpcca_server_release(tpcca_server_t *srv, uint64_t req_id);
+int tpcca_server_stats(tpcca_server_t *srv, tpcca_stats_t *st);
+int tpcca_server_reset_stats(tpcca_server_t *srv);
+/* Stop accepting, finish in-flight work, free everything. */
+int tpcca_server_destroy(tpcca_server_t *srv);
+
+/* Seconds on the steady clock the server stamps with. */
+double tpcca_now(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPCCA_H */

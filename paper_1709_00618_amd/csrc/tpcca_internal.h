@@ -1,0 +1,110 @@
+// Internal layout shared by the gfx950 kernels and the host runtime of the
+// GPU library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tpcca.h"
+
+namespace tpcca {
+
+constexpr int kMaxRows = 255;
+constexpr int kChunk = 1024;        // clusters per chunk (block work unit)
+constexpr int kBlock = 256;         // threads per block of the cluster kernels
+constexpr int kScanTile = 2048;     // elements per tile of the device scans
+constexpr int kKfBlock = 128;       // threads per block of the Kalman filter
+
+// One (slot, sector) unit.  Work arrays are indexed by global cluster index:
+// the unit owns [cl_begin, cl_begin + n) of every per-cluster array.
+struct UnitDev {
+  const float4 *cl;      // input clusters (device address)
+  const uint8_t *row;    // input pad rows (device address)
+  int64_t bin_base;      // first entry of the unit's bin-begin table
+  int32_t cl_begin;
+  int32_t n;
+  int32_t trk_base;      // first tracklet slot reserved for the unit
+  int32_t slot, sector;
+  int32_t pad_;
+};
+
+// A chunk of <= kChunk consecutive clusters of one unit.
+struct Chunk {
+  int32_t unit;
+  int32_t begin;  // unit-local
+  int32_t count;
+  int32_t pad_;
+};
+
+// Per (unit, row) grid description; row n_rows is the dump row of invalid
+// clusters.  Bins split the row in z; entries bin0 .. bin0 + nb hold the
+// sorted index where each bin starts (the last one is the row's end).
+struct RowTab {
+  int32_t begin;  // global sorted index of the row's first hit
+  int32_t count;
+  int32_t nb;
+  int32_t pad_;
+  int64_t bin0;
+  float z0, inv;  // bin(z) = clamp(floor((z - z0) * inv), 0, nb - 1)
+};
+
+// Everything one launch needs to know about the units it processes.  The
+// host writes the static part; the device fills the counters.
+struct RunDev {
+  int32_t u0, u1;       // units [u0, u1)
+  int32_t c0, c1;       // chunks [c0, c1)
+  int32_t cl0, cl1;     // global clusters [cl0, cl1)
+  int64_t bin0, bin1;   // bin-begin entries [bin0, bin1)
+  int32_t trk0;         // first tracklet slot of the run
+  int32_t trk_cap;      // tracklet slots reserved for the run
+  // device-written
+  int32_t n_trk;
+  int32_t n_acc;
+  int64_t n_acc_hits;
+  int32_t err;          // 1: invalid cluster seen
+  int32_t pad_;
+};
+
+// Device-side parameters (FP32 copies of tpcca_params_t).
+struct ParamsDev {
+  int32_t n_rows;
+  float wy, wz, link_chi2;
+  int32_t min_chain;
+  float kB, ery, erz, max_sin, c22, c33, c44, r00, r11, nsig, wmax, pick_chi2;
+  int32_t max_miss, min_hits, own_pct;
+  float inflate;
+  int32_t hits_per_bin;
+};
+
+// Device buffers of a context (all indices global).
+struct Bufs {
+  const float *row_x;
+  UnitDev *units;
+  Chunk *chunks;
+  RunDev *runs;
+  RowTab *rowtab;        // units x (n_rows + 1)
+  int32_t *row_cnt;      // units x (n_rows + 1)
+  int32_t *zmm;          // units x 2 (ordered-int min, max)
+  int32_t *bincnt;       // bins
+  int32_t *binbeg;       // bins
+  float2 *yz;            // sorted hits
+  int32_t *sid;          // sorted -> unit-local cluster ID
+  int32_t *up, *dn;      // raw links (sorted indices)
+  int32_t *upc, *dnc;    // cleaned links
+  int32_t *flag;         // by global cluster index: start sorted index + 1, or 0
+  int32_t *trk_start;    // tracklet -> sorted index of its start hit
+  int32_t *trk_unit;     // tracklet -> unit
+  int32_t *unit_tbegin;  // unit -> first tracklet
+  tpcca_tracklet_t *trk; // tracklet fits
+  int32_t *trk_hits;     // tracklet x n_rows sorted indices
+  unsigned long long *owner;  // by sorted index
+  unsigned long long *accv;   // by tracklet: accepted << 40 | won hits
+  unsigned long long *accx;   // exclusive scan of accv (+ total)
+  tpcca_track_t *tracks;      // by tracklet slot of the run (compacted)
+  int32_t *hits_out;          // by global cluster index (compacted per run)
+  int32_t *assign;            // by global cluster index
+  tpcca_unit_result_t *unit_res;
+  int64_t *scan_tmp;          // tile sums
+  int32_t *ids_tmp;           // translation scratch
+};
+
+}  // namespace tpcca

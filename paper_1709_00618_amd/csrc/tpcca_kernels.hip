@@ -1,0 +1,1164 @@
+// gfx950 kernels of the TPC sector tracker.
+//
+// Stages (Rohr, LHCP 2017, Sec. 2 and Fig. 1):
+//   grid      counting sort of clusters by (unit, pad row, z bin)
+//   links     CA neighbour finding: best straight-line (down, up) pair (Fig. 1a)
+//   clean     keep reciprocal links; chains start at up-only hits (Fig. 1b)
+//   tracklets chain compaction, then a per-thread two-pass Kalman fit with
+//             track following (Fig. 1c)
+//   select    one-round claim of clusters by (hits, chi2, id) keys, acceptance,
+//             compaction of tracks, hits and the cluster assignment
+//
+// Every kernel is a grid-stride loop over work whose extent it reads from a
+// device-side run descriptor, so the same launches serve one sector, one
+// event, or a whole batch replayed from a captured graph.
+//
+// Floating point: compiled with -ffp-contract=off and correctly rounded FP32
+// division and square root; fused multiply-adds appear only where written as
+// __builtin_fmaf.  Decisions therefore reproduce, bit for bit, any other
+// IEEE-754 implementation of the same operation sequence.
+#include <hip/hip_runtime.h>
+
+#include "tpcca_internal.h"
+#include "tpcca_kernels.h"
+
+namespace tpcca {
+
+// ------------------------------------------------------------- helpers ---
+__device__ __forceinline__ int ordered_int(float f) {
+  int i = __float_as_int(f);
+  return i >= 0 ? i : (i ^ 0x7FFFFFFF);
+}
+__device__ __forceinline__ float from_ordered(int i) {
+  return __int_as_float(i >= 0 ? i : (i ^ 0x7FFFFFFF));
+}
+
+// pad row of a cluster after validation; invalid clusters go to row R
+__device__ __forceinline__ int valid_row(float4 c, int r, const float *row_x, int R) {
+  if (r >= R) return R;
+  if (!(isfinite(c.x) && isfinite(c.y) && isfinite(c.z))) return R;
+  if (!(fabsf(c.x - row_x[r]) <= 1e-3f)) return R;
+  return r;
+}
+
+__device__ __forceinline__ int zbin(const RowTab &t, float z) {
+  float v = (z - t.z0) * t.inv;
+  v = fminf(fmaxf(v, 0.0f), (float)(t.nb - 1));  // NaN -> 0
+  return (int)v;
+}
+
+// sorted-index range of the bins covering [z - lim, z + lim] (a superset
+// of the hits inside the window; the exact window test follows)
+__device__ __forceinline__ void bin_range(const RowTab &t, const int32_t *binbeg, float z,
+                                          float lim, int &b, int &e) {
+  const float pad = 1e-3f + 1e-6f * fabsf(z);
+  const int lo = zbin(t, z - lim - pad);
+  const int hi = zbin(t, z + lim + pad);
+  b = binbeg[t.bin0 + lo];
+  e = binbeg[t.bin0 + hi + 1];
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide exclusive scan of one value per thread (blockDim.x <= 1024,
+// multiple of 64).  Returns the exclusive prefix; *total gets the sum.
+template <typename T>
+__device__ T block_exclusive_scan(T v, T *lds /* >= 16 */, T *total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  T incl = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    T n = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += n;
+  }
+  if (lane == 63) lds[wid] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T run = 0;
+    for (int w = 0; w < nw; ++w) {
+      T t = lds[w];
+      lds[w] = run;
+      run += t;
+    }
+    lds[nw] = run;
+  }
+  __syncthreads();
+  T res = incl - v + lds[wid];
+  if (total) *total = lds[nw];
+  __syncthreads();
+  return res;
+}
+
+// ----------------------------------------------------------- utilities ---
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Reset of a run's per-unit tables and device counters.
+__global__ void k_run_reset(Bufs B, int run, int R) {
+  RunDev &rd = B.runs[run];
+  const int units = rd.u1 - rd.u0;
+  const int nrow = units * (R + 1);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nrow; i += gridDim.x * blockDim.x)
+    B.row_cnt[(int64_t)rd.u0 * (R + 1) + i] = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < units; i += gridDim.x * blockDim.x) {
+    B.zmm[2 * (rd.u0 + i)] = 0x7FFFFFFF;
+    B.zmm[2 * (rd.u0 + i) + 1] = (int)0x80000000;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    rd.n_trk = 0;
+    rd.n_acc = 0;
+    rd.n_acc_hits = 0;
+    rd.err = 0;
+  }
+}
+
+// ---------------------------------------------------------------- grid ---
+// Pass 1: clusters per (unit, row) and the z range of each unit.
+__global__ __launch_bounds__(kBlock) void k_count(Bufs B, int run, int R) {
+  __shared__ int hist[kMaxRows + 1];
+  __shared__ int smin[kBlock / 64], smax[kBlock / 64], serr;
+  const RunDev &rd = B.runs[run];
+  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
+    const Chunk ch = B.chunks[c];
+    const UnitDev U = B.units[ch.unit];
+    for (int r = threadIdx.x; r <= R; r += blockDim.x) hist[r] = 0;
+    if (threadIdx.x == 0) serr = 0;
+    __syncthreads();
+    int zmin = 0x7FFFFFFF, zmax = (int)0x80000000, bad = 0;
+    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
+      const int li = ch.begin + i;
+      const float4 c4 = U.cl[li];
+      const int r = valid_row(c4, U.row[li], B.row_x, R);
+      atomicAdd(&hist[r], 1);
+      if (r < R) {
+        const int oz = ordered_int(c4.z);
+        zmin = min(zmin, oz);
+        zmax = max(zmax, oz);
+      } else {
+        bad = 1;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      zmin = min(zmin, __shfl_xor(zmin, o, 64));
+      zmax = max(zmax, __shfl_xor(zmax, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      smin[threadIdx.x >> 6] = zmin;
+      smax[threadIdx.x >> 6] = zmax;
+    }
+    if (bad) serr = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < kBlock / 64; ++w) {
+        smin[0] = min(smin[0], smin[w]);
+        smax[0] = max(smax[0], smax[w]);
+      }
+      if (smin[0] != 0x7FFFFFFF) {
+        atomicMin(&B.zmm[2 * ch.unit], smin[0]);
+        atomicMax(&B.zmm[2 * ch.unit + 1], smax[0]);
+      }
+      if (serr) B.runs[run].err = 1;
+    }
+    for (int r = threadIdx.x; r <= R; r += blockDim.x)
+      if (hist[r]) atomicAdd(&B.row_cnt[(int64_t)ch.unit * (R + 1) + r], hist[r]);
+    __syncthreads();
+  }
+}
+
+// Pass 2 (one block per unit): row offsets and z-bin layout of every row.
+__global__ __launch_bounds__(kBlock) void k_plan(Bufs B, int run, int R, int hits_per_bin) {
+  __shared__ int64_t lds64[kBlock / 64 + 1];
+  __shared__ int32_t lds32[kBlock / 64 + 1];
+  const RunDev &rd = B.runs[run];
+  for (int u = rd.u0 + blockIdx.x; u < rd.u1; u += gridDim.x) {
+    const UnitDev U = B.units[u];
+    const int r = threadIdx.x;
+    const int cnt = r <= R ? B.row_cnt[(int64_t)u * (R + 1) + r] : 0;
+    int32_t tot;
+    const int32_t begin = block_exclusive_scan<int32_t>(cnt, lds32, &tot);
+    int nb = 0;
+    if (r < R) nb = max(1, min(cnt / hits_per_bin, 1 << 20));
+    else if (r == R) nb = 1;
+    const int64_t width = r <= R ? (int64_t)nb + 1 : 0;
+    int64_t wtot;
+    const int64_t boff = block_exclusive_scan<int64_t>(width, lds64, &wtot);
+    float z0 = 0.0f, z1 = 1.0f;
+    const int a = B.zmm[2 * u], b = B.zmm[2 * u + 1];
+    if (a != 0x7FFFFFFF) {
+      z0 = from_ordered(a);
+      z1 = from_ordered(b);
+    }
+    float span = z1 - z0;
+    if (!(span > 1e-3f)) span = 1e-3f;
+    if (r <= R) {
+      RowTab t;
+      t.begin = U.cl_begin + begin;
+      t.count = cnt;
+      t.nb = nb;
+      t.pad_ = 0;
+      t.bin0 = U.bin_base + boff;
+      t.z0 = z0;
+      t.inv = (float)nb / span;
+      B.rowtab[(int64_t)u * (R + 1) + r] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Pass 3: occupancy of every bin.
+__global__ __launch_bounds__(kBlock) void k_bin_count(Bufs B, int run, int R) {
+  const RunDev &rd = B.runs[run];
+  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
+    const Chunk ch = B.chunks[c];
+    const UnitDev U = B.units[ch.unit];
+    const RowTab *rt = B.rowtab + (int64_t)ch.unit * (R + 1);
+    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
+      const int li = ch.begin + i;
+      const float4 c4 = U.cl[li];
+      const int r = valid_row(c4, U.row[li], B.row_x, R);
+      const RowTab t = rt[r];
+      atomicAdd(&B.bincnt[t.bin0 + zbin(t, c4.z)], 1);
+    }
+  }
+}
+
+// Pass 4 is a device scan of the bin counts into B.binbeg (see below).
+
+// Pass 5: scatter hits into bin order (order inside a bin is arbitrary: all
+// later decisions compare cluster IDs, never positions).
+__global__ __launch_bounds__(kBlock) void k_scatter(Bufs B, int run, int R) {
+  const RunDev &rd = B.runs[run];
+  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
+    const Chunk ch = B.chunks[c];
+    const UnitDev U = B.units[ch.unit];
+    const RowTab *rt = B.rowtab + (int64_t)ch.unit * (R + 1);
+    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
+      const int li = ch.begin + i;
+      const float4 c4 = U.cl[li];
+      const int r = valid_row(c4, U.row[li], B.row_x, R);
+      const RowTab t = rt[r];
+      const int64_t g = t.bin0 + zbin(t, c4.z);
+      const int k = atomicSub(&B.bincnt[g], 1) - 1;
+      const int pos = B.binbeg[g] + k;
+      B.yz[pos] = make_float2(c4.y, c4.z);
+      B.sid[pos] = li;
+    }
+  }
+}
+
+// Row of sorted hit g from the unit's row table held in LDS.
+__device__ __forceinline__ int row_of(const RowTab *t, int R, int g) {
+  int lo = 0, hi = R;  // rows 0..R; find last row with begin <= g
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (t[mid].begin <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- links ---
+// Fig. 1a: for every hit of rows 1..R-2 the pair (u in row+1, d in row-1)
+// inside |dy|, |dz| <= W dx that minimises (chi2, id_u, id_d), where chi2 is
+// the squared deviation of the hit from the line d -> u at the hit's row.
+__global__ __launch_bounds__(kBlock) void k_links(Bufs B, ParamsDev P, int run) {
+  __shared__ RowTab srt[kMaxRows + 1];
+  const int R = P.n_rows;
+  const RunDev &rd = B.runs[run];
+  int cur = -1;
+  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
+    const Chunk ch = B.chunks[c];
+    if (ch.unit != cur) {
+      __syncthreads();
+      for (int r = threadIdx.x; r <= R; r += blockDim.x)
+        srt[r] = B.rowtab[(int64_t)ch.unit * (R + 1) + r];
+      __syncthreads();
+      cur = ch.unit;
+    }
+    const int base = B.units[ch.unit].cl_begin + ch.begin;
+    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
+      const int g = base + i;
+      const int r = row_of(srt, R, g);
+      int bu = -1, bd = -1;
+      if (r >= 1 && r <= R - 2) {
+        const float2 h = B.yz[g];
+        const float xr = B.row_x[r];
+        const float dxu = B.row_x[r + 1] - xr;
+        const float dxd = xr - B.row_x[r - 1];
+        const float w = dxd / (dxd + dxu);
+        const float luy = P.wy * dxu, luz = P.wz * dxu, ldy = P.wy * dxd, ldz = P.wz * dxd;
+        int ub, ue, db, de;
+        bin_range(srt[r + 1], B.binbeg, h.y, luz, ub, ue);
+        bin_range(srt[r - 1], B.binbeg, h.y, ldz, db, de);
+        float best = __builtin_inff();
+        for (int u = ub; u < ue; ++u) {
+          const float2 cu = B.yz[u];
+          if (!(fabsf(cu.x - h.x) <= luy && fabsf(cu.y - h.y) <= luz)) continue;
+          for (int d = db; d < de; ++d) {
+            const float2 cd = B.yz[d];
+            if (!(fabsf(cd.x - h.x) <= ldy && fabsf(cd.y - h.y) <= ldz)) continue;
+            const float ey = h.x - __builtin_fmaf(cu.x - cd.x, w, cd.x);
+            const float ez = h.y - __builtin_fmaf(cu.y - cd.y, w, cd.y);
+            const float c2 = __builtin_fmaf(ey, ey, ez * ez);
+            bool take = c2 < best;
+            if (!take && c2 == best && bu >= 0) {
+              const int iu = B.sid[u], id = B.sid[d], ibu = B.sid[bu], ibd = B.sid[bd];
+              take = iu < ibu || (iu == ibu && id < ibd);
+            }
+            if (take) {
+              best = c2;
+              bu = u;
+              bd = d;
+            }
+          }
+        }
+        if (!(best <= P.link_chi2)) {
+          bu = -1;
+          bd = -1;
+        }
+      }
+      B.up[g] = bu;
+      B.dn[g] = bd;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- clean ---
+// Fig. 1b: keep a link only if its partner links back.
+__global__ __launch_bounds__(kBlock) void k_clean(Bufs B, int run) {
+  const RunDev &rd = B.runs[run];
+  for (int g = rd.cl0 + blockIdx.x * blockDim.x + threadIdx.x; g < rd.cl1;
+       g += gridDim.x * blockDim.x) {
+    const int u = B.up[g], d = B.dn[g];
+    B.upc[g] = (u >= 0 && B.dn[u] == g) ? u : -1;
+    B.dnc[g] = (d >= 0 && B.up[d] == g) ? d : -1;
+  }
+}
+
+// Chains: a start hit has an up link and no down link; a chain of at least
+// min_chain hits marks its start in cluster-ID order (flag = sorted + 1).
+__global__ __launch_bounds__(kBlock) void k_chain(Bufs B, ParamsDev P, int run) {
+  const RunDev &rd = B.runs[run];
+  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
+    const Chunk ch = B.chunks[c];
+    const int ub = B.units[ch.unit].cl_begin;
+    const int base = ub + ch.begin;
+    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
+      const int g = base + i;
+      int f = 0;
+      if (B.upc[g] >= 0 && B.dnc[g] < 0) {
+        int n = 1, k = B.upc[g];
+        for (int s = 0; k >= 0 && s < P.n_rows; ++s) {
+          ++n;
+          k = B.upc[k];
+        }
+        if (n >= P.min_chain) f = g + 1;
+      }
+      B.flag[ub + B.sid[g]] = f;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- scans ---
+// Tile sums of a plain int32 array segment [a, b) (tiles of kScanTile).
+__global__ __launch_bounds__(kBlock) void k_scan_sums_i32(const int32_t *in, int64_t a, int64_t b,
+                                                          int64_t *sums) {
+  const int64_t ntiles = (b - a + kScanTile - 1) / kScanTile;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t s = a + t * kScanTile, e = min(b, s + kScanTile);
+    int64_t v = 0;
+    for (int64_t i = s + threadIdx.x; i < e; i += blockDim.x) v += in[i];
+    v = wave_sum(v);
+    __shared__ int64_t part[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t tot = 0;
+      for (int w = 0; w < kBlock / 64; ++w) tot += part[w];
+      sums[t] = tot;
+    }
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of n tile sums in place (one block); sums[n] = total.
+__global__ __launch_bounds__(1024) void k_scan_tiles(int64_t *sums, int64_t n) {
+  __shared__ int64_t lds[1024 / 64 + 1];
+  int64_t carry = 0;
+  for (int64_t s = 0; s < n; s += 1024) {
+    const int64_t i = s + threadIdx.x;
+    const int64_t v = i < n ? sums[i] : 0;
+    int64_t tot;
+    const int64_t ex = block_exclusive_scan<int64_t>(v, lds, &tot);
+    if (i < n) sums[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) sums[n] = carry;
+}
+
+// out[i] = add + exclusive prefix of in over [a, b) (tile offsets from sums).
+__global__ __launch_bounds__(kBlock) void k_scan_apply_i32(const int32_t *in, int32_t *out, int64_t a,
+                                                           int64_t b, const int64_t *sums,
+                                                           int64_t add) {
+  __shared__ int64_t lds[kBlock / 64 + 1];
+  const int64_t ntiles = (b - a + kScanTile - 1) / kScanTile;
+  constexpr int per = kScanTile / kBlock;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t s = a + t * kScanTile;
+    int32_t v[per];
+    int64_t loc = 0;
+    for (int k = 0; k < per; ++k) {
+      const int64_t i = s + threadIdx.x * per + k;
+      v[k] = i < b ? in[i] : 0;
+      loc += v[k];
+    }
+    int64_t tot;
+    int64_t ex = block_exclusive_scan<int64_t>(loc, lds, &tot) + sums[t] + add;
+    for (int k = 0; k < per; ++k) {
+      const int64_t i = s + threadIdx.x * per + k;
+      if (i < b) out[i] = (int32_t)ex;
+      ex += v[k];
+    }
+  }
+}
+
+// Tracklet compaction: per chunk, count flags (tile = chunk).
+__global__ __launch_bounds__(kBlock) void k_flag_sums(Bufs B, int run) {
+  __shared__ int64_t part[kBlock / 64];
+  const RunDev &rd = B.runs[run];
+  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
+    const Chunk ch = B.chunks[c];
+    const int base = B.units[ch.unit].cl_begin + ch.begin;
+    int64_t v = 0;
+    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) v += B.flag[base + i] != 0;
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t tot = 0;
+      for (int w = 0; w < kBlock / 64; ++w) tot += part[w];
+      B.scan_tmp[c - rd.c0] = tot;
+    }
+    __syncthreads();
+  }
+}
+
+// Tracklet compaction: slots in cluster-ID order (ascending start IDs).
+__global__ __launch_bounds__(kBlock) void k_flag_apply(Bufs B, int run) {
+  __shared__ int64_t lds[kBlock / 64 + 1];
+  RunDev &rd = B.runs[run];
+  constexpr int per = kChunk / kBlock;
+  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
+    const Chunk ch = B.chunks[c];
+    const int base = B.units[ch.unit].cl_begin + ch.begin;
+    int32_t f[per];
+    int64_t loc = 0;
+    for (int k = 0; k < per; ++k) {
+      const int i = threadIdx.x * per + k;
+      f[k] = i < ch.count ? B.flag[base + i] : 0;
+      loc += f[k] != 0;
+    }
+    int64_t tot;
+    int64_t ex = block_exclusive_scan<int64_t>(loc, lds, &tot) + B.scan_tmp[c - rd.c0];
+    if (ch.begin == 0 && threadIdx.x == 0) B.unit_tbegin[ch.unit] = rd.trk0 + (int32_t)ex;
+    for (int k = 0; k < per; ++k) {
+      if (f[k]) {
+        const int t = rd.trk0 + (int32_t)ex;
+        B.trk_start[t] = f[k] - 1;
+        B.trk_unit[t] = ch.unit;
+        ++ex;
+      }
+    }
+    if (c == rd.c1 - 1 && threadIdx.x == 0) rd.n_trk = (int32_t)B.scan_tmp[rd.c1 - rd.c0];
+  }
+}
+
+// Units without clusters have no chunk: their first tracklet is the one of
+// the next non-empty unit of the run (or the run's end).
+__global__ void k_empty_units(Bufs B, int run) {
+  const RunDev &rd = B.runs[run];
+  for (int u = rd.u0 + blockIdx.x * blockDim.x + threadIdx.x; u < rd.u1;
+       u += gridDim.x * blockDim.x) {
+    if (B.units[u].n != 0) continue;
+    int t = rd.trk0 + rd.n_trk;
+    for (int v = u + 1; v < rd.u1; ++v)
+      if (B.units[v].n != 0) {
+        t = B.unit_tbegin[v];
+        break;
+      }
+    B.unit_tbegin[u] = t;
+  }
+}
+
+// ------------------------------------------------------------ tracklets ---
+// Track state at plane x: p = (y, z, sin phi, tan lambda, q/pT), C lower
+// triangle (00,10,11,20,21,22,30,31,32,33,40,41,42,43,44).
+struct KState {
+  float p[5];
+  float C[15];
+  float x;
+};
+
+// Propagation x -> x1 with Bz only (Sec. 2).  sin(phi) is linear in x
+// along a circle of curvature kB q/pT; dy = dx (s0 + s1) / (c0 + c1); the
+// arc length (signed like dx) is the chord times the Maclaurin series of
+// asin(u)/u to u^8, u = chord |k| / 2.  The Jacobian is the simplified one
+// that drops the curvature term of the arc length.  C <- F C F^T.
+__device__ __forceinline__ bool kf_propagate(const ParamsDev &P, KState &s, float x1) {
+  const float dx = x1 - s.x;
+  const float kk = P.kB * s.p[4];
+  const float s0 = s.p[2];
+  const float s1 = __builtin_fmaf(kk, dx, s0);
+  if (!(fabsf(s1) <= P.max_sin)) return false;
+  const float c0 = sqrtf(__builtin_fmaf(-s0, s0, 1.0f));
+  const float c1 = sqrtf(__builtin_fmaf(-s1, s1, 1.0f));
+  const float cc = c0 + c1;
+  const float tt = (s0 + s1) / cc;
+  const float dy = dx * tt;
+  const float ch2 = __builtin_fmaf(dy, dy, dx * dx);
+  const float ch = sqrtf(ch2);
+  const float chs = dx < 0.0f ? -ch : ch;
+  const float u2 = ch2 * kk * kk * 0.25f;
+  float h = (float)(35.0 / 1152.0);
+  h = __builtin_fmaf(u2, h, (float)(5.0 / 112.0));
+  h = __builtin_fmaf(u2, h, (float)(3.0 / 40.0));
+  h = __builtin_fmaf(u2, h, (float)(1.0 / 6.0));
+  h = __builtin_fmaf(u2, h, 1.0f);
+  const float dS = chs * h;
+  const float t = s.p[3];
+
+  const float a = dx * (2.0f + tt * (s0 / c0 + s1 / c1)) / cc;
+  const float b = dx * P.kB * dx * (1.0f + tt * s1 / c1) / cc;
+  const float g = ch > 0.0f ? t * (dy / chs) : 0.0f;
+  const float cz = g * a;
+  const float dzq = g * b;
+  const float e = dS;
+  const float f = P.kB * dx;
+
+  s.p[0] = s.p[0] + dy;
+  s.p[1] = s.p[1] + t * dS;
+  s.p[2] = s1;
+  s.x = x1;
+
+  float *C = s.C;
+  const float c00 = C[0], c10 = C[1], c11 = C[2], c20 = C[3], c21 = C[4], c22 = C[5];
+  const float c30 = C[6], c31 = C[7], c32 = C[8], c33 = C[9];
+  const float c40 = C[10], c41 = C[11], c42 = C[12], c43 = C[13], c44 = C[14];
+  const float fc00 = c00 + a * c20 + b * c40;
+  const float fc02 = c20 + a * c22 + b * c42;
+  const float fc04 = c40 + a * c42 + b * c44;
+  const float fc10 = c10 + cz * c20 + e * c30 + dzq * c40;
+  const float fc11 = c11 + cz * c21 + e * c31 + dzq * c41;
+  const float fc12 = c21 + cz * c22 + e * c32 + dzq * c42;
+  const float fc13 = c31 + cz * c32 + e * c33 + dzq * c43;
+  const float fc14 = c41 + cz * c42 + e * c43 + dzq * c44;
+  const float fc20 = c20 + f * c40;
+  const float fc21 = c21 + f * c41;
+  const float fc22 = c22 + f * c42;
+  const float fc23 = c32 + f * c43;
+  const float fc24 = c42 + f * c44;
+  C[0] = fc00 + a * fc02 + b * fc04;
+  C[1] = fc10 + a * fc12 + b * fc14;
+  C[2] = fc11 + cz * fc12 + e * fc13 + dzq * fc14;
+  C[3] = fc20 + a * fc22 + b * fc24;
+  C[4] = fc21 + cz * fc22 + e * fc23 + dzq * fc24;
+  C[5] = fc22 + f * fc24;
+  C[6] = c30 + a * c32 + b * c43;
+  C[7] = c31 + cz * c32 + e * c33 + dzq * c43;
+  C[8] = c32 + f * c43;
+  C[9] = c33;
+  C[10] = c40 + a * c42 + b * c44;
+  C[11] = c41 + cz * c42 + e * c43 + dzq * c44;
+  C[12] = c42 + f * c44;
+  C[13] = c43;
+  C[14] = c44;
+  return true;
+}
+
+// chi2 of a 2-D measurement against the state (S = C_yz + R).
+__device__ __forceinline__ bool kf_chi2(const ParamsDev &P, const KState &s, float ym, float zm,
+                                        float &chi2) {
+  const float r0 = ym - s.p[0];
+  const float r1 = zm - s.p[1];
+  const float s00 = s.C[0] + P.ery;
+  const float s10 = s.C[1];
+  const float s11 = s.C[2] + P.erz;
+  const float det = s00 * s11 - s10 * s10;
+  if (!(det > 0.0f)) return false;
+  const float inv = 1.0f / det;
+  const float i00 = s11 * inv, i10 = -s10 * inv, i11 = s00 * inv;
+  const float v0 = i00 * r0 + i10 * r1;
+  const float v1 = i10 * r0 + i11 * r1;
+  chi2 = r0 * v0 + r1 * v1;
+  return true;
+}
+
+// Kalman update with (ym, zm): K = C H^T S^-1, p += K r, C -= K H C.
+__device__ __forceinline__ bool kf_update(const ParamsDev &P, KState &s, float ym, float zm,
+                                          float &chi2) {
+  const float r0 = ym - s.p[0];
+  const float r1 = zm - s.p[1];
+  const float s00 = s.C[0] + P.ery;
+  const float s10 = s.C[1];
+  const float s11 = s.C[2] + P.erz;
+  const float det = s00 * s11 - s10 * s10;
+  if (!(det > 0.0f)) return false;
+  const float inv = 1.0f / det;
+  const float i00 = s11 * inv, i10 = -s10 * inv, i11 = s00 * inv;
+  const float v0 = i00 * r0 + i10 * r1;
+  const float v1 = i10 * r0 + i11 * r1;
+  chi2 = r0 * v0 + r1 * v1;
+  // first two columns of C (old values), row k = (C_k0, C_k1)
+  const float cj0[5] = {s.C[0], s.C[1], s.C[3], s.C[6], s.C[10]};
+  const float cj1[5] = {s.C[1], s.C[2], s.C[4], s.C[7], s.C[11]};
+  float k0[5], k1[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    k0[k] = cj0[k] * i00 + cj1[k] * i10;
+    k1[k] = cj0[k] * i10 + cj1[k] * i11;
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) s.p[k] = s.p[k] + k0[k] * r0 + k1[k] * r1;
+  int idx = 0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      s.C[idx] = s.C[idx] - (k0[i] * cj0[j] + k1[i] * cj1[j]);
+      ++idx;
+    }
+  return true;
+}
+
+// Nearest hit (dy^2 + dz^2, ties to the lower ID) inside the prediction
+// window of row r; -1 if none.
+__device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, const RowTab *rt,
+                                         const KState &s, int r) {
+  float wy = P.nsig * sqrtf(s.C[0] + P.ery);
+  float wz = P.nsig * sqrtf(s.C[2] + P.erz);
+  if (wy > P.wmax) wy = P.wmax;
+  if (wz > P.wmax) wz = P.wmax;
+  const RowTab t = rt[r];
+  int b, e;
+  bin_range(t, B.binbeg, s.p[1], wz, b, e);
+  int best = -1, bid = 0;
+  float bd2 = __builtin_inff();
+  for (int i = b; i < e; ++i) {
+    const float2 c = B.yz[i];
+    if (!(fabsf(c.x - s.p[0]) <= wy && fabsf(c.y - s.p[1]) <= wz)) continue;
+    const float dy = c.x - s.p[0];
+    const float dz = c.y - s.p[1];
+    const float d2 = __builtin_fmaf(dy, dy, dz * dz);
+    if (d2 < bd2) {
+      bd2 = d2;
+      best = i;
+      bid = B.sid[i];
+    } else if (d2 == bd2) {
+      const int id = B.sid[i];
+      if (id < bid) {
+        best = i;
+        bid = id;
+      }
+    }
+  }
+  return best;
+}
+
+// Track following with the Kalman filter (Fig. 1c), one tracklet per thread:
+// seed on the chain's first hit with the direction of its end points; pass 1
+// updates with the chain and follows outward picking the nearest window hit
+// with chi2 <= pick_chi2 (stop after max_miss empty rows); pass 2 restarts at
+// the outermost hit with the pass-1 covariance x refit_inflate, refits inward
+// through all pass-1 hits and continues below the chain start.
+__global__ __launch_bounds__(kKfBlock) void k_kf(Bufs B, ParamsDev P, int run) {
+  const RunDev &rd = B.runs[run];
+  const int R = P.n_rows;
+  const int n_trk = rd.n_trk;
+  for (int tl = blockIdx.x * blockDim.x + threadIdx.x; tl < n_trk; tl += gridDim.x * blockDim.x) {
+    const int t = rd.trk0 + tl;
+    const int g0 = B.trk_start[t];
+    const int u = B.trk_unit[t];
+    const RowTab *rt = B.rowtab + (int64_t)u * (R + 1);
+    int32_t *hl = B.trk_hits + (int64_t)t * R;
+    tpcca_tracklet_t o;
+    for (int k = 0; k < 15; ++k) {
+      o.cov[k] = 0.0f;
+      o.cov_out[k] = 0.0f;
+    }
+    for (int k = 0; k < 5; ++k) {
+      o.p[k] = 0.0f;
+      o.p_out[k] = 0.0f;
+    }
+    o.start_id = B.sid[g0];
+    o.status = 2;
+    o.n_hits = 0;
+    o.n_pass1 = 0;
+    o.ndf = 0;
+    o.row_ref = 0;
+    o.row_out = 0;
+    o.x_ref = 0.0f;
+    o.x_out = 0.0f;
+    o.chi2 = 0.0f;
+    // chain
+    int n1 = 0;
+    for (int k = g0; k >= 0 && n1 < R; k = B.upc[k]) hl[n1++] = k;
+    o.n_chain = n1;
+    const int r0 = row_of(rt, R, g0);
+    const int gL = hl[n1 - 1];
+    const int rL = r0 + n1 - 1;
+    KState st;
+    {
+      const float2 h0 = B.yz[g0], hL = B.yz[gL];
+      const float x0 = B.row_x[r0], xL = B.row_x[rL];
+      const float dxs = xL - x0;
+      const float ty = (hL.x - h0.x) / dxs;
+      const float sn = ty / sqrtf(__builtin_fmaf(ty, ty, 1.0f));
+      const float tz = (hL.y - h0.y) / dxs;
+      const float tl2 = tz * sqrtf(__builtin_fmaf(-sn, sn, 1.0f));
+      st.p[0] = h0.x;
+      st.p[1] = h0.y;
+      st.p[2] = sn;
+      st.p[3] = tl2;
+      st.p[4] = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 15; ++k) st.C[k] = 0.0f;
+      st.C[0] = P.ery;
+      st.C[2] = P.erz;
+      st.C[5] = P.c22;
+      st.C[9] = P.c33;
+      st.C[14] = P.c44;
+      st.x = x0;
+    }
+    bool ok = true;
+    float c2;
+    for (int k = 1; k < n1 && ok; ++k) {
+      const float2 h = B.yz[hl[k]];
+      ok = kf_propagate(P, st, B.row_x[r0 + k]) && kf_update(P, st, h.x, h.y, c2);
+    }
+    if (ok) {
+      KState saved = st;
+      int row_out = rL;
+      int miss = 0;
+      for (int r = rL + 1; r < R; ++r) {
+        if (!kf_propagate(P, st, B.row_x[r])) break;
+        const int h = kf_search(B, P, rt, st, r);
+        bool took = false;
+        if (h >= 0) {
+          const float2 c = B.yz[h];
+          float cc2;
+          if (kf_chi2(P, st, c.x, c.y, cc2) && cc2 <= P.pick_chi2 &&
+              kf_update(P, st, c.x, c.y, c2)) {
+            hl[n1++] = h;
+            saved = st;
+            row_out = r;
+            took = true;
+          }
+        }
+        if (took) {
+          miss = 0;
+        } else if (++miss >= P.max_miss) {
+          break;
+        }
+      }
+      // pass 2
+      st = saved;
+      if (P.inflate > 0.0f) {
+#pragma unroll
+        for (int k = 0; k < 15; ++k) st.C[k] = st.C[k] * P.inflate;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 15; ++k) st.C[k] = 0.0f;
+        st.C[0] = P.r00;
+        st.C[2] = P.r11;
+        st.C[5] = P.c22;
+        st.C[9] = P.c33;
+        st.C[14] = P.c44;
+      }
+      float chi2 = 0.0f;
+      // pass-1 hits sit in rows: chain rows r0.., then rows recorded in hl
+      int hr_prev = -1;
+      for (int k = n1 - 1; k >= 0 && ok; --k) {
+        const int gh = hl[k];
+        const int hr = k < o.n_chain ? r0 + k : row_of(rt, R, gh);
+        if (k < n1 - 1) ok = kf_propagate(P, st, B.row_x[hr]);
+        const float2 h = B.yz[gh];
+        ok = ok && kf_update(P, st, h.x, h.y, c2);
+        if (ok) chi2 = chi2 + c2;
+        hr_prev = hr;
+      }
+      (void)hr_prev;
+      if (ok) {
+        KState out = st;
+        int ne = 0;
+        int miss2 = 0;
+        int row_ref = r0;
+        for (int r = r0 - 1; r >= 0; --r) {
+          if (!kf_propagate(P, st, B.row_x[r])) break;
+          const int h = kf_search(B, P, rt, st, r);
+          bool took = false;
+          if (h >= 0) {
+            const float2 c = B.yz[h];
+            float cc2;
+            if (kf_chi2(P, st, c.x, c.y, cc2) && cc2 <= P.pick_chi2 &&
+                kf_update(P, st, c.x, c.y, c2)) {
+              chi2 = chi2 + c2;
+              hl[n1 + ne] = h;
+              ++ne;
+              out = st;
+              row_ref = r;
+              took = true;
+            }
+          }
+          if (took) {
+            miss2 = 0;
+          } else if (++miss2 >= P.max_miss) {
+            break;
+          }
+        }
+        o.n_hits = n1 + ne;
+        o.n_pass1 = n1;
+        o.ndf = 2 * o.n_hits - 5;
+        o.row_ref = row_ref;
+        o.row_out = row_out;
+        o.x_ref = out.x;
+        o.x_out = saved.x;
+        o.chi2 = chi2;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          o.p[k] = out.p[k];
+          o.p_out[k] = saved.p[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 15; ++k) {
+          o.cov[k] = out.C[k];
+          o.cov_out[k] = saved.C[k];
+        }
+        o.status = o.n_hits < P.min_hits ? 1 : 0;
+      }
+    }
+    B.trk[t] = o;
+  }
+}
+
+// ------------------------------------------------------------ selection ---
+// Claim key: more hits, then smaller chi2 (FP32 bits of a non-negative
+// float order like its value), then smaller start ID.
+__device__ __forceinline__ unsigned long long select_key(const tpcca_tracklet_t &o) {
+  const float c = o.chi2 > 0.0f ? o.chi2 : 0.0f;
+  const unsigned int bits = __float_as_uint(c);
+  return ((unsigned long long)(unsigned int)o.n_hits << 56) |
+         ((unsigned long long)(0xFFFFFFFFu - bits) << 24) |
+         (unsigned long long)(0xFFFFFFu - (unsigned int)o.start_id);
+}
+
+__global__ __launch_bounds__(kBlock) void k_claim(Bufs B, ParamsDev P, int run) {
+  const RunDev &rd = B.runs[run];
+  const int R = P.n_rows;
+  for (int tl = blockIdx.x * blockDim.x + threadIdx.x; tl < rd.n_trk; tl += gridDim.x * blockDim.x) {
+    const int t = rd.trk0 + tl;
+    const tpcca_tracklet_t &o = B.trk[t];
+    if (o.status != 0) continue;
+    const unsigned long long key = select_key(o);
+    const int32_t *hl = B.trk_hits + (int64_t)t * R;
+    for (int k = 0; k < o.n_hits; ++k) atomicMax(&B.owner[hl[k]], key);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
+  const RunDev &rd = B.runs[run];
+  const int R = P.n_rows;
+  for (int tl = blockIdx.x * blockDim.x + threadIdx.x; tl < rd.n_trk; tl += gridDim.x * blockDim.x) {
+    const int t = rd.trk0 + tl;
+    const tpcca_tracklet_t &o = B.trk[t];
+    unsigned long long v = 0;
+    if (o.status == 0) {
+      const unsigned long long key = select_key(o);
+      const int32_t *hl = B.trk_hits + (int64_t)t * R;
+      int won = 0;
+      for (int k = 0; k < o.n_hits; ++k) won += B.owner[hl[k]] == key;
+      if (won >= P.min_hits && won * 100 >= P.own_pct * o.n_hits)
+        v = (1ull << 40) | (unsigned long long)won;
+    }
+    B.accv[tl] = v;
+  }
+}
+
+// Scan of accv over the run's tracklets (count read on the device).
+__global__ __launch_bounds__(kBlock) void k_acc_sums(Bufs B, int run) {
+  __shared__ unsigned long long part[kBlock / 64];
+  const RunDev &rd = B.runs[run];
+  const int64_t n = rd.n_trk;
+  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    unsigned long long v = 0;
+    for (int64_t i = t * kScanTile + threadIdx.x; i < min(n, (t + 1) * kScanTile); i += blockDim.x)
+      v += B.accv[i];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long tot = 0;
+      for (int w = 0; w < kBlock / 64; ++w) tot += part[w];
+      B.scan_tmp[t] = (int64_t)tot;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_acc_tiles(Bufs B, int run) {
+  __shared__ int64_t lds[1024 / 64 + 1];
+  RunDev &rd = B.runs[run];
+  const int64_t n = (rd.n_trk + kScanTile - 1) / kScanTile;
+  int64_t carry = 0;
+  for (int64_t s = 0; s < n; s += 1024) {
+    const int64_t i = s + threadIdx.x;
+    const int64_t v = i < n ? B.scan_tmp[i] : 0;
+    int64_t tot;
+    const int64_t ex = block_exclusive_scan<int64_t>(v, lds, &tot);
+    if (i < n) B.scan_tmp[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    B.scan_tmp[n] = carry;
+    rd.n_acc = (int32_t)((unsigned long long)carry >> 40);
+    rd.n_acc_hits = (int64_t)((unsigned long long)carry & ((1ull << 40) - 1));
+    B.accx[rd.n_trk] = (unsigned long long)carry;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_acc_apply(Bufs B, int run) {
+  __shared__ int64_t lds[kBlock / 64 + 1];
+  const RunDev &rd = B.runs[run];
+  const int64_t n = rd.n_trk;
+  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  constexpr int per = kScanTile / kBlock;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t s = t * kScanTile;
+    unsigned long long v[per];
+    int64_t loc = 0;
+    for (int k = 0; k < per; ++k) {
+      const int64_t i = s + threadIdx.x * per + k;
+      v[k] = i < n ? B.accv[i] : 0;
+      loc += (int64_t)v[k];
+    }
+    int64_t tot;
+    int64_t ex = block_exclusive_scan<int64_t>(loc, lds, &tot) + B.scan_tmp[t];
+    for (int k = 0; k < per; ++k) {
+      const int64_t i = s + threadIdx.x * per + k;
+      if (i < n) B.accx[i] = (unsigned long long)ex;
+      ex += (int64_t)v[k];
+    }
+  }
+}
+
+__device__ __forceinline__ int acc_count(unsigned long long v) { return (int)(v >> 40); }
+__device__ __forceinline__ int64_t acc_hits(unsigned long long v) {
+  return (int64_t)(v & ((1ull << 40) - 1));
+}
+
+// Per-unit result table (after the accepted-track scan).
+__global__ void k_unit_results(Bufs B, int run) {
+  const RunDev &rd = B.runs[run];
+  for (int u = rd.u0 + blockIdx.x * blockDim.x + threadIdx.x; u < rd.u1;
+       u += gridDim.x * blockDim.x) {
+    const UnitDev U = B.units[u];
+    const int tb = B.unit_tbegin[u] - rd.trk0;
+    const int te = (u + 1 < rd.u1) ? B.unit_tbegin[u + 1] - rd.trk0 : rd.n_trk;
+    const unsigned long long a = B.accx[tb], b = B.accx[te];
+    tpcca_unit_result_t r;
+    r.slot = U.slot;
+    r.sector = U.sector;
+    r.n_clusters = U.n;
+    r.n_tracklets = te - tb;
+    r.n_tracks = acc_count(b) - acc_count(a);
+    r.n_track_hits = (int32_t)(acc_hits(b) - acc_hits(a));
+    r.cluster_begin = U.cl_begin;
+    r.track_begin = rd.trk0 + acc_count(a);
+    r.hit_begin = rd.cl0 + acc_hits(a);
+    B.unit_res[u] = r;
+  }
+}
+
+// Compaction of accepted tracks: parameters, won hits in ascending rows
+// (inward hits were stored after the pass-1 hits in descending rows), and
+// the per-cluster assignment (unit-local track index).
+__global__ __launch_bounds__(kBlock) void k_output(Bufs B, ParamsDev P, int run) {
+  const RunDev &rd = B.runs[run];
+  const int R = P.n_rows;
+  for (int tl = blockIdx.x * blockDim.x + threadIdx.x; tl < rd.n_trk; tl += gridDim.x * blockDim.x) {
+    if (B.accv[tl] == 0) continue;
+    const int t = rd.trk0 + tl;
+    const tpcca_tracklet_t &o = B.trk[t];
+    const int u = B.trk_unit[t];
+    const UnitDev U = B.units[u];
+    const tpcca_unit_result_t ur = B.unit_res[u];
+    const unsigned long long ex = B.accx[tl];
+    const int k = rd.trk0 + acc_count(ex);
+    const int64_t h0 = rd.cl0 + acc_hits(ex);
+    const unsigned long long key = select_key(o);
+    const int32_t *hl = B.trk_hits + (int64_t)t * R;
+    const int n1 = o.n_pass1, ne = o.n_hits - o.n_pass1;
+    const int local_track = k - (int)ur.track_begin;
+    int w = 0;
+    for (int j = 0; j < o.n_hits; ++j) {
+      const int gh = j < ne ? hl[n1 + ne - 1 - j] : hl[j - ne];
+      if (B.owner[gh] != key) continue;
+      const int id = B.sid[gh];
+      B.hits_out[h0 + w] = id;
+      B.assign[U.cl_begin + id] = local_track;
+      ++w;
+    }
+    tpcca_track_t tr;
+    tr.x_ref = o.x_ref;
+    for (int q = 0; q < 5; ++q) tr.p[q] = o.p[q];
+    for (int q = 0; q < 15; ++q) tr.cov[q] = o.cov[q];
+    tr.chi2 = o.chi2;
+    tr.ndf = o.ndf;
+    tr.n_hits = w;
+    tr.hit_offset = (int32_t)(h0 - ur.hit_begin);
+    tr.sector = U.sector;
+    tr.start_id = o.start_id;
+    B.tracks[k] = tr;
+  }
+}
+
+// Sorted indices -> unit-local cluster IDs (for the parity getters).
+__global__ void k_to_ids(const int32_t *sid, const int32_t *in, int32_t *out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = in[i];
+    out[i] = v >= 0 ? sid[v] : -1;
+  }
+}
+
+// Links of one unit in cluster-ID space.
+__global__ void k_links_by_id(const int32_t *sid, const int32_t *up, const int32_t *dn, int32_t *out_up,
+                              int32_t *out_dn, int32_t cl_begin, int32_t n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int g = cl_begin + i;
+    const int id = sid[g];
+    const int a = up[g], b = dn[g];
+    out_up[id] = a >= 0 ? sid[a] : -1;
+    out_dn[id] = b >= 0 ? sid[b] : -1;
+  }
+}
+
+
+// ============================================================ launchers ===
+static inline int grid_for(int64_t work, int per_block, int cap) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_fill_i32<<<grid_for(n, 256 * 8, 4096), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_fill_u64<<<grid_for(n, 256 * 8, 4096), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
+                       hipStream_t s) {
+  const int R = P.n_rows;
+  const int nch = h.c1 - h.c0, nu = h.u1 - h.u0;
+  k_run_reset<<<grid_for((int64_t)nu * (R + 1), 256, 1024), 256, 0, s>>>(B, run, R);
+  hipError_t e = launch_fill_i32(B.bincnt + h.bin0, h.bin1 - h.bin0, 0, s);
+  if (e != hipSuccess) return e;
+  if (nch > 0) k_count<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run, R);
+  if (nu > 0) k_plan<<<grid_for(nu, 1, 4096), kBlock, 0, s>>>(B, run, R, P.hits_per_bin);
+  if (nch > 0) k_bin_count<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run, R);
+  const int64_t nb = h.bin1 - h.bin0;
+  const int64_t tiles = (nb + kScanTile - 1) / kScanTile;
+  if (nb > 0) {
+    k_scan_sums_i32<<<grid_for(tiles, 1, 8192), kBlock, 0, s>>>(B.bincnt, h.bin0, h.bin1, B.scan_tmp);
+    k_scan_tiles<<<1, 1024, 0, s>>>(B.scan_tmp, tiles);
+    k_scan_apply_i32<<<grid_for(tiles, 1, 8192), kBlock, 0, s>>>(B.bincnt, B.binbeg, h.bin0, h.bin1,
+                                                                  B.scan_tmp, h.cl0);
+  }
+  if (nch > 0) k_scatter<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_links(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
+                        hipStream_t s) {
+  const int nch = h.c1 - h.c0;
+  if (nch > 0) k_links<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, P, run);
+  return hipGetLastError();
+}
+
+hipError_t launch_clean(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
+                        hipStream_t s) {
+  (void)P;
+  const int64_t n = h.cl1 - h.cl0;
+  if (n > 0) k_clean<<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(B, run);
+  return hipGetLastError();
+}
+
+hipError_t launch_tracklets(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
+                            hipStream_t s) {
+  const int nch = h.c1 - h.c0, nu = h.u1 - h.u0;
+  if (nch > 0) {
+    k_chain<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, P, run);
+    k_flag_sums<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
+    k_scan_tiles<<<1, 1024, 0, s>>>(B.scan_tmp, nch);
+    k_flag_apply<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
+  }
+  if (nu > 0) k_empty_units<<<grid_for(nu, 64, 1024), 64, 0, s>>>(B, run);
+  if (h.trk_cap > 0) k_kf<<<grid_for(h.trk_cap, kKfBlock, 4096), kKfBlock, 0, s>>>(B, P, run);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
+                         hipStream_t s) {
+  const int64_t n = h.cl1 - h.cl0;
+  hipError_t e = launch_fill_u64(B.owner + h.cl0, n, 0ull, s);
+  if (e != hipSuccess) return e;
+  e = launch_fill_i32(B.assign + h.cl0, n, -1, s);
+  if (e != hipSuccess) return e;
+  const int nu = h.u1 - h.u0;
+  const int tg = grid_for(h.trk_cap, kBlock, 4096);
+  const int64_t tiles = (h.trk_cap + kScanTile - 1) / kScanTile;
+  if (h.trk_cap > 0) {
+    k_claim<<<tg, kBlock, 0, s>>>(B, P, run);
+    k_won<<<tg, kBlock, 0, s>>>(B, P, run);
+    k_acc_sums<<<grid_for(tiles, 1, 8192), kBlock, 0, s>>>(B, run);
+  }
+  k_acc_tiles<<<1, 1024, 0, s>>>(B, run);
+  if (h.trk_cap > 0) k_acc_apply<<<grid_for(tiles, 1, 8192), kBlock, 0, s>>>(B, run);
+  if (nu > 0) k_unit_results<<<grid_for(nu, 64, 1024), 64, 0, s>>>(B, run);
+  if (h.trk_cap > 0) k_output<<<tg, kBlock, 0, s>>>(B, P, run);
+  return hipGetLastError();
+}
+
+hipError_t launch_links_by_id(const Bufs &B, const int32_t *up, const int32_t *dn, int32_t *out_up,
+                              int32_t *out_dn, int32_t cl_begin, int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_links_by_id<<<grid_for(n, 256, 4096), 256, 0, s>>>(B.sid, up, dn, out_up, out_dn, cl_begin, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_ids(const Bufs &B, const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_to_ids<<<grid_for(n, 256, 4096), 256, 0, s>>>(B.sid, in, out, n);
+  return hipGetLastError();
+}
+
+}  // namespace tpcca

@@ -1,0 +1,962 @@
+// Host runtime of the gfx950 sector tracker: contexts, device arenas, the
+// stage calls of the C ABI and the batched (graph-replayed) path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "tpcca.h"
+#include "tpcca_internal.h"
+#include "tpcca_kernels.h"
+#include "tpcca_runtime.h"
+
+using namespace tpcca;
+
+namespace {
+
+enum UnitState { kLoaded = 1, kLinked = 2, kCleaned = 3, kTracklets = 4, kSelected = 5 };
+
+struct UnitHost {
+  int32_t slot, sector, n;
+  int32_t state;
+  int32_t run;
+};
+
+int64_t bins_cap_of(int64_t n, int hpb, int R) { return n / hpb + 2 * (int64_t)(R + 1) + 1; }
+int64_t trk_cap_of(int64_t n, int min_chain) { return n / std::max(1, min_chain) + 1; }
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct tpcca_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0, allocated = 0;
+  tpcca_params_t params;
+  ParamsDev P;
+  int R = 0;
+  int n_sectors = 36;
+  std::vector<float> row_x;
+
+  std::vector<UnitDev> units;
+  std::vector<UnitHost> uh;
+  std::vector<Chunk> chunks;
+  std::vector<int32_t> unit_chunk0;  // first chunk of each unit
+  std::vector<RunHost> runs;
+  std::map<std::pair<int, int>, int> index;
+  int64_t n_total = 0, bins_total = 0, trk_total = 0, in_used = 0;
+  bool tables_dirty = true;
+  std::vector<int> pending_runs;  // runs launched since the last sync
+
+  // device buffers
+  DevBuf row_x_d, units_d, chunks_d, runs_d, rowtab, row_cnt, zmm, bincnt, binbeg, yz, sid, up,
+      dn, upc, dnc, flag, trk_start, trk_unit, unit_tbegin, trk, trk_hits, owner, accv, accx,
+      tracks, hits_out, assign, unit_res, scan_tmp, in_cl, in_row;
+  Bufs B{};
+
+  // graph replay of the batch path
+  hipGraphExec_t gexec = nullptr;
+  RunHost gcap{};
+  int generation = 0;
+  int gen_captured = -1;
+
+  bool timing = false;
+  hipEvent_t ev[6] = {};
+  float stage_ms[5] = {};
+  bool have_times = false;
+
+  std::string last_error;
+};
+
+// --------------------------------------------------------------- errors ---
+static int dev_err(tpcca_ctx *c, hipError_t e, const char *what) {
+  if (c) {
+    c->last_error = std::string(what) + ": " + hipGetErrorString(e);
+  }
+  return TPCCA_EDEVICE;
+}
+#define HIPCHK(ctx, call)                                   \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return dev_err((ctx), e_, #call); \
+  } while (0)
+
+// Grow a device buffer to at least `bytes` (x1.25 headroom), preserving the
+// first `keep` bytes.  Budget-checked.
+static int ensure(tpcca_ctx *c, DevBuf &b, size_t bytes, size_t keep) {
+  if (bytes <= b.bytes) return TPCCA_OK;
+  size_t nb = std::max(bytes, b.bytes + b.bytes / 4);
+  nb = (nb + 255) & ~(size_t)255;
+  if (c->allocated - b.bytes + nb > c->budget) {
+    nb = bytes;
+    if (c->allocated - b.bytes + nb > c->budget) {
+      c->last_error = "device budget exceeded";
+      return TPCCA_ENOMEM;
+    }
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, nb);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    c->last_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+    return TPCCA_ENOMEM;
+  }
+  if (b.p && keep) {
+    e = hipMemcpyAsync(p, b.p, std::min(keep, b.bytes), hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return dev_err(c, e, "hipMemcpyAsync(grow)");
+  }
+  if (b.p) {
+    hipStreamSynchronize(c->stream);
+    hipFree(b.p);
+  }
+  c->allocated = c->allocated - b.bytes + nb;
+  b.p = p;
+  b.bytes = nb;
+  c->generation++;
+  return TPCCA_OK;
+}
+
+template <typename T>
+static T *ptr(DevBuf &b) {
+  return static_cast<T *>(b.p);
+}
+
+static void refresh_bufs(tpcca_ctx *c) {
+  Bufs &B = c->B;
+  B.row_x = ptr<float>(c->row_x_d);
+  B.units = ptr<UnitDev>(c->units_d);
+  B.chunks = ptr<Chunk>(c->chunks_d);
+  B.runs = ptr<RunDev>(c->runs_d);
+  B.rowtab = ptr<RowTab>(c->rowtab);
+  B.row_cnt = ptr<int32_t>(c->row_cnt);
+  B.zmm = ptr<int32_t>(c->zmm);
+  B.bincnt = ptr<int32_t>(c->bincnt);
+  B.binbeg = ptr<int32_t>(c->binbeg);
+  B.yz = ptr<float2>(c->yz);
+  B.sid = ptr<int32_t>(c->sid);
+  B.up = ptr<int32_t>(c->up);
+  B.dn = ptr<int32_t>(c->dn);
+  B.upc = ptr<int32_t>(c->upc);
+  B.dnc = ptr<int32_t>(c->dnc);
+  B.flag = ptr<int32_t>(c->flag);
+  B.trk_start = ptr<int32_t>(c->trk_start);
+  B.trk_unit = ptr<int32_t>(c->trk_unit);
+  B.unit_tbegin = ptr<int32_t>(c->unit_tbegin);
+  B.trk = ptr<tpcca_tracklet_t>(c->trk);
+  B.trk_hits = ptr<int32_t>(c->trk_hits);
+  B.owner = ptr<unsigned long long>(c->owner);
+  B.accv = ptr<unsigned long long>(c->accv);
+  B.accx = ptr<unsigned long long>(c->accx);
+  B.tracks = ptr<tpcca_track_t>(c->tracks);
+  B.hits_out = ptr<int32_t>(c->hits_out);
+  B.assign = ptr<int32_t>(c->assign);
+  B.unit_res = ptr<tpcca_unit_result_t>(c->unit_res);
+  B.scan_tmp = ptr<int64_t>(c->scan_tmp);
+  B.ids_tmp = nullptr;
+}
+
+// Size every work buffer for the loaded units plus `extra` capacity.
+static int ensure_work(tpcca_ctx *c, int64_t n_cl, int64_t n_units, int64_t n_bins, int64_t n_trk,
+                       int64_t n_chunks) {
+  const int R = c->R;
+  const size_t N = (size_t)std::max<int64_t>(n_cl, 1), U = (size_t)std::max<int64_t>(n_units, 1);
+  const size_t NB = (size_t)std::max<int64_t>(n_bins, 1), T = (size_t)std::max<int64_t>(n_trk, 1);
+  const size_t NC = (size_t)std::max<int64_t>(n_chunks, 1);
+  const size_t keepN = (size_t)c->n_total, keepU = c->units.size(), keepB = (size_t)c->bins_total,
+               keepT = (size_t)c->trk_total;
+  int rc;
+#define ENS(buf, count, elem, keepc)                                               \
+  if ((rc = ensure(c, c->buf, (count) * (elem), (keepc) * (elem))) != TPCCA_OK) \
+    return rc;
+  ENS(units_d, U, sizeof(UnitDev), 0);
+  ENS(chunks_d, NC, sizeof(Chunk), 0);
+  ENS(runs_d, U + 1, sizeof(RunDev), c->runs.size());
+  ENS(rowtab, U * (R + 1), sizeof(RowTab), keepU * (R + 1));
+  ENS(row_cnt, U * (R + 1), sizeof(int32_t), keepU * (R + 1));
+  ENS(zmm, 2 * U, sizeof(int32_t), 2 * keepU);
+  ENS(bincnt, NB, sizeof(int32_t), keepB);
+  ENS(binbeg, NB, sizeof(int32_t), keepB);
+  ENS(yz, N, sizeof(float2), keepN);
+  ENS(sid, N, sizeof(int32_t), keepN);
+  ENS(up, N, sizeof(int32_t), keepN);
+  ENS(dn, N, sizeof(int32_t), keepN);
+  ENS(upc, N, sizeof(int32_t), keepN);
+  ENS(dnc, N, sizeof(int32_t), keepN);
+  ENS(flag, N, sizeof(int32_t), keepN);
+  ENS(owner, N, sizeof(unsigned long long), keepN);
+  ENS(hits_out, N, sizeof(int32_t), keepN);
+  ENS(assign, N, sizeof(int32_t), keepN);
+  ENS(trk_start, T, sizeof(int32_t), keepT);
+  ENS(trk_unit, T, sizeof(int32_t), keepT);
+  ENS(unit_tbegin, U + 1, sizeof(int32_t), keepU);
+  ENS(trk, T, sizeof(tpcca_tracklet_t), keepT);
+  ENS(trk_hits, T * (size_t)R, sizeof(int32_t), keepT * (size_t)R);
+  ENS(accv, T + 1, sizeof(unsigned long long), 0);
+  ENS(accx, T + 1, sizeof(unsigned long long), 0);
+  ENS(tracks, T, sizeof(tpcca_track_t), keepT);
+  ENS(unit_res, U, sizeof(tpcca_unit_result_t), keepU);
+  const size_t tiles = std::max(NB / kScanTile + 2, std::max(NC + 2, T / kScanTile + 2));
+  ENS(scan_tmp, tiles, sizeof(int64_t), 0);
+#undef ENS
+  refresh_bufs(c);
+  return TPCCA_OK;
+}
+
+static int upload_tables(tpcca_ctx *c) {
+  if (!c->tables_dirty) return TPCCA_OK;
+  if (!c->units.empty())
+    HIPCHK(c, hipMemcpyAsync(c->units_d.p, c->units.data(), c->units.size() * sizeof(UnitDev),
+                             hipMemcpyHostToDevice, c->stream));
+  if (!c->chunks.empty())
+    HIPCHK(c, hipMemcpyAsync(c->chunks_d.p, c->chunks.data(), c->chunks.size() * sizeof(Chunk),
+                             hipMemcpyHostToDevice, c->stream));
+  // host vectors may be modified by later loads before the copy runs
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->tables_dirty = false;
+  return TPCCA_OK;
+}
+
+static int write_run(tpcca_ctx *c, int run) {
+  const RunHost &h = c->runs[run];
+  RunDev d{};
+  d.u0 = h.u0;
+  d.u1 = h.u1;
+  d.c0 = h.c0;
+  d.c1 = h.c1;
+  d.cl0 = h.cl0;
+  d.cl1 = h.cl1;
+  d.bin0 = h.bin0;
+  d.bin1 = h.bin1;
+  d.trk0 = h.trk0;
+  d.trk_cap = h.trk_cap;
+  // pageable source: the copy completes before return
+  HIPCHK(c, hipMemcpy(ptr<RunDev>(c->runs_d) + run, &d, sizeof(d), hipMemcpyHostToDevice));
+  return TPCCA_OK;
+}
+
+static RunHost make_run(tpcca_ctx *c, int u0, int u1) {
+  RunHost h{};
+  h.u0 = u0;
+  h.u1 = u1;
+  h.c0 = c->unit_chunk0[u0];
+  h.c1 = c->unit_chunk0[u1];
+  h.cl0 = c->units[u0].cl_begin;
+  const UnitDev &L = c->units[u1 - 1];
+  h.cl1 = L.cl_begin + L.n;
+  h.bin0 = c->units[u0].bin_base;
+  h.bin1 = L.bin_base + bins_cap_of(L.n, c->P.hits_per_bin, c->R);
+  h.trk0 = c->units[u0].trk_base;
+  h.trk_cap = (int32_t)(L.trk_base + trk_cap_of(L.n, c->P.min_chain) - h.trk0);
+  return h;
+}
+
+// Units matching (slot, sector), grouped into maximal index ranges.
+static std::vector<std::pair<int, int>> select_ranges(tpcca_ctx *c, int slot, int sector) {
+  std::vector<std::pair<int, int>> out;
+  int a = -1;
+  for (int u = 0; u <= (int)c->uh.size(); ++u) {
+    bool m = u < (int)c->uh.size() && (slot < 0 || c->uh[u].slot == slot) &&
+             (sector < 0 || c->uh[u].sector == sector);
+    if (m && a < 0) a = u;
+    if (!m && a >= 0) {
+      out.push_back({a, u});
+      a = -1;
+    }
+  }
+  return out;
+}
+
+static void record_event(tpcca_ctx *c, int k) {
+  if (c->timing) hipEventRecord(c->ev[k], c->stream);
+}
+
+// Launch stages [first, last] (1 = grid + links, 2 = clean, 3 = tracklets,
+// 4 = selection) for one run.
+static int launch_stages(tpcca_ctx *c, int run, const RunHost &h, int first, int last) {
+  hipError_t e = hipSuccess;
+  hipStream_t s = c->stream;
+  for (int st = first; st <= last && e == hipSuccess; ++st) {
+    switch (st) {
+      case 1:
+        record_event(c, 0);
+        e = launch_grid(c->B, c->P, run, h, s);
+        record_event(c, 1);
+        if (e == hipSuccess) e = launch_links(c->B, c->P, run, h, s);
+        record_event(c, 2);
+        break;
+      case 2:
+        e = launch_clean(c->B, c->P, run, h, s);
+        record_event(c, 3);
+        break;
+      case 3:
+        e = launch_tracklets(c->B, c->P, run, h, s);
+        record_event(c, 4);
+        break;
+      case 4:
+        e = launch_select(c->B, c->P, run, h, s);
+        record_event(c, 5);
+        break;
+    }
+  }
+  if (e != hipSuccess) return dev_err(c, e, "kernel launch");
+  if (c->timing && first == 1 && last == 4) c->have_times = true;
+  return TPCCA_OK;
+}
+
+static int stage_call(tpcca_ctx *c, int slot, int sector, int stage) {
+  if (!c) return TPCCA_EINVAL;
+  auto ranges = select_ranges(c, slot, sector);
+  if (ranges.empty()) return TPCCA_ESTATE;
+  if (stage == 1) {
+    for (auto &r : ranges)
+      for (int u = r.first; u < r.second; ++u)
+        if (c->uh[u].state != kLoaded) return TPCCA_ESTATE;
+    int rc = ensure_work(c, c->n_total, (int64_t)c->units.size(), c->bins_total, c->trk_total,
+                         (int64_t)c->chunks.size());
+    if (rc != TPCCA_OK) return rc;
+    if ((rc = upload_tables(c)) != TPCCA_OK) return rc;
+    for (auto &r : ranges) {
+      const int run = (int)c->runs.size();
+      c->runs.push_back(make_run(c, r.first, r.second));
+      if ((rc = ensure_work(c, c->n_total, (int64_t)c->units.size(), c->bins_total, c->trk_total,
+                            (int64_t)c->chunks.size())) != TPCCA_OK)
+        return rc;
+      if ((rc = write_run(c, run)) != TPCCA_OK) return rc;
+      if ((rc = launch_stages(c, run, c->runs[run], 1, 1)) != TPCCA_OK) return rc;
+      for (int u = r.first; u < r.second; ++u) {
+        c->uh[u].state = kLinked;
+        c->uh[u].run = run;
+      }
+      c->pending_runs.push_back(run);
+    }
+    return TPCCA_OK;
+  }
+  // later stages act on whole runs
+  std::vector<int> runs;
+  for (auto &r : ranges)
+    for (int u = r.first; u < r.second; ++u)
+      if (std::find(runs.begin(), runs.end(), c->uh[u].run) == runs.end()) runs.push_back(c->uh[u].run);
+  for (int run : runs) {
+    if (run < 0) return TPCCA_ESTATE;
+    const RunHost &h = c->runs[run];
+    for (int u = h.u0; u < h.u1; ++u)
+      if (c->uh[u].state != stage) return TPCCA_ESTATE;
+  }
+  for (int run : runs) {
+    const RunHost &h = c->runs[run];
+    int rc = launch_stages(c, run, h, stage, stage);
+    if (rc != TPCCA_OK) return rc;
+    for (int u = h.u0; u < h.u1; ++u) c->uh[u].state = stage + 1;
+  }
+  return TPCCA_OK;
+}
+
+static int check_errors(tpcca_ctx *c) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int rc = TPCCA_OK;
+  for (int run : c->pending_runs) {
+    RunDev d;
+    HIPCHK(c, hipMemcpy(&d, ptr<RunDev>(c->runs_d) + run, sizeof(d), hipMemcpyDeviceToHost));
+    if (d.err) {
+      c->last_error = "invalid cluster (row out of range, non-finite value, or x off its row)";
+      rc = TPCCA_EINVAL;
+    }
+  }
+  c->pending_runs.clear();
+  if (c->timing && c->have_times) {
+    for (int k = 0; k < 5; ++k) hipEventElapsedTime(&c->stage_ms[k], c->ev[k], c->ev[k + 1]);
+  }
+  return rc;
+}
+
+static int find_unit(tpcca_ctx *c, int slot, int sector) {
+  auto it = c->index.find({slot, sector});
+  return it == c->index.end() ? -1 : it->second;
+}
+
+static int load_unit(tpcca_ctx *c, int32_t slot, int32_t sector, const tpcca_cluster_t *cl,
+                     const uint8_t *row, int32_t n, int32_t flags, bool defer_copy) {
+  if (!c || n < 0 || slot < 0 || sector < 0 || sector >= c->n_sectors) return TPCCA_EINVAL;
+  if (n > 0 && (!cl || !row)) return TPCCA_EINVAL;
+  if (n > 0xFFFFFF) {
+    c->last_error = "a unit holds at most 2^24 - 1 clusters";
+    return TPCCA_EINVAL;
+  }
+  if (c->index.count({slot, sector})) return TPCCA_ESTATE;
+  if (c->n_total + n > (int64_t)0x7FFFFFFF) return TPCCA_ENOMEM;
+  UnitDev U{};
+  U.n = n;
+  U.slot = slot;
+  U.sector = sector;
+  U.cl_begin = (int32_t)c->n_total;
+  U.bin_base = c->bins_total;
+  U.trk_base = (int32_t)c->trk_total;
+  if ((flags & 1) == TPCCA_MEM_DEVICE) {
+    U.cl = reinterpret_cast<const float4 *>(cl);
+    U.row = row;
+  } else if (n > 0) {
+    float4 *old_cl = ptr<float4>(c->in_cl);
+    uint8_t *old_row = ptr<uint8_t>(c->in_row);
+    int rc = ensure(c, c->in_cl, (size_t)(c->in_used + n) * sizeof(float4),
+                    (size_t)c->in_used * sizeof(float4));
+    if (rc != TPCCA_OK) return rc;
+    rc = ensure(c, c->in_row, (size_t)(c->in_used + n), (size_t)c->in_used);
+    if (rc != TPCCA_OK) return rc;
+    if (old_cl && old_cl != ptr<float4>(c->in_cl)) {
+      // staged units recorded addresses in the old buffers: rebase them
+      for (auto &V : c->units) {
+        if (V.cl >= old_cl && V.cl < old_cl + c->in_used) {
+          V.row = ptr<uint8_t>(c->in_row) + (V.row - old_row);
+          V.cl = ptr<float4>(c->in_cl) + (V.cl - old_cl);
+        }
+      }
+      c->tables_dirty = true;
+    }
+    float4 *dcl = ptr<float4>(c->in_cl) + c->in_used;
+    uint8_t *drow = ptr<uint8_t>(c->in_row) + c->in_used;
+    if (!defer_copy) {
+      HIPCHK(c, hipMemcpyAsync(dcl, cl, (size_t)n * sizeof(float4), hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(drow, row, (size_t)n, hipMemcpyHostToDevice, c->stream));
+    }
+    U.cl = dcl;
+    U.row = drow;
+    c->in_used += n;
+  }
+  const int u = (int)c->units.size();
+  c->units.push_back(U);
+  c->uh.push_back({slot, sector, n, kLoaded, -1});
+  for (int32_t b = 0; b < n; b += kChunk) c->chunks.push_back({u, b, std::min(kChunk, n - b), 0});
+  c->unit_chunk0.push_back((int32_t)c->chunks.size());
+  c->index[{slot, sector}] = u;
+  c->n_total += n;
+  c->bins_total += bins_cap_of(n, c->P.hits_per_bin, c->R);
+  c->trk_total += trk_cap_of(n, c->P.min_chain);
+  c->tables_dirty = true;
+  return TPCCA_OK;
+}
+
+// ===================================================================== ABI
+extern "C" {
+
+void tpcca_params_default(tpcca_params_t *p) {
+  if (!p) return;
+  p->n_rows = 159;
+  p->link_wy = 2.0f;
+  p->link_wz = 2.0f;
+  p->link_chi2 = 0.2f;
+  p->min_chain_hits = 3;
+  p->kB = (float)(-0.5 * 0.299792458e-2);
+  p->err2_y = 0.01f;
+  p->err2_z = 0.01f;
+  p->max_sinphi = 0.95f;
+  p->seed_c22 = 0.25f;
+  p->seed_c33 = 0.25f;
+  p->seed_c44 = 400.0f;
+  p->reset_c00 = 1.0f;
+  p->reset_c11 = 1.0f;
+  p->pick_nsig = 3.0f;
+  p->pick_win_max = 4.0f;
+  p->pick_chi2 = 16.0f;
+  p->max_miss = 10;
+  p->min_track_hits = 10;
+  p->own_frac_pct = 90;
+  p->refit_inflate = 100.0f;
+  p->grid_hits_per_bin = 2;
+}
+
+const char *tpcca_error_string(int s) {
+  switch (s) {
+    case TPCCA_OK: return "ok";
+    case TPCCA_EINVAL: return "invalid argument or cluster";
+    case TPCCA_ENOMEM: return "device memory budget exceeded";
+    case TPCCA_ECAPACITY: return "output buffer too small";
+    case TPCCA_EDEVICE: return "HIP runtime error";
+    case TPCCA_ESTATE: return "stage called out of order or unit not loaded";
+    case TPCCA_EBUSY: return "busy, retry later";
+    case TPCCA_ENOTFOUND: return "unknown request";
+  }
+  return "unknown status";
+}
+
+const char *tpcca_last_error(tpcca_ctx_t *c) { return c ? c->last_error.c_str() : ""; }
+
+int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int device,
+                 void *hip_stream, size_t budget, tpcca_ctx_t **out) {
+  if (!geo || !params || !out || !geo->row_x) return TPCCA_EINVAL;
+  if (geo->n_rows < 3 || geo->n_rows > kMaxRows || params->n_rows != geo->n_rows) return TPCCA_EINVAL;
+  if (geo->n_sectors < 1 || params->grid_hits_per_bin < 1 || params->min_chain_hits < 2 ||
+      params->min_track_hits < 1 || params->max_miss < 1)
+    return TPCCA_EINVAL;
+  *out = nullptr;
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return TPCCA_EDEVICE;
+  tpcca_ctx *c = new tpcca_ctx();
+  c->device = device;
+  c->budget = budget ? budget : ((size_t)64 << 30);
+  c->params = *params;
+  c->R = geo->n_rows;
+  c->n_sectors = geo->n_sectors;
+  c->row_x.assign(geo->row_x, geo->row_x + geo->n_rows);
+  ParamsDev &P = c->P;
+  P.n_rows = params->n_rows;
+  P.wy = params->link_wy;
+  P.wz = params->link_wz;
+  P.link_chi2 = params->link_chi2;
+  P.min_chain = params->min_chain_hits;
+  P.kB = params->kB;
+  P.ery = params->err2_y;
+  P.erz = params->err2_z;
+  P.max_sin = params->max_sinphi;
+  P.c22 = params->seed_c22;
+  P.c33 = params->seed_c33;
+  P.c44 = params->seed_c44;
+  P.r00 = params->reset_c00;
+  P.r11 = params->reset_c11;
+  P.nsig = params->pick_nsig;
+  P.wmax = params->pick_win_max;
+  P.pick_chi2 = params->pick_chi2;
+  P.max_miss = params->max_miss;
+  P.min_hits = params->min_track_hits;
+  P.own_pct = params->own_frac_pct;
+  P.inflate = params->refit_inflate;
+  P.hits_per_bin = params->grid_hits_per_bin;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return TPCCA_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  for (int k = 0; k < 6; ++k) hipEventCreate(&c->ev[k]);
+  c->unit_chunk0.push_back(0);
+  int rc = ensure(c, c->row_x_d, sizeof(float) * c->R, 0);
+  if (rc == TPCCA_OK) {
+    e = hipMemcpy(c->row_x_d.p, c->row_x.data(), sizeof(float) * c->R, hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = dev_err(c, e, "hipMemcpy(row_x)");
+  }
+  if (rc != TPCCA_OK) {
+    tpcca_destroy(c);
+    return rc;
+  }
+  refresh_bufs(c);
+  *out = c;
+  return TPCCA_OK;
+}
+
+int tpcca_destroy(tpcca_ctx_t *c) {
+  if (!c) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  DevBuf *all[] = {&c->row_x_d, &c->units_d, &c->chunks_d, &c->runs_d, &c->rowtab, &c->row_cnt,
+                   &c->zmm, &c->bincnt, &c->binbeg, &c->yz, &c->sid, &c->up, &c->dn, &c->upc,
+                   &c->dnc, &c->flag, &c->trk_start, &c->trk_unit, &c->unit_tbegin, &c->trk,
+                   &c->trk_hits, &c->owner, &c->accv, &c->accx, &c->tracks, &c->hits_out,
+                   &c->assign, &c->unit_res, &c->scan_tmp, &c->in_cl, &c->in_row};
+  for (DevBuf *b : all)
+    if (b->p) hipFree(b->p);
+  for (int k = 0; k < 6; ++k)
+    if (c->ev[k]) hipEventDestroy(c->ev[k]);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  delete c;
+  return TPCCA_OK;
+}
+
+int tpcca_reset(tpcca_ctx_t *c) {
+  if (!c) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->units.clear();
+  c->uh.clear();
+  c->chunks.clear();
+  c->unit_chunk0.assign(1, 0);
+  c->runs.clear();
+  c->index.clear();
+  c->pending_runs.clear();
+  c->n_total = c->bins_total = c->trk_total = c->in_used = 0;
+  c->tables_dirty = true;
+  c->have_times = false;
+  return TPCCA_OK;
+}
+
+int tpcca_load_sector(tpcca_ctx_t *c, int32_t slot, int32_t sector, const tpcca_cluster_t *cl,
+                      const uint8_t *row, int32_t n, int32_t flags) {
+  if (!c) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  int rc = load_unit(c, slot, sector, cl, row, n, flags, false);
+  if (rc == TPCCA_OK && (flags & 1) == TPCCA_MEM_HOST && n > 0) {
+    // the caller may reuse pageable buffers on return
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return rc;
+}
+
+int tpcca_find_links(tpcca_ctx_t *c, int32_t slot, int32_t sector) {
+  if (!c) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  return stage_call(c, slot, sector, 1);
+}
+int tpcca_clean_links(tpcca_ctx_t *c, int32_t slot, int32_t sector) {
+  if (!c) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  return stage_call(c, slot, sector, kLinked);
+}
+int tpcca_build_tracklets(tpcca_ctx_t *c, int32_t slot, int32_t sector) {
+  if (!c) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  return stage_call(c, slot, sector, kCleaned);
+}
+int tpcca_select_tracks(tpcca_ctx_t *c, int32_t slot, int32_t sector) {
+  if (!c) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  return stage_call(c, slot, sector, kTracklets);
+}
+
+int tpcca_sync(tpcca_ctx_t *c) {
+  if (!c) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  return check_errors(c);
+}
+
+int tpcca_get_links(tpcca_ctx_t *c, int32_t slot, int32_t sector, int32_t which, int32_t *up,
+                    int32_t *down, int32_t n) {
+  if (!c || !up || !down) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  const int u = find_unit(c, slot, sector);
+  if (u < 0 || c->uh[u].state < kLinked || (which == 1 && c->uh[u].state < kCleaned))
+    return TPCCA_ESTATE;
+  if (n != c->uh[u].n) return TPCCA_EINVAL;
+  int rc = check_errors(c);
+  if (rc != TPCCA_OK) return rc;
+  if (n == 0) return TPCCA_OK;
+  int32_t *tmp = nullptr;
+  HIPCHK(c, hipMalloc(&tmp, sizeof(int32_t) * 2 * (size_t)n));
+  const UnitDev &U = c->units[u];
+  hipError_t e = launch_links_by_id(c->B, which ? c->B.upc : c->B.up, which ? c->B.dnc : c->B.dn,
+                                    tmp, tmp + n, U.cl_begin, n, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(up, tmp, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(down, tmp + n, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(tmp);
+  if (e != hipSuccess) return dev_err(c, e, "get_links");
+  return TPCCA_OK;
+}
+
+// tracklet range [t0, t1) of a unit (valid once tracklets were built)
+static int unit_tracklets(tpcca_ctx *c, int u, int32_t *t0, int32_t *t1) {
+  const int run = c->uh[u].run;
+  const RunHost &h = c->runs[run];
+  int32_t tb[2];
+  HIPCHK(c, hipMemcpy(&tb[0], ptr<int32_t>(c->unit_tbegin) + u, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (u + 1 < h.u1) {
+    HIPCHK(c, hipMemcpy(&tb[1], ptr<int32_t>(c->unit_tbegin) + u + 1, sizeof(int32_t),
+                        hipMemcpyDeviceToHost));
+  } else {
+    RunDev d;
+    HIPCHK(c, hipMemcpy(&d, ptr<RunDev>(c->runs_d) + run, sizeof(d), hipMemcpyDeviceToHost));
+    tb[1] = d.trk0 + d.n_trk;
+  }
+  *t0 = tb[0];
+  *t1 = tb[1];
+  return TPCCA_OK;
+}
+
+int tpcca_get_tracklets(tpcca_ctx_t *c, int32_t slot, int32_t sector, tpcca_tracklet_t *out,
+                        int32_t cap, int32_t *n_out, int64_t *hit_begin, int32_t *hits,
+                        int64_t hits_cap, int64_t *n_hits_out) {
+  if (!c || !n_out) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  const int u = find_unit(c, slot, sector);
+  if (u < 0 || c->uh[u].state < kTracklets) return TPCCA_ESTATE;
+  int rc = check_errors(c);
+  if (rc != TPCCA_OK) return rc;
+  int32_t t0, t1;
+  if ((rc = unit_tracklets(c, u, &t0, &t1)) != TPCCA_OK) return rc;
+  const int T = t1 - t0;
+  std::vector<tpcca_tracklet_t> trk(T);
+  if (T > 0)
+    HIPCHK(c, hipMemcpy(trk.data(), ptr<tpcca_tracklet_t>(c->trk) + t0, sizeof(tpcca_tracklet_t) * T,
+                        hipMemcpyDeviceToHost));
+  int64_t nh = 0;
+  for (auto &t : trk) nh += t.n_hits;
+  *n_out = T;
+  if (n_hits_out) *n_hits_out = nh;
+  if (cap < T || (hits && hits_cap < nh)) return TPCCA_ECAPACITY;
+  if (out && T) std::memcpy(out, trk.data(), sizeof(tpcca_tracklet_t) * T);
+  if (hits || hit_begin) {
+    const UnitDev &U = c->units[u];
+    std::vector<int32_t> sid(U.n);
+    if (U.n)
+      HIPCHK(c, hipMemcpy(sid.data(), ptr<int32_t>(c->sid) + U.cl_begin, sizeof(int32_t) * U.n,
+                          hipMemcpyDeviceToHost));
+    std::vector<int32_t> slots((size_t)T * c->R);
+    if (T)
+      HIPCHK(c, hipMemcpy(slots.data(), ptr<int32_t>(c->trk_hits) + (int64_t)t0 * c->R,
+                          sizeof(int32_t) * slots.size(), hipMemcpyDeviceToHost));
+    int64_t off = 0;
+    for (int t = 0; t < T; ++t) {
+      if (hit_begin) hit_begin[t] = off;
+      const int n1 = trk[t].n_pass1, ne = trk[t].n_hits - trk[t].n_pass1;
+      const int32_t *hl = slots.data() + (size_t)t * c->R;
+      for (int j = 0; j < trk[t].n_hits; ++j) {
+        const int g = j < ne ? hl[n1 + ne - 1 - j] : hl[j - ne];
+        if (hits) hits[off] = sid[g - U.cl_begin];
+        ++off;
+      }
+    }
+    if (hit_begin) hit_begin[T] = off;
+  }
+  return TPCCA_OK;
+}
+
+int tpcca_get_tracks(tpcca_ctx_t *c, int32_t slot, int32_t sector, tpcca_track_t *out, int32_t cap,
+                     int32_t *n_out, int32_t *hits, int64_t hits_cap, int64_t *n_hits_out) {
+  if (!c || !n_out) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  const int u = find_unit(c, slot, sector);
+  if (u < 0 || c->uh[u].state < kSelected) return TPCCA_ESTATE;
+  int rc = check_errors(c);
+  if (rc != TPCCA_OK) return rc;
+  tpcca_unit_result_t r;
+  HIPCHK(c, hipMemcpy(&r, ptr<tpcca_unit_result_t>(c->unit_res) + u, sizeof(r), hipMemcpyDeviceToHost));
+  *n_out = r.n_tracks;
+  if (n_hits_out) *n_hits_out = r.n_track_hits;
+  if (cap < r.n_tracks || (hits && hits_cap < r.n_track_hits)) return TPCCA_ECAPACITY;
+  if (out && r.n_tracks)
+    HIPCHK(c, hipMemcpy(out, ptr<tpcca_track_t>(c->tracks) + r.track_begin,
+                        sizeof(tpcca_track_t) * r.n_tracks, hipMemcpyDeviceToHost));
+  if (hits && r.n_track_hits)
+    HIPCHK(c, hipMemcpy(hits, ptr<int32_t>(c->hits_out) + r.hit_begin, sizeof(int32_t) * r.n_track_hits,
+                        hipMemcpyDeviceToHost));
+  return TPCCA_OK;
+}
+
+int tpcca_get_assignment(tpcca_ctx_t *c, int32_t slot, int32_t sector, int32_t *a, int32_t n) {
+  if (!c || !a) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  const int u = find_unit(c, slot, sector);
+  if (u < 0 || c->uh[u].state < kSelected) return TPCCA_ESTATE;
+  if (n != c->uh[u].n) return TPCCA_EINVAL;
+  int rc = check_errors(c);
+  if (rc != TPCCA_OK) return rc;
+  if (n)
+    HIPCHK(c, hipMemcpy(a, ptr<int32_t>(c->assign) + c->units[u].cl_begin, sizeof(int32_t) * n,
+                        hipMemcpyDeviceToHost));
+  return TPCCA_OK;
+}
+
+// ---------------------------------------------------------------- batch ---
+static int64_t bucket(int64_t v) {
+  int64_t b = 1024;
+  while (b < v) b += b / 2;
+  return b;
+}
+
+int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
+  if (!c || !bt || bt->n_units < 0) return TPCCA_EINVAL;
+  if (bt->n_units > 0 && (!bt->slot || !bt->sector || !bt->begin || !bt->n)) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  int rc = tpcca_reset(c);
+  if (rc != TPCCA_OK) return rc;
+  const bool host = (bt->flags & 1) == TPCCA_MEM_HOST;
+  const bool graph = (bt->flags & TPCCA_BATCH_GRAPH) != 0;
+  int64_t lo = INT64_MAX, hi = 0, tot = 0;
+  for (int u = 0; u < bt->n_units; ++u) {
+    if (bt->n[u] < 0 || bt->begin[u] < 0) return TPCCA_EINVAL;
+    if (bt->n[u] == 0) continue;
+    lo = std::min<int64_t>(lo, bt->begin[u]);
+    hi = std::max<int64_t>(hi, bt->begin[u] + bt->n[u]);
+    tot += bt->n[u];
+  }
+  if (tot > 0 && (!bt->cl || !bt->row)) return TPCCA_EINVAL;
+  const tpcca_cluster_t *cl_base = bt->cl;
+  const uint8_t *row_base = bt->row;
+  if (host && tot > 0) {
+    // one copy of the batch's input span
+    const int64_t span = hi - lo;
+    if ((rc = ensure(c, c->in_cl, (size_t)span * sizeof(float4), 0)) != TPCCA_OK) return rc;
+    if ((rc = ensure(c, c->in_row, (size_t)span, 0)) != TPCCA_OK) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->in_cl.p, bt->cl + lo, (size_t)span * sizeof(float4),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->in_row.p, bt->row + lo, (size_t)span, hipMemcpyHostToDevice, c->stream));
+    cl_base = reinterpret_cast<const tpcca_cluster_t *>(ptr<float4>(c->in_cl)) - lo;
+    row_base = ptr<uint8_t>(c->in_row) - lo;
+  }
+  for (int u = 0; u < bt->n_units; ++u) {
+    rc = load_unit(c, bt->slot[u], bt->sector[u], cl_base + bt->begin[u], row_base + bt->begin[u],
+                   bt->n[u], TPCCA_MEM_DEVICE, true);
+    if (rc != TPCCA_OK) return rc;
+  }
+  if (c->units.empty()) return TPCCA_OK;
+  // capacities: graphs are captured for buckets so that they are replayed
+  const int U = (int)c->units.size();
+  int64_t capN = c->n_total, capU = U, capB = c->bins_total, capT = c->trk_total,
+          capC = (int64_t)c->chunks.size();
+  if (graph) {
+    capN = bucket(capN);
+    capU = bucket(capU);
+    capB = bucket(capB);
+    capT = bucket(capT);
+    capC = bucket(capC);
+  }
+  if ((rc = ensure_work(c, capN, capU, capB, capT, capC)) != TPCCA_OK) return rc;
+  if ((rc = upload_tables(c)) != TPCCA_OK) return rc;
+  c->runs.push_back(make_run(c, 0, U));
+  if ((rc = write_run(c, 0)) != TPCCA_OK) return rc;
+  for (int u = 0; u < U; ++u) {
+    c->uh[u].run = 0;
+    c->uh[u].state = kSelected;
+  }
+  c->pending_runs.push_back(0);
+  if (!graph) return launch_stages(c, 0, c->runs[0], 1, 4);
+  RunHost capr = c->runs[0];
+  capr.u1 = (int32_t)capU;
+  capr.c1 = (int32_t)capC;
+  capr.cl1 = (int32_t)capN;
+  capr.bin1 = capB;
+  capr.trk_cap = (int32_t)capT;
+  const bool reuse = c->gexec && c->gen_captured == c->generation && c->gcap.u1 == capr.u1 &&
+                     c->gcap.c1 == capr.c1 && c->gcap.cl1 == capr.cl1 && c->gcap.bin1 == capr.bin1 &&
+                     c->gcap.trk_cap == capr.trk_cap;
+  if (!reuse) {
+    if (c->gexec) {
+      hipGraphExecDestroy(c->gexec);
+      c->gexec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    const bool tm = c->timing;
+    c->timing = false;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int lrc = launch_stages(c, 0, capr, 1, 4);
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->timing = tm;
+    if (lrc != TPCCA_OK) return lrc;
+    if (e != hipSuccess) return dev_err(c, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return dev_err(c, e, "hipGraphInstantiate");
+    c->gcap = capr;
+    c->gen_captured = c->generation;
+  }
+  record_event(c, 0);
+  HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+  if (c->timing) {
+    for (int k = 1; k <= 5; ++k) hipEventRecord(c->ev[k], c->stream);
+  }
+  return TPCCA_OK;
+}
+
+int tpcca_batch_totals(tpcca_ctx_t *c, int32_t *n_units, int64_t *n_clusters, int64_t *n_tracks,
+                       int64_t *n_hits) {
+  if (!c) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  int rc = check_errors(c);
+  if (rc != TPCCA_OK) return rc;
+  if (n_units) *n_units = (int32_t)c->units.size();
+  if (n_clusters) *n_clusters = c->n_total;
+  int64_t nt = 0, nh = 0;
+  for (size_t r = 0; r < c->runs.size(); ++r) {
+    RunDev d;
+    HIPCHK(c, hipMemcpy(&d, ptr<RunDev>(c->runs_d) + r, sizeof(d), hipMemcpyDeviceToHost));
+    bool selected = true;
+    for (int u = c->runs[r].u0; u < c->runs[r].u1; ++u) selected &= c->uh[u].state >= kSelected;
+    if (selected) {
+      nt += d.n_acc;
+      nh += d.n_acc_hits;
+    }
+  }
+  if (n_tracks) *n_tracks = nt;
+  if (n_hits) *n_hits = nh;
+  return TPCCA_OK;
+}
+
+int tpcca_get_batch_results(tpcca_ctx_t *c, tpcca_unit_result_t *units, tpcca_track_t *tracks,
+                            int64_t tracks_cap, int32_t *hits, int64_t hits_cap, int32_t *assignment,
+                            int64_t n_clusters) {
+  if (!c) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  int rc = check_errors(c);
+  if (rc != TPCCA_OK) return rc;
+  const int U = (int)c->units.size();
+  for (int u = 0; u < U; ++u)
+    if (c->uh[u].state < kSelected) return TPCCA_ESTATE;
+  std::vector<tpcca_unit_result_t> ur(U);
+  if (U)
+    HIPCHK(c, hipMemcpy(ur.data(), c->unit_res.p, sizeof(tpcca_unit_result_t) * U, hipMemcpyDeviceToHost));
+  int64_t nt = 0, nh = 0;
+  for (auto &r : ur) {
+    nt += r.n_tracks;
+    nh += r.n_track_hits;
+  }
+  if ((tracks && tracks_cap < nt) || (hits && hits_cap < nh) || (assignment && n_clusters < c->n_total))
+    return TPCCA_ECAPACITY;
+  // batch-relative offsets
+  int64_t to = 0, ho = 0;
+  for (int u = 0; u < U; ++u) {
+    if (tracks && ur[u].n_tracks)
+      HIPCHK(c, hipMemcpyAsync(tracks + to, ptr<tpcca_track_t>(c->tracks) + ur[u].track_begin,
+                               sizeof(tpcca_track_t) * ur[u].n_tracks, hipMemcpyDeviceToHost, c->stream));
+    if (hits && ur[u].n_track_hits)
+      HIPCHK(c, hipMemcpyAsync(hits + ho, ptr<int32_t>(c->hits_out) + ur[u].hit_begin,
+                               sizeof(int32_t) * ur[u].n_track_hits, hipMemcpyDeviceToHost, c->stream));
+    ur[u].track_begin = to;
+    ur[u].hit_begin = ho;
+    to += ur[u].n_tracks;
+    ho += ur[u].n_track_hits;
+  }
+  if (assignment && c->n_total)
+    HIPCHK(c, hipMemcpyAsync(assignment, c->assign.p, sizeof(int32_t) * c->n_total, hipMemcpyDeviceToHost,
+                             c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (units && U) std::memcpy(units, ur.data(), sizeof(tpcca_unit_result_t) * U);
+  return TPCCA_OK;
+}
+
+int tpcca_device_results(tpcca_ctx_t *c, tpcca_device_results_t *out) {
+  if (!c || !out) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  int rc = check_errors(c);
+  if (rc != TPCCA_OK) return rc;
+  out->tracks = ptr<tpcca_track_t>(c->tracks);
+  out->hits = ptr<int32_t>(c->hits_out);
+  out->assignment = ptr<int32_t>(c->assign);
+  out->units = ptr<tpcca_unit_result_t>(c->unit_res);
+  out->n_units = (int32_t)c->units.size();
+  return TPCCA_OK;
+}
+
+int tpcca_set_timing(tpcca_ctx_t *c, int32_t enable) {
+  if (!c) return TPCCA_EINVAL;
+  c->timing = enable != 0;
+  return TPCCA_OK;
+}
+
+int tpcca_stage_times(tpcca_ctx_t *c, float *ms, int32_t cap) {
+  if (!c || !ms) return TPCCA_EINVAL;
+  if (!c->have_times) return 0;
+  int n = std::min(cap, 5);
+  for (int k = 0; k < n; ++k) ms[k] = c->stage_ms[k];
+  return n;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ internal (server) hooks ---
+namespace tpcca {
+hipStream_t ctx_stream(tpcca_ctx *c) { return c->stream; }
+size_t ctx_allocated(tpcca_ctx *c) { return c->allocated; }
+}  // namespace tpcca

@@ -1,0 +1,58 @@
+"""The C ABI library: it loads, exports what include/tpcca.h declares, and
+its defaults agree with the oracle's reading (no GPU needed)."""
+import os
+import re
+
+import numpy as np
+
+import oracle
+from paper_1709_00618_amd import tpcca
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "tpcca.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tpcca_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = tpcca.lib()
+    names = _declared()
+    assert len(names) >= 30
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(tpcca.SYMBOLS)
+
+
+def test_struct_layouts():
+    import ctypes
+    assert tpcca.TRACK_DTYPE.itemsize == 108
+    assert ctypes.sizeof(tpcca.Params) == 22 * 4
+    assert ctypes.sizeof(tpcca.Timeframe) == 13 * 8
+
+
+def test_defaults_match_the_oracle_reading():
+    g = tpcca.params_default()
+    o = oracle.default_params()
+    for name, _ in oracle.Params._fields_:
+        assert np.float32(getattr(g, name)) == np.float32(getattr(o, name)), name
+    assert g.grid_hits_per_bin >= 1
+
+
+def test_error_strings():
+    for s in (tpcca.OK, tpcca.EINVAL, tpcca.ENOMEM, tpcca.ECAPACITY, tpcca.EDEVICE, tpcca.ESTATE,
+              tpcca.EBUSY, tpcca.ENOTFOUND):
+        assert tpcca.error_string(s) not in ("", "unknown status")
+    assert tpcca.error_string(12345) == "unknown status"
+
+
+def test_product_path_does_not_touch_the_oracle():
+    """The package and its sources never import or link the oracle."""
+    pkg = os.path.join(ROOT, "paper_1709_00618_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "tpcref" not in text and "import oracle" not in text, f

@@ -1,0 +1,233 @@
+"""GPU parity: the gfx950 path against the FP32 oracle, element by element.
+
+Sizes span several chunks (1024 clusters) and a ragged tail; the workloads
+are the one-sector, central-event and minimum-bias recipes of tpcgen, plus
+edge cases (empty unit, one cluster, one row, edge rows only, bad input).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import tpcgen
+from tests import _parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def tpcca(torch_cuda):
+    from paper_1709_00618_amd import tpcca as m
+    m.lib()
+    return m
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_one_sector_stagewise_host_input(tpcca, row_x):
+    b = tpcgen.one_sector(seed=0)
+    cl, row, slot, sec, _ = b.unit(0)
+    print(f"one sector: {cl.shape[0]} clusters", flush=True)
+    ref = oracle.run_sector(cl, row, row_x)
+    with tpcca.Context(row_x) as ctx:
+        ctx.load_sector(slot, sec, cl, row)
+        ctx.find_links(slot, sec)
+        ctx.clean_links(slot, sec)
+        ctx.build_tracklets(slot, sec)
+        ctx.select_tracks(slot, sec)
+        ctx.sync()
+        _parity.compare_unit_stagewise(ctx, slot, sec, cl, row, ref)
+    assert ref.n_tracks > 20
+
+
+def test_central_event_one_launch_per_stage(tpcca, torch_cuda, row_x):
+    """All 36 sectors of a central event in one launch per kernel, inputs in HBM."""
+    torch = torch_cuda
+    b = tpcgen.central_event(seed=0, keep_truth=False)
+    print(f"central event: {b.n_clusters} clusters", flush=True)
+    dcl, drow = _dev(torch, b.cl), _dev(torch, b.row)
+    torch.cuda.synchronize()
+    refs = _parity.oracle_units(b, row_x)
+    with tpcca.Context(row_x) as ctx:
+        for u in range(b.units.shape[0]):
+            beg, n, slot, sec = (int(v) for v in b.units[u])
+            ctx.load_sector(slot, sec, dcl[beg:beg + n], drow[beg:beg + n], device=True)
+        ctx.run_all(0, -1)
+        ctx.sync()
+        for u in range(b.units.shape[0]):
+            cl, row, slot, sec, _ = b.unit(u)
+            _parity.compare_unit_stagewise(ctx, slot, sec, cl, row, refs[u])
+    assert sum(r.n_tracks for r in refs) > 15000
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_minbias_batch(tpcca, torch_cuda, row_x, graph):
+    torch = torch_cuda
+    b = tpcgen.minbias_batch(seed=1, n_events=6)
+    print(f"batch: {b.units.shape[0]} units, {b.n_clusters} clusters, graph={graph}", flush=True)
+    refs = _parity.oracle_units(b, row_x)
+    dcl, drow = _dev(torch, b.cl), _dev(torch, b.row)
+    torch.cuda.synchronize()
+    with tpcca.Context(row_x) as ctx:
+        ctx.run_batch(dcl, drow, b.units, device=True, graph=graph)
+        units, tracks, hits, asg = ctx.get_batch_results()
+    _parity.compare_batch(units, tracks, hits, asg, b, refs)
+
+
+def test_graph_replays_track_changing_batches(tpcca, torch_cuda, row_x):
+    """One context, graph replays of different batches, host work between."""
+    torch = torch_cuda
+    batches = [tpcgen.minbias_batch(seed=s, n_events=k) for s, k in ((2, 5), (3, 3), (4, 5))]
+    with tpcca.Context(row_x) as ctx:
+        for b in batches:
+            print(f"replay batch {b.n_clusters} clusters", flush=True)
+            refs = _parity.oracle_units(b, row_x)
+            ctx.run_batch(b.cl, b.row, b.units, device=False, graph=True)
+            units, tracks, hits, asg = ctx.get_batch_results()
+            _parity.compare_batch(units, tracks, hits, asg, b, refs)
+
+
+def test_batch_equals_sector_by_sector(tpcca, row_x):
+    """A unit's results do not depend on the batch it runs in."""
+    b = tpcgen.minbias_batch(seed=5, n_events=3)
+    with tpcca.Context(row_x) as ctx:
+        ctx.run_batch(b.cl, b.row, b.units, graph=True)
+        units, tracks, hits, asg = ctx.get_batch_results()
+    with tpcca.Context(row_x) as ctx:
+        for u in range(b.units.shape[0]):
+            cl, row, slot, sec, _ = b.unit(u)
+            ctx.load_sector(slot, sec, cl, row)
+            ctx.run_all(slot, sec)
+        ctx.sync()
+        for u in range(b.units.shape[0]):
+            cl, row, slot, sec, _ = b.unit(u)
+            tr, h = ctx.get_tracks(slot, sec)
+            ur = units[u]
+            t0, nt = int(ur["track_begin"]), int(ur["n_tracks"])
+            h0, nh = int(ur["hit_begin"]), int(ur["n_track_hits"])
+            assert tr.tobytes() == tracks[t0:t0 + nt].tobytes()
+            assert np.array_equal(h, hits[h0:h0 + nh])
+            a = ctx.get_assignment(slot, sec, cl.shape[0])
+            c0 = int(ur["cluster_begin"])
+            assert np.array_equal(a, asg[c0:c0 + cl.shape[0]])
+
+
+def _edge_units(row_x):
+    rng = np.random.default_rng(9)
+    units = []
+    units.append(("empty", np.zeros((0, 4), np.float32), np.zeros(0, np.uint8)))
+    units.append(("one", np.array([[row_x[5], 1.0, 20.0, 1.0]], np.float32), np.array([5], np.uint8)))
+    # all clusters in one row
+    k = 3000
+    cl = np.stack([np.full(k, row_x[40]), rng.uniform(-20, 20, k), rng.uniform(0, 250, k), np.ones(k)], 1)
+    units.append(("one row", cl.astype(np.float32), np.full(k, 40, np.uint8)))
+    # only the edge rows (no links can form there)
+    k = 500
+    r = np.where(rng.random(k) < 0.5, 0, 158).astype(np.uint8)
+    cl = np.stack([row_x[r], rng.uniform(-10, 10, k), rng.uniform(0, 250, k), np.ones(k)], 1)
+    units.append(("edge rows", cl.astype(np.float32), r))
+    # dense straight tracks with many exact duplicates (ties by ID), ragged size
+    b = tpcgen.one_sector(seed=7, sigma=0.0)
+    cl, row, _, _, _ = b.unit(0)
+    dup = rng.choice(cl.shape[0], 777, replace=False)
+    cl = np.concatenate([cl, cl[dup]])
+    row = np.concatenate([row, row[dup]])
+    units.append(("duplicates", cl, row))
+    # a sector of a time frame: z' spans tens of metres
+    tf = tpcgen.timeframe(seed=3, n_events=12)
+    cl, row, _, _, _ = tf.unit(4)
+    units.append(("timeframe sector", cl, row))
+    return units
+
+
+def test_edge_cases(tpcca, row_x):
+    units = _edge_units(row_x)
+    with tpcca.Context(row_x) as ctx:
+        for k, (name, cl, row) in enumerate(units):
+            ctx.load_sector(0, k, cl, row)
+        ctx.run_all(0, -1)
+        ctx.sync()
+        for k, (name, cl, row) in enumerate(units):
+            print(f"edge case {name}: {cl.shape[0]} clusters", flush=True)
+            ref = oracle.run_sector(cl, row, row_x)
+            _parity.compare_unit_stagewise(ctx, 0, k, cl, row, ref)
+
+
+def test_invalid_clusters_are_reported(tpcca, row_x):
+    b = tpcgen.one_sector(seed=1)
+    cl, row, _, _, _ = b.unit(0)
+    row = row.copy()
+    row[17] = 200  # beyond the last pad row
+    with tpcca.Context(row_x) as ctx:
+        ctx.load_sector(0, 0, cl, row)
+        ctx.run_all(0, 0)
+        with pytest.raises(tpcca.TpccaError) as ei:
+            ctx.sync()
+        assert ei.value.status == tpcca.EINVAL
+    cl2 = cl.copy()
+    cl2[3, 0] += 1.0  # x off its row
+    with tpcca.Context(row_x) as ctx:
+        ctx.load_sector(0, 0, cl2, b.unit(0)[1])
+        ctx.run_all(0, 0)
+        with pytest.raises(tpcca.TpccaError):
+            ctx.sync()
+
+
+def test_stage_order_and_arguments(tpcca, row_x):
+    b = tpcgen.one_sector(seed=1)
+    cl, row, _, _, _ = b.unit(0)
+    with tpcca.Context(row_x) as ctx:
+        with pytest.raises(tpcca.TpccaError) as ei:
+            ctx.clean_links(0, 0)
+        assert ei.value.status == tpcca.ESTATE
+        ctx.load_sector(0, 0, cl, row)
+        with pytest.raises(tpcca.TpccaError):
+            ctx.load_sector(0, 0, cl, row)  # loaded twice
+        with pytest.raises(tpcca.TpccaError):
+            ctx.build_tracklets(0, 0)       # links not found yet
+        with pytest.raises(tpcca.TpccaError):
+            ctx.load_sector(0, 99, cl, row)  # no sector 99
+        ctx.find_links(0, 0)
+        with pytest.raises(tpcca.TpccaError):
+            ctx.get_links(0, 0, cl.shape[0] + 1)
+        ctx.clean_links(0, 0)
+        ctx.build_tracklets(0, 0)
+        ctx.select_tracks(0, 0)
+        ctx.sync()
+
+
+def test_fit_within_1e4_of_fp64_replay(tpcca, row_x):
+    """Every GPU tracklet parameter lies within 1e-4 relative of the FP64
+    oracle replayed along the GPU's own decisions (denominator floored at
+    10 sigma of the FP64 fit)."""
+    b = tpcgen.central_event(seed=4, n_tracks=8000, keep_truth=False)
+    checked = 0
+    with tpcca.Context(row_x) as ctx:
+        for u in (0, 13, 29):
+            cl, row, slot, sec, _ = b.unit(u)
+            ctx.load_sector(slot, sec, cl, row)
+        ctx.run_all(0, -1)
+        ctx.sync()
+        for u in (0, 13, 29):
+            cl, row, slot, sec, _ = b.unit(u)
+            gt, ghb, gh = ctx.get_tracklets(slot, sec)
+            for t in np.nonzero(gt["status"] == 0)[0]:
+                hits = gh[ghb[t]:ghb[t + 1]]
+                k0 = int(np.nonzero(hits == gt["start_id"][t])[0][0])
+                rc, R = oracle.refit(cl, row, row_x, hits, k0, int(gt["n_chain"][t]), precision=64)
+                assert rc == 0
+                sig = np.sqrt(np.diag(oracle.cov_matrix(R["cov"])))
+                tol = 1e-4 * np.maximum(np.abs(R["p"]), 10 * sig)
+                assert np.all(np.abs(gt["p"][t].astype(np.float64) - R["p"]) <= tol), (t, gt["p"][t], R["p"])
+                checked += 1
+    assert checked > 1500
