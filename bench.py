@@ -1,0 +1,219 @@
+"""Benchmark of the gfx950 TPC sector tracker (one MI355X).
+
+Headline value: tracked TPC clusters per second of the batched form on a
+continuous-readout time frame (128 minimum-bias Pb-Pb events, Poisson
+arrivals at 50 kHz, z shifted by the drift velocity, clusters mixed per
+sector: about 32.5 M clusters), inputs resident in HBM, all stages replayed
+as one captured HIP graph per step.
+
+Also reported on the same JSON line:
+  per_event   - the plain path, one launch per kernel per central Pb-Pb
+                event (36 sectors, ~1.07 M clusters), and the ratio to it;
+  served      - the continuous-batching server on time frames of 8-256
+                events (log-uniform) at Poisson arrivals, host-resident
+                inputs, p50 / p99 latency (see --served-tfs);
+  stages      - per-stage HIP-event times of one instrumented pass;
+  roofline    - the neighbour-finding kernel against HBM peak, and the
+                Kalman-fit kernel timing;
+  cpu_baseline- the plain CPU oracle on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+LINK_BYTES_PER_CLUSTER = 16  # read y, z (8 B) + write up, down (8 B)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--events", type=int, default=128, help="events per time frame")
+    ap.add_argument("--served-tfs", type=int, default=48, help="time frames per served load level (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile", action="store_true", help="short run for rocprofv3")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this tracker runs on one GPU; multi-GPU runs are not part of this build "
+              "(sectors and time frames are independent: see the sharding note in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import tpcgen
+    from paper_1709_00618_amd import tpcca
+
+    tpcca.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    rx = tpcgen.row_x()
+
+    if args.profile:
+        args.steps, args.warmup, args.served_tfs = min(args.steps, 3), 1, 0
+        args.no_cpu_baseline = True
+
+    # ------------------------------------------------------------ inputs
+    t = time.time()
+    tf = tpcgen.timeframe(seed=0, n_events=args.events)
+    log(f"time frame: {tf.n_clusters} clusters in {tf.units.shape[0]} sector units "
+        f"({time.time() - t:.1f} s to generate)")
+    dcl = torch.from_numpy(tf.cl).cuda()
+    drow = torch.from_numpy(tf.row).cuda()
+    ev = tpcgen.central_event(seed=0, keep_truth=False)
+    ecl = torch.from_numpy(ev.cl).cuda()
+    erow = torch.from_numpy(ev.row).cuda()
+    torch.cuda.synchronize()
+
+    # ------------------------------------------------- batched (headline)
+    ctx = tpcca.Context(rx, device=0)
+    for _ in range(args.warmup):
+        ctx.run_batch(dcl, drow, tf.units, device=True, graph=True)
+        ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.run_batch(dcl, drow, tf.units, device=True, graph=True)
+        ctx.sync()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    nu, ncl, ntr, nhits = ctx.batch_totals()
+    batched = ncl / dt
+    log(f"batched time frame: {dt * 1e3:.2f} ms/step, {batched / 1e9:.3f} G clusters/s, "
+        f"{ntr} tracks, {nhits} assigned clusters")
+
+    # ------------------------------------- instrumented pass: stage times
+    ctx.set_timing(True)
+    stage_runs = []
+    for _ in range(max(3, args.steps // 2)):
+        ctx.run_batch(dcl, drow, tf.units, device=True, graph=False)
+        ctx.sync()
+        stage_runs.append(ctx.stage_times())
+    ctx.set_timing(False)
+    stages = {k: float(np.mean([s[k] for s in stage_runs])) for k in stage_runs[0]}
+    log("stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
+
+    # --------------------------------------------- per-event plain path
+    pe = tpcca.Context(rx, device=0)
+
+    def per_event_step():
+        pe.reset()
+        for u in range(ev.units.shape[0]):
+            b, n, slot, sec = (int(v) for v in ev.units[u])
+            pe.load_sector(slot, sec, ecl[b:b + n], erow[b:b + n], device=True)
+        pe.run_all(0, -1)
+        pe.sync()
+
+    for _ in range(args.warmup):
+        per_event_step()
+    pe_steps = max(args.steps, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(pe_steps):
+        per_event_step()
+    torch.cuda.synchronize()
+    pe_dt = (time.perf_counter() - t0) / pe_steps
+    per_event = ev.n_clusters / pe_dt
+    log(f"per-event plain: {pe_dt * 1e3:.2f} ms/event, {per_event / 1e9:.3f} G clusters/s")
+    pe.close()
+
+    # ------------------------------------------------------------ served
+    served = None
+    if args.served_tfs > 0:
+        from paper_1709_00618_amd import serving
+        served = serving.bench_served(rx, n_tf=args.served_tfs, log=log)
+
+    ctx.close()
+
+    # ---------------------------------------------------------- roofline
+    link_ms = stages["links"]
+    link_bytes = LINK_BYTES_PER_CLUSTER * ncl
+    link_gbs = link_bytes / (link_ms * 1e-3) / 1e9
+    roofline = {"kernel": "k_links (CA neighbour finding)", "bound": "hbm", "achieved": round(link_gbs, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(link_gbs / HBM_PEAK_GBS, 4),
+                "traffic": None, "bytes_per_cluster": LINK_BYTES_PER_CLUSTER, "ms": round(link_ms, 4)}
+
+    # ------------------------------------------------------ cpu baseline
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(ev, rx, args.cpu_seconds)
+
+    out = {
+        "metric": "tracked TPC clusters/s on 1 MI355X (batched time frame; served and per-event beside)",
+        "value": round(batched, 1),
+        "unit": "clusters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded helices, tpcgen)",
+        "config": {"workload": f"continuous-readout time frame: {args.events} min-bias Pb-Pb events at 50 kHz, "
+                               f"36 sector units, {ncl} clusters, device-resident, graph replay",
+                   "clusters": ncl, "units": nu, "tracks": ntr, "assigned_clusters": nhits},
+        "tracks_per_s": round(ntr / dt, 1),
+        "per_event": {"workload": f"central Pb-Pb event, 8000 tracks, {ev.n_clusters} clusters, one launch per "
+                                  "kernel per event, device-resident",
+                      "value": round(per_event, 1), "unit": "clusters/s", "ms_per_event": round(pe_dt * 1e3, 4)},
+        "batched_over_per_event": round(batched / per_event, 3),
+        "served": served,
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(ev, rx, seconds):
+    """The plain oracle, as it stands, over the sectors of the central event
+    on a thread pool of the host's cores until `seconds` of wall time."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    cores = max(1, min(16, os.cpu_count() or 1))
+    units = list(range(ev.units.shape[0]))
+    done_cl = 0
+    t0 = time.perf_counter()
+    rounds = 0
+    with ThreadPoolExecutor(cores) as ex:
+        while True:
+            def run(u):
+                cl, row, _, _, _ = ev.unit(u)
+                oracle.run_sector(cl, row, rx, precision=32)
+                return cl.shape[0]
+            done_cl += sum(ex.map(run, units))
+            rounds += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+    dt = time.perf_counter() - t0
+    return {"value": round(done_cl / dt, 1), "unit": "clusters/s", "cores": cores, "kind": "oracle",
+            "sample": f"{rounds} pass(es) over the 36 sectors of one central Pb-Pb event "
+                      f"({ev.n_clusters} clusters), FP32 oracle, one sector per thread, {dt:.1f} s wall"}
+
+
+if __name__ == "__main__":
+    main()

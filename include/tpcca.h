@@ -222,9 +222,11 @@ int tpcca_device_results(tpcca_ctx_t *ctx, tpcca_device_results_t *out);
 const char *tpcca_error_string(int status);
 const char *tpcca_last_error(tpcca_ctx_t *ctx);
 
-/* Stage timing of the last run_batch / stage sequence on ctx's stream, via
-   HIP events (ms): index 0 grid, 1 links, 2 clean, 3 tracklets(chains+fit),
-   4 selection.  Returns the number of entries written. */
+/* Stage timing of the last full stage sequence on ctx's stream, via HIP
+   events (ms): 0 grid, 1 links (the neighbour kernel alone), 2 clean,
+   3 chains (compaction), 4 Kalman fit (the fit kernel alone), 5 selection.
+   Graph replays record only the whole graph (entry 0).  Returns the number
+   of entries written (0 if timing was off). */
 int tpcca_stage_times(tpcca_ctx_t *ctx, float *ms, int32_t cap);
 /* Enable/disable per-stage event recording (off by default). */
 int tpcca_set_timing(tpcca_ctx_t *ctx, int32_t enable);

@@ -18,8 +18,9 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 hipError_t launch_grid(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s);
 hipError_t launch_links(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s);
 hipError_t launch_clean(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s);
-hipError_t launch_tracklets(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
-                            hipStream_t s);
+hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
+                         hipStream_t s);
+hipError_t launch_kf(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s);
 hipError_t launch_select(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s);
 hipError_t launch_links_by_id(const Bufs &B, const int32_t *up, const int32_t *dn, int32_t *out_up,
                               int32_t *out_dn, int32_t cl_begin, int32_t n, hipStream_t s);

@@ -1112,8 +1112,8 @@ hipError_t launch_clean(const Bufs &B, const ParamsDev &P, int run, const RunHos
   return hipGetLastError();
 }
 
-hipError_t launch_tracklets(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
-                            hipStream_t s) {
+hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
+                         hipStream_t s) {
   const int nch = h.c1 - h.c0, nu = h.u1 - h.u0;
   if (nch > 0) {
     k_chain<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, P, run);
@@ -1122,6 +1122,10 @@ hipError_t launch_tracklets(const Bufs &B, const ParamsDev &P, int run, const Ru
     k_flag_apply<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
   }
   if (nu > 0) k_empty_units<<<grid_for(nu, 64, 1024), 64, 0, s>>>(B, run);
+  return hipGetLastError();
+}
+
+hipError_t launch_kf(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s) {
   if (h.trk_cap > 0) k_kf<<<grid_for(h.trk_cap, kKfBlock, 4096), kKfBlock, 0, s>>>(B, P, run);
   return hipGetLastError();
 }

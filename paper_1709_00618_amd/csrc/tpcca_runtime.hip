@@ -71,8 +71,8 @@ struct tpcca_ctx {
   int gen_captured = -1;
 
   bool timing = false;
-  hipEvent_t ev[6] = {};
-  float stage_ms[5] = {};
+  hipEvent_t ev[7] = {};
+  float stage_ms[6] = {};
   bool have_times = false;
 
   std::string last_error;
@@ -299,12 +299,14 @@ static int launch_stages(tpcca_ctx *c, int run, const RunHost &h, int first, int
         record_event(c, 3);
         break;
       case 3:
-        e = launch_tracklets(c->B, c->P, run, h, s);
+        e = launch_chains(c->B, c->P, run, h, s);
         record_event(c, 4);
+        if (e == hipSuccess) e = launch_kf(c->B, c->P, run, h, s);
+        record_event(c, 5);
         break;
       case 4:
         e = launch_select(c->B, c->P, run, h, s);
-        record_event(c, 5);
+        record_event(c, 6);
         break;
     }
   }
@@ -374,7 +376,7 @@ static int check_errors(tpcca_ctx *c) {
   }
   c->pending_runs.clear();
   if (c->timing && c->have_times) {
-    for (int k = 0; k < 5; ++k) hipEventElapsedTime(&c->stage_ms[k], c->ev[k], c->ev[k + 1]);
+    for (int k = 0; k < 6; ++k) hipEventElapsedTime(&c->stage_ms[k], c->ev[k], c->ev[k + 1]);
   }
   return rc;
 }
@@ -540,7 +542,7 @@ int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int 
     }
     c->own_stream = true;
   }
-  for (int k = 0; k < 6; ++k) hipEventCreate(&c->ev[k]);
+  for (int k = 0; k < 7; ++k) hipEventCreate(&c->ev[k]);
   c->unit_chunk0.push_back(0);
   int rc = ensure(c, c->row_x_d, sizeof(float) * c->R, 0);
   if (rc == TPCCA_OK) {
@@ -568,7 +570,7 @@ int tpcca_destroy(tpcca_ctx_t *c) {
                    &c->assign, &c->unit_res, &c->scan_tmp, &c->in_cl, &c->in_row};
   for (DevBuf *b : all)
     if (b->p) hipFree(b->p);
-  for (int k = 0; k < 6; ++k)
+  for (int k = 0; k < 7; ++k)
     if (c->ev[k]) hipEventDestroy(c->ev[k]);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
@@ -813,7 +815,18 @@ int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
     capT = bucket(capT);
     capC = bucket(capC);
   }
-  if ((rc = ensure_work(c, capN, capU, capB, capT, capC)) != TPCCA_OK) return rc;
+  rc = ensure_work(c, capN, capU, capB, capT, capC);
+  if (rc == TPCCA_ENOMEM && graph) {
+    // the rounded-up capacities do not fit the budget: use the exact ones
+    // (the graph is then re-captured whenever the sizes change)
+    capN = c->n_total;
+    capU = U;
+    capB = c->bins_total;
+    capT = c->trk_total;
+    capC = (int64_t)c->chunks.size();
+    rc = ensure_work(c, capN, capU, capB, capT, capC);
+  }
+  if (rc != TPCCA_OK) return rc;
   if ((rc = upload_tables(c)) != TPCCA_OK) return rc;
   c->runs.push_back(make_run(c, 0, U));
   if ((rc = write_run(c, 0)) != TPCCA_OK) return rc;
@@ -855,7 +868,7 @@ int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
   record_event(c, 0);
   HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
   if (c->timing) {
-    for (int k = 1; k <= 5; ++k) hipEventRecord(c->ev[k], c->stream);
+    for (int k = 1; k <= 6; ++k) hipEventRecord(c->ev[k], c->stream);
   }
   return TPCCA_OK;
 }
@@ -948,7 +961,7 @@ int tpcca_set_timing(tpcca_ctx_t *c, int32_t enable) {
 int tpcca_stage_times(tpcca_ctx_t *c, float *ms, int32_t cap) {
   if (!c || !ms) return TPCCA_EINVAL;
   if (!c->have_times) return 0;
-  int n = std::min(cap, 5);
+  int n = std::min(cap, 6);
   for (int k = 0; k < n; ++k) ms[k] = c->stage_ms[k];
   return n;
 }

@@ -333,10 +333,12 @@ class Context:
     def set_timing(self, on=True):
         lib().tpcca_set_timing(self.h, 1 if on else 0)
 
+    STAGES = ("grid", "links", "clean", "chains", "fit", "select")
+
     def stage_times(self):
-        ms = np.zeros(5, np.float32)
-        n = lib().tpcca_stage_times(self.h, _p(ms), 5)
-        return ms[:n]
+        ms = np.zeros(6, np.float32)
+        n = lib().tpcca_stage_times(self.h, _p(ms), 6)
+        return dict(zip(self.STAGES, ms[:n].tolist()))
 
 
 def now() -> float:

@@ -1,0 +1,129 @@
+"""The continuous-batching server: each time frame's result is the same
+alone and in a mix of concurrent frames, and equals the batch path and the
+oracle; admission errors are reported at submit."""
+import numpy as np
+import pytest
+
+import tpcgen
+from tests import _parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_00618_amd import serving, tpcca
+    tpcca.lib()
+    return tpcca, serving
+
+
+@pytest.fixture(scope="module")
+def frames():
+    pool = tpcgen.minbias_pool(seed=3, n=12)
+    out = []
+    for i, k in enumerate((8, 13, 21)):
+        out.append(tpcgen.timeframe(seed=3, n_events=k, tf_index=i, event_pool=pool, stream=tpcgen.STREAM_SERVED))
+    return out
+
+
+def _results(serving, srv, tfs, pinned):
+    fr = [serving.Frame(t.cl, t.row, t.units, pinned=pinned) for t in tfs]
+    outs = [serving.Outputs(f.n_clusters, f.n_units) for f in fr]
+    rids = [srv.submit(f, o) for f, o in zip(fr, outs)]
+    res = []
+    for rid, f, o in zip(rids, fr, outs):
+        r = srv.wait(rid, 300)
+        assert r.status == 0 and r.done == 1
+        assert r.end_s >= r.start_s >= r.arrival_s - 1e-3
+        res.append([(a.copy(), b.copy(), c.copy()) for a, b, c in serving.unit_results(f, o)])
+        srv.release(rid)
+    return res
+
+
+def test_alone_equals_mix_equals_batch(mods, frames, row_x):
+    tpcca, serving = mods
+    with serving.Server(row_x, n_streams=2, budget_bytes=8 << 30) as srv:
+        alone = [_results(serving, srv, [t], pinned=True)[0] for t in frames]
+        print("alone done", flush=True)
+        mix_tfs = [frames[0], frames[1], frames[2], frames[0], frames[1]]
+        mix = _results(serving, srv, mix_tfs, pinned=False)
+        st = srv.stats()
+        assert st.completed == 3 + 5 and st.batches_run >= 2
+    for k, m in zip((0, 1, 2, 0, 1), mix):
+        for (ta, ha, aa), (tm, hm, am) in zip(alone[k], m):
+            assert ta.tobytes() == tm.tobytes()
+            assert np.array_equal(ha, hm) and np.array_equal(aa, am)
+    # the batch path gives the same per-unit results
+    with tpcca.Context(row_x) as ctx:
+        for k, t in enumerate(frames):
+            ctx.run_batch(t.cl, t.row, t.units, graph=True)
+            units, tracks, hits, asg = ctx.get_batch_results()
+            for u in range(t.units.shape[0]):
+                ur = units[u]
+                t0, nt = int(ur["track_begin"]), int(ur["n_tracks"])
+                h0, nh = int(ur["hit_begin"]), int(ur["n_track_hits"])
+                c0, n = int(ur["cluster_begin"]), int(t.units[u, 1])
+                assert alone[k][u][0].tobytes() == tracks[t0:t0 + nt].tobytes()
+                assert np.array_equal(alone[k][u][1], hits[h0:h0 + nh])
+                assert np.array_equal(alone[k][u][2], asg[c0:c0 + n])
+    # and the oracle, on a few sectors of the largest frame
+    t = frames[2]
+    refs = _parity.oracle_units(t, row_x, which={0, 17, 35})
+    for u in (0, 17, 35):
+        tr, h, a = alone[2][u]
+        _parity.compare_tracks(tr, h, refs[u])
+        assert np.array_equal(a, refs[u].assignment)
+
+
+def test_admission_errors(mods, frames, row_x):
+    tpcca, serving = mods
+    t = frames[0]
+    with serving.Server(row_x, n_streams=1, budget_bytes=1 << 20) as srv:
+        f = serving.Frame(t.cl, t.row, t.units)
+        o = serving.Outputs(f.n_clusters, f.n_units)
+        with pytest.raises(tpcca.TpccaError) as ei:
+            srv.submit(f, o)  # one sector alone exceeds a 1 MiB lane
+        assert ei.value.status == tpcca.ENOMEM
+    with serving.Server(row_x, n_streams=1, budget_bytes=4 << 30) as srv:
+        units = t.units.copy()
+        units[0, 3] = 77
+        f = serving.Frame(t.cl, t.row, units)
+        with pytest.raises(tpcca.TpccaError) as ei:
+            srv.submit(f, serving.Outputs(f.n_clusters, f.n_units))
+        assert ei.value.status == tpcca.EINVAL
+        # an empty frame completes at once
+        f = serving.Frame(np.zeros((0, 4), np.float32), np.zeros(0, np.uint8), np.zeros((0, 4), np.int64))
+        rid = srv.submit(f, serving.Outputs(1, 1))
+        assert srv.wait(rid, 10).done == 1
+
+
+def test_large_frame_sliced_across_lane_batches(mods, row_x):
+    """A frame larger than a lane's share is split by sector over several
+    batches and lanes; the result equals one batch of the whole frame."""
+    tpcca, serving = mods
+    tf = tpcgen.timeframe(seed=8, n_events=40)
+    print(f"large frame: {tf.n_clusters} clusters", flush=True)
+    # 2 lanes of 1.5 GiB: about 2M clusters per lane batch
+    with serving.Server(row_x, n_streams=2, budget_bytes=3 << 30) as srv:
+        f = serving.Frame(tf.cl, tf.row, tf.units, pinned=True)
+        o = serving.Outputs(f.n_clusters, f.n_units)
+        rid = srv.submit(f, o)
+        r = srv.wait(rid, 300)
+        assert r.status == 0 and r.done == 1
+        st = srv.stats()
+        assert st.batches_run >= 3
+        got = serving.unit_results(f, o)
+    with tpcca.Context(row_x) as ctx:
+        ctx.run_batch(tf.cl, tf.row, tf.units, graph=True)
+        units, tracks, hits, asg = ctx.get_batch_results()
+    for u in range(tf.units.shape[0]):
+        ur = units[u]
+        t0, nt = int(ur["track_begin"]), int(ur["n_tracks"])
+        h0, nh = int(ur["hit_begin"]), int(ur["n_track_hits"])
+        c0, n = int(ur["cluster_begin"]), int(tf.units[u, 1])
+        assert got[u][0].tobytes() == tracks[t0:t0 + nt].tobytes()
+        assert np.array_equal(got[u][1], hits[h0:h0 + nh])
+        assert np.array_equal(got[u][2], asg[c0:c0 + n])
