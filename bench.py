@@ -72,6 +72,17 @@ def main():
     if args.profile:
         args.steps, args.warmup, args.served_tfs = min(args.steps, 3), 1, 0
         args.no_cpu_baseline = True
+        # a plain device copy of known size: the reference that scales the
+        # FETCH_SIZE / WRITE_SIZE counters of the profiled kernels
+        src = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {src.numel() * 4} bytes")
+        del src, dst
 
     # ------------------------------------------------------------ inputs
     t = time.time()
@@ -98,9 +109,10 @@ def main():
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     nu, ncl, ntr, nhits = ctx.batch_totals()
+    work = ctx.work_stats()
     batched = ncl / dt
     log(f"batched time frame: {dt * 1e3:.2f} ms/step, {batched / 1e9:.3f} G clusters/s, "
-        f"{ntr} tracks, {nhits} assigned clusters")
+        f"{ntr} tracks, {nhits} assigned clusters; work {work}")
 
     # ------------------------------------- instrumented pass: stage times
     ctx.set_timing(True)

@@ -83,7 +83,7 @@ typedef struct {
   int32_t min_track_hits;  /* minimum hits of a tracklet and won hits of a track (10) */
   int32_t own_frac_pct;    /* a track must win this percentage of its hits (90) */
   float refit_inflate;     /* pass-2 restart: pass-1 covariance x this (100); 0 = hard */
-  int32_t grid_hits_per_bin; /* z-bin occupancy target of the row grid (tuning only) */
+  int32_t grid_hits_per_bin; /* z-bin occupancy target of the row grid (1; tuning only) */
 } tpcca_params_t;
 
 /* An accepted track (FP32).  Parameters at plane x_ref (the innermost hit's
@@ -215,6 +215,15 @@ int tpcca_get_batch_results(tpcca_ctx_t *ctx, tpcca_unit_result_t *units, tpcca_
                             int32_t *assignment, int64_t n_clusters);
 int tpcca_batch_totals(tpcca_ctx_t *ctx, int32_t *n_units, int64_t *n_clusters, int64_t *n_tracks,
                        int64_t *n_hits);
+/* Work counters of everything processed since the last reset (synchronises):
+   clusters, tracklets (fitted candidates), accepted tracks and their hits,
+   Kalman row steps (propagations) and candidate clusters examined by the
+   track-following searches. */
+typedef struct {
+  int64_t clusters, tracklets, tracks, track_hits, fit_steps, fit_candidates;
+} tpcca_work_stats_t;
+int tpcca_work_stats(tpcca_ctx_t *ctx, tpcca_work_stats_t *out);
+
 /* Device pointers to the batch results (no copy; synchronises). */
 int tpcca_device_results(tpcca_ctx_t *ctx, tpcca_device_results_t *out);
 

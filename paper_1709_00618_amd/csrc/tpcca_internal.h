@@ -24,8 +24,10 @@ struct UnitDev {
   int32_t n;
   int32_t trk_base;      // first tracklet slot reserved for the unit
   int32_t slot, sector;
-  int32_t pad_;
+  int32_t tile_base;     // first row tile slot reserved for the unit
 };
+
+constexpr int kTile = 256;  // hits of one row per neighbour-finding tile
 
 // A chunk of <= kChunk consecutive clusters of one unit.
 struct Chunk {
@@ -56,12 +58,16 @@ struct RunDev {
   int64_t bin0, bin1;   // bin-begin entries [bin0, bin1)
   int32_t trk0;         // first tracklet slot of the run
   int32_t trk_cap;      // tracklet slots reserved for the run
+  int32_t tile0, tile1; // row tile slots [tile0, tile1)
   // device-written
   int32_t n_trk;
   int32_t n_acc;
   int64_t n_acc_hits;
   int32_t err;          // 1: invalid cluster seen
-  int32_t pad_;
+  int32_t kf_next;      // work counter of the fit kernel
+  int32_t n_starts;     // chain start hits found by the cleaning kernel
+  unsigned long long kf_steps;   // row steps of the fit (propagations)
+  unsigned long long kf_cands;   // candidate hits examined by the fit's searches
 };
 
 // Device-side parameters (FP32 copies of tpcca_params_t).
@@ -88,9 +94,17 @@ struct Bufs {
   int32_t *binbeg;       // bins
   float2 *yz;            // sorted hits
   int32_t *sid;          // sorted -> unit-local cluster ID
+  uint8_t *srow;         // sorted -> pad row
+  int2 *cinfo;           // sorted start hit -> (last hit, chain length)
   int32_t *up, *dn;      // raw links (sorted indices)
   int32_t *upc, *dnc;    // cleaned links
   int32_t *flag;         // by global cluster index: start sorted index + 1, or 0
+  int2 *starts;          // chain start hits: (sorted index, flag index), per chunk region
+  int32_t *chunk_nstart; // start hits found in each chunk
+  int4 *tiles;           // (unit, row, first sorted hit, count) row tiles
+  uint8_t *sval;         // sorted: 1 if the hit starts a tracklet
+  int32_t *tofg;         // sorted start hit -> tracklet
+  int32_t *kf_order;     // processing rank -> tracklet (grid order of start hits)
   int32_t *trk_start;    // tracklet -> sorted index of its start hit
   int32_t *trk_unit;     // tracklet -> unit
   int32_t *unit_tbegin;  // unit -> first tracklet
@@ -98,6 +112,7 @@ struct Bufs {
   int32_t *trk_hits;     // tracklet x n_rows sorted indices
   unsigned long long *owner;  // by sorted index
   unsigned long long *accv;   // by tracklet: accepted << 40 | won hits
+  unsigned long long *wonmask;  // by tracklet: 4 x 64 bits, slot k won its hit
   unsigned long long *accx;   // exclusive scan of accv (+ total)
   tpcca_track_t *tracks;      // by tracklet slot of the run (compacted)
   int32_t *hits_out;          // by global cluster index (compacted per run)

@@ -11,6 +11,7 @@ struct RunHost {
   int32_t u0, u1, c0, c1, cl0, cl1;
   int64_t bin0, bin1;
   int32_t trk0, trk_cap;
+  int32_t tile0, tile1;
 };
 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);

@@ -22,6 +22,8 @@
 #include "tpcca_internal.h"
 #include "tpcca_kernels.h"
 
+#include <algorithm>
+
 namespace tpcca {
 
 // ------------------------------------------------------------- helpers ---
@@ -120,6 +122,10 @@ __global__ void k_run_reset(Bufs B, int run, int R) {
     rd.n_acc = 0;
     rd.n_acc_hits = 0;
     rd.err = 0;
+    rd.kf_next = 0;
+    rd.n_starts = 0;
+    rd.kf_steps = 0;
+    rd.kf_cands = 0;
   }
 }
 
@@ -212,6 +218,16 @@ __global__ __launch_bounds__(kBlock) void k_plan(Bufs B, int run, int R, int hit
       t.inv = (float)nb / span;
       B.rowtab[(int64_t)u * (R + 1) + r] = t;
     }
+    // row tiles of at most kTile hits for the neighbour search; the unused
+    // slots of the unit's reservation are marked empty
+    const int nt = r <= R ? (cnt + kTile - 1) / kTile : 0;
+    int32_t ttot;
+    const int32_t toff = block_exclusive_scan<int32_t>(nt, lds32, &ttot);
+    for (int i = 0; i < nt; ++i)
+      B.tiles[U.tile_base + toff + i] =
+          make_int4(u, r, U.cl_begin + begin + i * kTile, min(kTile, cnt - i * kTile));
+    const int cap = U.n / kTile + R + 2;
+    for (int i = ttot + r; i < cap; i += blockDim.x) B.tiles[U.tile_base + i] = make_int4(u, 0, 0, 0);
     __syncthreads();
   }
 }
@@ -253,6 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Bufs B, int run, int R) {
       const int pos = B.binbeg[g] + k;
       B.yz[pos] = make_float2(c4.y, c4.z);
       B.sid[pos] = li;
+      B.srow[pos] = (uint8_t)r;
     }
   }
 }
@@ -272,100 +289,231 @@ __device__ __forceinline__ int row_of(const RowTab *t, int R, int g) {
 // Fig. 1a: for every hit of rows 1..R-2 the pair (u in row+1, d in row-1)
 // inside |dy|, |dz| <= W dx that minimises (chi2, id_u, id_d), where chi2 is
 // the squared deviation of the hit from the line d -> u at the hit's row.
-__global__ __launch_bounds__(kBlock) void k_links(Bufs B, ParamsDev P, int run) {
-  __shared__ RowTab srt[kMaxRows + 1];
+//
+// One block per row tile (<= kTile hits of one row, contiguous in z-bin
+// order).  The z bins of rows r-1 and r+1 that any hit of the tile can reach
+// are a contiguous range of sorted hits; they are staged in LDS with their
+// bin offsets, so every candidate test reads LDS.  Tiles whose neighbour
+// ranges exceed the LDS capacity read the candidates from global memory.
+// Tiles are walked XCD by XCD so that neighbouring rows of a unit share an
+// L2.
+constexpr int kNbrCap = 1536;   // staged hits per neighbour row
+constexpr int kBinCap = 1024;   // staged bin offsets per neighbour row
+
+// Candidates inside the window are first collected per side (up to kKeep
+// each, in LDS), then paired: the pair loop runs over the short lists, so
+// lanes with different candidate counts do not multiply their trip counts.
+// A side with more than kKeep window hits falls back to the full double loop.
+constexpr int kKeep = 8;
+
+template <bool kLds>
+__device__ __forceinline__ float2 cand(const Bufs &B, const float2 *src, int i, int off) {
+  return kLds ? src[i - off] : B.yz[i];
+}
+
+template <bool kLds>
+__device__ __forceinline__ void link_hit(const Bufs &B, const ParamsDev &P, float2 h, float luy,
+                                         float luz, float ldy, float ldz, float w, int ub, int ue,
+                                         int db, int de, const float2 *cu_src, const float2 *cd_src,
+                                         int u_off, int d_off, int *keep_u, int *keep_d, int &bu,
+                                         int &bd) {
+  float best = __builtin_inff();
+  bu = -1;
+  bd = -1;
+  int nu = 0, nd = 0;
+  for (int u = ub; u < ue; ++u) {
+    const float2 cu = cand<kLds>(B, cu_src, u, u_off);
+    if (fabsf(cu.x - h.x) <= luy && fabsf(cu.y - h.y) <= luz) {
+      if (nu < kKeep) keep_u[nu * kTile] = u;
+      ++nu;
+    }
+  }
+  if (nu > 0) {
+    for (int d = db; d < de; ++d) {
+      const float2 cd = cand<kLds>(B, cd_src, d, d_off);
+      if (fabsf(cd.x - h.x) <= ldy && fabsf(cd.y - h.y) <= ldz) {
+        if (nd < kKeep) keep_d[nd * kTile] = d;
+        ++nd;
+      }
+    }
+  }
+  const bool full = nu > kKeep || nd > kKeep;
+  const int mu = full ? ue - ub : nu, md = full ? de - db : nd;
+  for (int a = 0; a < mu && nd > 0; ++a) {
+    const int u = full ? ub + a : keep_u[a * kTile];
+    const float2 cu = cand<kLds>(B, cu_src, u, u_off);
+    if (full && !(fabsf(cu.x - h.x) <= luy && fabsf(cu.y - h.y) <= luz)) continue;
+    for (int b = 0; b < md; ++b) {
+      const int d = full ? db + b : keep_d[b * kTile];
+      const float2 cd = cand<kLds>(B, cd_src, d, d_off);
+      if (full && !(fabsf(cd.x - h.x) <= ldy && fabsf(cd.y - h.y) <= ldz)) continue;
+      const float ey = h.x - __builtin_fmaf(cu.x - cd.x, w, cd.x);
+      const float ez = h.y - __builtin_fmaf(cu.y - cd.y, w, cd.y);
+      const float c2 = __builtin_fmaf(ey, ey, ez * ez);
+      bool take = c2 < best;
+      if (!take && c2 == best && bu >= 0) {
+        const int iu = B.sid[u], id = B.sid[d], ibu = B.sid[bu], ibd = B.sid[bd];
+        take = iu < ibu || (iu == ibu && id < ibd);
+      }
+      if (take) {
+        best = c2;
+        bu = u;
+        bd = d;
+      }
+    }
+  }
+  if (!(best <= P.link_chi2)) {
+    bu = -1;
+    bd = -1;
+  }
+}
+
+__global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
+  __shared__ float2 s_up[kNbrCap], s_dn[kNbrCap];
+  __shared__ int32_t s_bup[kBinCap + 1], s_bdn[kBinCap + 1];
+  __shared__ int s_red[2 * (kTile / 64)];
+  __shared__ int s_keep[2 * kKeep * kTile];
   const int R = P.n_rows;
   const RunDev &rd = B.runs[run];
-  int cur = -1;
-  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
-    const Chunk ch = B.chunks[c];
-    if (ch.unit != cur) {
-      __syncthreads();
-      for (int r = threadIdx.x; r <= R; r += blockDim.x)
-        srt[r] = B.rowtab[(int64_t)ch.unit * (R + 1) + r];
-      __syncthreads();
-      cur = ch.unit;
+  const int ntile = rd.tile1 - rd.tile0;
+  // XCD-aware walk: blocks b with b % 8 == x take the x-th eighth of tiles
+  const int nx = gridDim.x >> 3;
+  const int xcd = blockIdx.x & 7;
+  const int per = (ntile + 7) >> 3;
+  const int lo = xcd * per, hi = min(ntile, lo + per);
+  for (int it = lo + (int)(blockIdx.x >> 3); it < hi; it += nx) {
+    const int4 tile = B.tiles[rd.tile0 + it];
+    const int cnt = tile.w;
+    if (cnt == 0) continue;
+    const int u = tile.x, r = tile.y, g0 = tile.z;
+    const int i = threadIdx.x;
+    const int g = g0 + i;
+    if (r < 1 || r > R - 2) {
+      if (i < cnt) {
+        B.up[g] = -1;
+        B.dn[g] = -1;
+      }
+      continue;
     }
-    const int base = B.units[ch.unit].cl_begin + ch.begin;
-    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
-      const int g = base + i;
-      const int r = row_of(srt, R, g);
-      int bu = -1, bd = -1;
-      if (r >= 1 && r <= R - 2) {
-        const float2 h = B.yz[g];
-        const float xr = B.row_x[r];
-        const float dxu = B.row_x[r + 1] - xr;
-        const float dxd = xr - B.row_x[r - 1];
-        const float w = dxd / (dxd + dxu);
-        const float luy = P.wy * dxu, luz = P.wz * dxu, ldy = P.wy * dxd, ldz = P.wz * dxd;
-        int ub, ue, db, de;
-        bin_range(srt[r + 1], B.binbeg, h.y, luz, ub, ue);
-        bin_range(srt[r - 1], B.binbeg, h.y, ldz, db, de);
-        float best = __builtin_inff();
-        for (int u = ub; u < ue; ++u) {
-          const float2 cu = B.yz[u];
-          if (!(fabsf(cu.x - h.x) <= luy && fabsf(cu.y - h.y) <= luz)) continue;
-          for (int d = db; d < de; ++d) {
-            const float2 cd = B.yz[d];
-            if (!(fabsf(cd.x - h.x) <= ldy && fabsf(cd.y - h.y) <= ldz)) continue;
-            const float ey = h.x - __builtin_fmaf(cu.x - cd.x, w, cd.x);
-            const float ez = h.y - __builtin_fmaf(cu.y - cd.y, w, cd.y);
-            const float c2 = __builtin_fmaf(ey, ey, ez * ez);
-            bool take = c2 < best;
-            if (!take && c2 == best && bu >= 0) {
-              const int iu = B.sid[u], id = B.sid[d], ibu = B.sid[bu], ibd = B.sid[bd];
-              take = iu < ibu || (iu == ibu && id < ibd);
-            }
-            if (take) {
-              best = c2;
-              bu = u;
-              bd = d;
-            }
-          }
-        }
-        if (!(best <= P.link_chi2)) {
-          bu = -1;
-          bd = -1;
-        }
+    const RowTab *rtu = B.rowtab + (int64_t)u * (R + 1);
+    const RowTab tu = rtu[r + 1], td = rtu[r - 1];
+    const float xr = B.row_x[r];
+    const float dxu = B.row_x[r + 1] - xr;
+    const float dxd = xr - B.row_x[r - 1];
+    const float w = dxd / (dxd + dxu);
+    const float luy = P.wy * dxu, luz = P.wz * dxu, ldy = P.wy * dxd, ldz = P.wz * dxd;
+    float2 h = make_float2(0.0f, 0.0f);
+    int zmin = 0x7FFFFFFF, zmax = (int)0x80000000;
+    if (i < cnt) {
+      h = B.yz[g];
+      zmin = zmax = ordered_int(h.y);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      zmin = min(zmin, __shfl_xor(zmin, o, 64));
+      zmax = max(zmax, __shfl_xor(zmax, o, 64));
+    }
+    if ((i & 63) == 0) {
+      s_red[i >> 6] = zmin;
+      s_red[(kTile / 64) + (i >> 6)] = zmax;
+    }
+    __syncthreads();
+    float zlo = from_ordered(s_red[0]), zhi = from_ordered(s_red[kTile / 64]);
+    for (int q = 1; q < kTile / 64; ++q) {
+      zlo = fminf(zlo, from_ordered(s_red[q]));
+      zhi = fmaxf(zhi, from_ordered(s_red[(kTile / 64) + q]));
+    }
+    // tile-wide bin ranges of the neighbour rows (a superset of every hit's)
+    const float tpad = 1e-3f + 1e-6f * fmaxf(fabsf(zlo), fabsf(zhi));
+    const int ublo = zbin(tu, zlo - luz - tpad), ubhi = zbin(tu, zhi + luz + tpad);
+    const int dblo = zbin(td, zlo - ldz - tpad), dbhi = zbin(td, zhi + ldz + tpad);
+    const int ua = B.binbeg[tu.bin0 + ublo], ue_ = B.binbeg[tu.bin0 + ubhi + 1];
+    const int da = B.binbeg[td.bin0 + dblo], de_ = B.binbeg[td.bin0 + dbhi + 1];
+    const bool lds = (ue_ - ua) <= kNbrCap && (de_ - da) <= kNbrCap && (ubhi - ublo + 2) <= kBinCap &&
+                     (dbhi - dblo + 2) <= kBinCap;
+    if (lds) {
+      for (int q = i; q < ue_ - ua; q += blockDim.x) s_up[q] = B.yz[ua + q];
+      for (int q = i; q < de_ - da; q += blockDim.x) s_dn[q] = B.yz[da + q];
+      for (int q = i; q <= ubhi - ublo + 1; q += blockDim.x) s_bup[q] = B.binbeg[tu.bin0 + ublo + q];
+      for (int q = i; q <= dbhi - dblo + 1; q += blockDim.x) s_bdn[q] = B.binbeg[td.bin0 + dblo + q];
+    }
+    __syncthreads();
+    if (i < cnt) {
+      const float pad = 1e-3f + 1e-6f * fabsf(h.y);
+      const int bu0 = zbin(tu, h.y - luz - pad), bu1 = zbin(tu, h.y + luz + pad);
+      const int bd0 = zbin(td, h.y - ldz - pad), bd1 = zbin(td, h.y + ldz + pad);
+      int bu, bd;
+      if (lds) {
+        const int ub = s_bup[bu0 - ublo], ue = s_bup[bu1 + 1 - ublo];
+        const int db = s_bdn[bd0 - dblo], de = s_bdn[bd1 + 1 - dblo];
+        link_hit<true>(B, P, h, luy, luz, ldy, ldz, w, ub, ue, db, de, s_up, s_dn, ua, da,
+                       s_keep + i, s_keep + kKeep * kTile + i, bu, bd);
+      } else {
+        const int ub = B.binbeg[tu.bin0 + bu0], ue = B.binbeg[tu.bin0 + bu1 + 1];
+        const int db = B.binbeg[td.bin0 + bd0], de = B.binbeg[td.bin0 + bd1 + 1];
+        link_hit<false>(B, P, h, luy, luz, ldy, ldz, w, ub, ue, db, de, nullptr, nullptr, 0, 0,
+                        s_keep + i, s_keep + kKeep * kTile + i, bu, bd);
       }
       B.up[g] = bu;
       B.dn[g] = bd;
     }
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------- clean ---
-// Fig. 1b: keep a link only if its partner links back.
+// Fig. 1b: keep a link only if its partner links back; a hit with an up
+// link and no down link starts a chain and is listed in its chunk's region
+// of the start list (an LDS counter per chunk, no global atomics).
 __global__ __launch_bounds__(kBlock) void k_clean(Bufs B, int run) {
-  const RunDev &rd = B.runs[run];
-  for (int g = rd.cl0 + blockIdx.x * blockDim.x + threadIdx.x; g < rd.cl1;
-       g += gridDim.x * blockDim.x) {
-    const int u = B.up[g], d = B.dn[g];
-    B.upc[g] = (u >= 0 && B.dn[u] == g) ? u : -1;
-    B.dnc[g] = (d >= 0 && B.up[d] == g) ? d : -1;
-  }
-}
-
-// Chains: a start hit has an up link and no down link; a chain of at least
-// min_chain hits marks its start in cluster-ID order (flag = sorted + 1).
-__global__ __launch_bounds__(kBlock) void k_chain(Bufs B, ParamsDev P, int run) {
+  __shared__ int cnt;
   const RunDev &rd = B.runs[run];
   for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
     const Chunk ch = B.chunks[c];
-    const int ub = B.units[ch.unit].cl_begin;
-    const int base = ub + ch.begin;
+    const UnitDev U = B.units[ch.unit];
+    const int base = U.cl_begin + ch.begin;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
     for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
       const int g = base + i;
-      int f = 0;
-      if (B.upc[g] >= 0 && B.dnc[g] < 0) {
-        int n = 1, k = B.upc[g];
-        for (int s = 0; k >= 0 && s < P.n_rows; ++s) {
-          ++n;
-          k = B.upc[k];
-        }
-        if (n >= P.min_chain) f = g + 1;
+      const int u = B.up[g], d = B.dn[g];
+      const int uc = (u >= 0 && B.dn[u] == g) ? u : -1;
+      const int dc = (d >= 0 && B.up[d] == g) ? d : -1;
+      B.upc[g] = uc;
+      B.dnc[g] = dc;
+      if (uc >= 0 && dc < 0) {
+        const int k = atomicAdd(&cnt, 1);
+        B.starts[base + k] = make_int2(g, U.cl_begin + B.sid[g]);
       }
-      B.flag[ub + B.sid[g]] = f;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) B.chunk_nstart[c] = cnt;
+    __syncthreads();
+  }
+}
+
+// Chains: follow the cleaned up links from every start hit; a chain of at
+// least min_chain hits marks its start in cluster-ID order (flag = sorted
+// index + 1) and records (last hit, length).  One wave per chunk.
+__global__ __launch_bounds__(64) void k_chain(Bufs B, ParamsDev P, int run) {
+  const RunDev &rd = B.runs[run];
+  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
+    const Chunk ch = B.chunks[c];
+    const int base = B.units[ch.unit].cl_begin + ch.begin;
+    const int ns = B.chunk_nstart[c];
+    for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+      const int2 st = B.starts[base + k];
+      const int g = st.x;
+      int n = 1, last = g, nx = B.upc[g];
+      for (int s = 0; nx >= 0 && s < P.n_rows; ++s) {
+        ++n;
+        last = nx;
+        nx = B.upc[nx];
+      }
+      if (n >= P.min_chain) {
+        B.flag[st.y] = g + 1;
+        B.cinfo[g] = make_int2(last, n);
+        B.sval[g] = 1;
+      }
     }
   }
 }
@@ -477,10 +625,60 @@ __global__ __launch_bounds__(kBlock) void k_flag_apply(Bufs B, int run) {
         const int t = rd.trk0 + (int32_t)ex;
         B.trk_start[t] = f[k] - 1;
         B.trk_unit[t] = ch.unit;
+        B.tofg[f[k] - 1] = t;
         ++ex;
       }
     }
     if (c == rd.c1 - 1 && threadIdx.x == 0) rd.n_trk = (int32_t)B.scan_tmp[rd.c1 - rd.c0];
+  }
+}
+
+// Processing order of the fit: tracklets ranked by the grid position
+// (unit, row, z bin) of their start hit, so that the lanes of a wave follow
+// nearby tracks and share cache lines.  Per chunk of sorted hits: count,
+// then (after the tile scan) write the ranks.
+__global__ __launch_bounds__(kBlock) void k_order_sums(Bufs B, int run) {
+  __shared__ int64_t part[kBlock / 64];
+  const RunDev &rd = B.runs[run];
+  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
+    const Chunk ch = B.chunks[c];
+    const int base = B.units[ch.unit].cl_begin + ch.begin;
+    int64_t v = 0;
+    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) v += B.sval[base + i];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t tot = 0;
+      for (int w = 0; w < kBlock / 64; ++w) tot += part[w];
+      B.scan_tmp[c - rd.c0] = tot;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_order_apply(Bufs B, int run) {
+  __shared__ int64_t lds[kBlock / 64 + 1];
+  const RunDev &rd = B.runs[run];
+  constexpr int per = kChunk / kBlock;
+  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
+    const Chunk ch = B.chunks[c];
+    const int base = B.units[ch.unit].cl_begin + ch.begin;
+    int f[per];
+    int64_t loc = 0;
+    for (int k = 0; k < per; ++k) {
+      const int i = threadIdx.x * per + k;
+      f[k] = i < ch.count ? B.sval[base + i] : 0;
+      loc += f[k];
+    }
+    int64_t tot;
+    int64_t ex = block_exclusive_scan<int64_t>(loc, lds, &tot) + B.scan_tmp[c - rd.c0];
+    for (int k = 0; k < per; ++k) {
+      if (f[k]) {
+        B.kf_order[rd.trk0 + (int32_t)ex] = B.tofg[base + threadIdx.x * per + k];
+        ++ex;
+      }
+    }
   }
 }
 
@@ -644,7 +842,7 @@ __device__ __forceinline__ bool kf_update(const ParamsDev &P, KState &s, float y
 // Nearest hit (dy^2 + dz^2, ties to the lower ID) inside the prediction
 // window of row r; -1 if none.
 __device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, const RowTab *rt,
-                                         const KState &s, int r) {
+                                         const KState &s, int r, unsigned int &cands) {
   float wy = P.nsig * sqrtf(s.C[0] + P.ery);
   float wz = P.nsig * sqrtf(s.C[2] + P.erz);
   if (wy > P.wmax) wy = P.wmax;
@@ -652,202 +850,286 @@ __device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, cons
   const RowTab t = rt[r];
   int b, e;
   bin_range(t, B.binbeg, s.p[1], wz, b, e);
-  int best = -1, bid = 0;
+  int best = -1;
   float bd2 = __builtin_inff();
+  cands += (unsigned int)(e - b);
   for (int i = b; i < e; ++i) {
     const float2 c = B.yz[i];
     if (!(fabsf(c.x - s.p[0]) <= wy && fabsf(c.y - s.p[1]) <= wz)) continue;
     const float dy = c.x - s.p[0];
     const float dz = c.y - s.p[1];
     const float d2 = __builtin_fmaf(dy, dy, dz * dz);
-    if (d2 < bd2) {
+    // equal distances (rare) are decided by the lower cluster ID
+    if (d2 < bd2 || (d2 == bd2 && B.sid[i] < B.sid[best])) {
       bd2 = d2;
       best = i;
-      bid = B.sid[i];
-    } else if (d2 == bd2) {
-      const int id = B.sid[i];
-      if (id < bid) {
-        best = i;
-        bid = id;
-      }
     }
   }
   return best;
 }
 
-// Track following with the Kalman filter (Fig. 1c), one tracklet per thread:
+// Track following with the Kalman filter (Fig. 1c), one tracklet per lane:
 // seed on the chain's first hit with the direction of its end points; pass 1
 // updates with the chain and follows outward picking the nearest window hit
 // with chi2 <= pick_chi2 (stop after max_miss empty rows); pass 2 restarts at
 // the outermost hit with the pass-1 covariance x refit_inflate, refits inward
 // through all pass-1 hits and continues below the chain start.
+//
+// The kernel is persistent and written as a per-lane state machine: every
+// loop iteration performs one row step (propagate, search or take the given
+// hit, update) of whatever phase the lane is in, and a lane whose tracklet
+// is done takes the next one from a device work counter (one atomic per
+// wave).  Lanes of a wave therefore stay busy while tracklets of very
+// different lengths and phases share it; each tracklet still sees exactly
+// the operation sequence of the sequential description above.
+enum : int { kIdle = 0, kChain = 1, kFollow = 2, kRefit = 3, kExtend = 4 };
+
+__device__ __forceinline__ void kf_fail(const Bufs &B, int t, int start_id, int n_chain) {
+  tpcca_tracklet_t o;
+  for (int k = 0; k < 15; ++k) {
+    o.cov[k] = 0.0f;
+    o.cov_out[k] = 0.0f;
+  }
+  for (int k = 0; k < 5; ++k) {
+    o.p[k] = 0.0f;
+    o.p_out[k] = 0.0f;
+  }
+  o.start_id = start_id;
+  o.n_chain = n_chain;
+  o.status = 2;
+  o.n_hits = 0;
+  o.n_pass1 = 0;
+  o.ndf = 0;
+  o.row_ref = 0;
+  o.row_out = 0;
+  o.x_ref = 0.0f;
+  o.x_out = 0.0f;
+  o.chi2 = 0.0f;
+  B.trk[t] = o;
+}
+
+__device__ __forceinline__ void kf_restart(const ParamsDev &P, KState &st) {
+  if (P.inflate > 0.0f) {
+#pragma unroll
+    for (int k = 0; k < 15; ++k) st.C[k] = st.C[k] * P.inflate;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 15; ++k) st.C[k] = 0.0f;
+    st.C[0] = P.r00;
+    st.C[2] = P.r11;
+    st.C[5] = P.c22;
+    st.C[9] = P.c33;
+    st.C[14] = P.c44;
+  }
+}
+
 __global__ __launch_bounds__(kKfBlock) void k_kf(Bufs B, ParamsDev P, int run) {
-  const RunDev &rd = B.runs[run];
+  RunDev &rd = B.runs[run];
   const int R = P.n_rows;
   const int n_trk = rd.n_trk;
-  for (int tl = blockIdx.x * blockDim.x + threadIdx.x; tl < n_trk; tl += gridDim.x * blockDim.x) {
-    const int t = rd.trk0 + tl;
-    const int g0 = B.trk_start[t];
-    const int u = B.trk_unit[t];
-    const RowTab *rt = B.rowtab + (int64_t)u * (R + 1);
-    int32_t *hl = B.trk_hits + (int64_t)t * R;
-    tpcca_tracklet_t o;
-    for (int k = 0; k < 15; ++k) {
-      o.cov[k] = 0.0f;
-      o.cov_out[k] = 0.0f;
+  const int lane = threadIdx.x & 63;
+  int phase = kIdle;
+  bool exhausted = false;
+  constexpr int kPool = 64;
+  int t = 0, start_id = 0, n_chain = 0, r0 = 0, k = 0, r = 0, miss = 0, n1 = 0, ne = 0;
+  int row_out = 0, row_ref = 0, prev = 0;
+  const RowTab *rt = nullptr;
+  int32_t *hl = nullptr;
+  KState st, aux;  // aux: pass-1 state at the outermost hit, then pass-2 output state
+  float chi2 = 0.0f;
+  unsigned int steps = 0, cands = 0;
+  int pnext = 0, pend = 0;  // wave-private pool of claimed tracklets
+  for (;;) {
+    const unsigned long long idle = __ballot(phase == kIdle);
+    if (idle && pnext == pend && !exhausted) {
+      // claim the next kPool tracklets with one atomic per wave
+      int base = 0;
+      if (lane == 0) base = atomicAdd(&rd.kf_next, kPool);
+      base = __shfl(base, 0, 64);
+      pnext = min(base, n_trk);
+      pend = min(base + kPool, n_trk);
+      if (pend >= n_trk) exhausted = true;
     }
-    for (int k = 0; k < 5; ++k) {
-      o.p[k] = 0.0f;
-      o.p_out[k] = 0.0f;
-    }
-    o.start_id = B.sid[g0];
-    o.status = 2;
-    o.n_hits = 0;
-    o.n_pass1 = 0;
-    o.ndf = 0;
-    o.row_ref = 0;
-    o.row_out = 0;
-    o.x_ref = 0.0f;
-    o.x_out = 0.0f;
-    o.chi2 = 0.0f;
-    // chain
-    int n1 = 0;
-    for (int k = g0; k >= 0 && n1 < R; k = B.upc[k]) hl[n1++] = k;
-    o.n_chain = n1;
-    const int r0 = row_of(rt, R, g0);
-    const int gL = hl[n1 - 1];
-    const int rL = r0 + n1 - 1;
-    KState st;
-    {
-      const float2 h0 = B.yz[g0], hL = B.yz[gL];
-      const float x0 = B.row_x[r0], xL = B.row_x[rL];
-      const float dxs = xL - x0;
-      const float ty = (hL.x - h0.x) / dxs;
-      const float sn = ty / sqrtf(__builtin_fmaf(ty, ty, 1.0f));
-      const float tz = (hL.y - h0.y) / dxs;
-      const float tl2 = tz * sqrtf(__builtin_fmaf(-sn, sn, 1.0f));
-      st.p[0] = h0.x;
-      st.p[1] = h0.y;
-      st.p[2] = sn;
-      st.p[3] = tl2;
-      st.p[4] = 0.0f;
+    if (idle && pnext < pend) {
+      const int take = min(__popcll(idle), pend - pnext);
+      const int rank = __popcll(idle & ((1ull << lane) - 1));
+      const int mine = pnext + rank;
+      pnext += take;
+      {
+        if (phase == kIdle) {
+          const int tl = mine;
+          if (rank < take) {
+            t = B.kf_order[rd.trk0 + tl];
+            const int g0 = B.trk_start[t];
+            const int u = B.trk_unit[t];
+            rt = B.rowtab + (int64_t)u * (R + 1);
+            hl = B.trk_hits + (int64_t)t * R;
+            const int2 ci = B.cinfo[g0];
+            const int gL = ci.x;
+            n_chain = ci.y;
+            r0 = B.srow[g0];
+            start_id = B.sid[g0];
+            const float2 h0 = B.yz[g0], hL = B.yz[gL];
+            const float x0 = B.row_x[r0], xL = B.row_x[r0 + n_chain - 1];
+            const float dxs = xL - x0;
+            const float ty = (hL.x - h0.x) / dxs;
+            const float sn = ty / sqrtf(__builtin_fmaf(ty, ty, 1.0f));
+            const float tz = (hL.y - h0.y) / dxs;
+            const float tl2 = tz * sqrtf(__builtin_fmaf(-sn, sn, 1.0f));
+            st.p[0] = h0.x;
+            st.p[1] = h0.y;
+            st.p[2] = sn;
+            st.p[3] = tl2;
+            st.p[4] = 0.0f;
 #pragma unroll
-      for (int k = 0; k < 15; ++k) st.C[k] = 0.0f;
-      st.C[0] = P.ery;
-      st.C[2] = P.erz;
-      st.C[5] = P.c22;
-      st.C[9] = P.c33;
-      st.C[14] = P.c44;
-      st.x = x0;
-    }
-    bool ok = true;
-    float c2;
-    for (int k = 1; k < n1 && ok; ++k) {
-      const float2 h = B.yz[hl[k]];
-      ok = kf_propagate(P, st, B.row_x[r0 + k]) && kf_update(P, st, h.x, h.y, c2);
-    }
-    if (ok) {
-      KState saved = st;
-      int row_out = rL;
-      int miss = 0;
-      for (int r = rL + 1; r < R; ++r) {
-        if (!kf_propagate(P, st, B.row_x[r])) break;
-        const int h = kf_search(B, P, rt, st, r);
-        bool took = false;
-        if (h >= 0) {
-          const float2 c = B.yz[h];
-          float cc2;
-          if (kf_chi2(P, st, c.x, c.y, cc2) && cc2 <= P.pick_chi2 &&
-              kf_update(P, st, c.x, c.y, c2)) {
-            hl[n1++] = h;
-            saved = st;
-            row_out = r;
-            took = true;
+            for (int q = 0; q < 15; ++q) st.C[q] = 0.0f;
+            st.C[0] = P.ery;
+            st.C[2] = P.erz;
+            st.C[5] = P.c22;
+            st.C[9] = P.c33;
+            st.C[14] = P.c44;
+            st.x = x0;
+            hl[0] = g0;
+            prev = g0;
+            k = 1;
+            chi2 = 0.0f;
+            phase = kChain;
           }
         }
-        if (took) {
+      }
+    }
+    if (!__any(phase != kIdle) && exhausted && pnext == pend) break;
+    // ---- inputs of this row step: a given hit to update with, or a search
+    bool act = phase != kIdle;
+    bool prop = act;
+    bool end = false;  // FOLLOW / EXTEND ran out of rows
+    int given = -1;
+    int row = 0;
+    if (phase == kChain) {
+      given = B.upc[prev];
+      row = r0 + k;
+    } else if (phase == kRefit) {
+      given = hl[k];
+      row = B.srow[given];
+      prop = k < n1 - 1;
+    } else if (phase == kFollow || phase == kExtend) {
+      end = phase == kFollow ? r >= R : r < 0;
+      row = r;
+      if (end) act = prop = false;
+    }
+    // ---- the step: one propagation, one search, one test, one update
+    bool ok = true;
+    if (prop) {
+      ++steps;
+      ok = kf_propagate(P, st, B.row_x[row]);
+    }
+    int h = given;
+    const bool search = act && ok && given < 0;
+    if (search) h = kf_search(B, P, rt, st, row, cands);
+    bool acc = act && ok && h >= 0;
+    float2 c = make_float2(0.0f, 0.0f);
+    if (acc) c = B.yz[h];
+    if (acc && search) {
+      float cc2;
+      acc = kf_chi2(P, st, c.x, c.y, cc2) && cc2 <= P.pick_chi2;
+    }
+    float c2 = 0.0f;
+    const bool upd = acc && kf_update(P, st, c.x, c.y, c2);
+    // ---- bookkeeping
+    if (phase == kChain) {
+      if (!upd) {
+        kf_fail(B, t, start_id, n_chain);
+        phase = kIdle;
+      } else {
+        hl[k] = h;
+        prev = h;
+        if (++k == n_chain) {
+          aux = st;
+          row_out = r0 + n_chain - 1;
+          r = row_out + 1;
           miss = 0;
-        } else if (++miss >= P.max_miss) {
-          break;
+          n1 = n_chain;
+          phase = kFollow;
         }
       }
-      // pass 2
-      st = saved;
-      if (P.inflate > 0.0f) {
-#pragma unroll
-        for (int k = 0; k < 15; ++k) st.C[k] = st.C[k] * P.inflate;
+    } else if (phase == kRefit) {
+      if (!upd) {
+        kf_fail(B, t, start_id, n_chain);
+        phase = kIdle;
       } else {
-#pragma unroll
-        for (int k = 0; k < 15; ++k) st.C[k] = 0.0f;
-        st.C[0] = P.r00;
-        st.C[2] = P.r11;
-        st.C[5] = P.c22;
-        st.C[9] = P.c33;
-        st.C[14] = P.c44;
+        chi2 = chi2 + c2;
+        if (--k < 0) {
+          aux = st;
+          row_ref = r0;
+          ne = 0;
+          miss = 0;
+          r = r0 - 1;
+          phase = kExtend;
+        }
       }
-      float chi2 = 0.0f;
-      // pass-1 hits sit in rows: chain rows r0.., then rows recorded in hl
-      int hr_prev = -1;
-      for (int k = n1 - 1; k >= 0 && ok; --k) {
-        const int gh = hl[k];
-        const int hr = k < o.n_chain ? r0 + k : row_of(rt, R, gh);
-        if (k < n1 - 1) ok = kf_propagate(P, st, B.row_x[hr]);
-        const float2 h = B.yz[gh];
-        ok = ok && kf_update(P, st, h.x, h.y, c2);
-        if (ok) chi2 = chi2 + c2;
-        hr_prev = hr;
-      }
-      (void)hr_prev;
-      if (ok) {
-        KState out = st;
-        int ne = 0;
-        int miss2 = 0;
-        int row_ref = r0;
-        for (int r = r0 - 1; r >= 0; --r) {
-          if (!kf_propagate(P, st, B.row_x[r])) break;
-          const int h = kf_search(B, P, rt, st, r);
-          bool took = false;
-          if (h >= 0) {
-            const float2 c = B.yz[h];
-            float cc2;
-            if (kf_chi2(P, st, c.x, c.y, cc2) && cc2 <= P.pick_chi2 &&
-                kf_update(P, st, c.x, c.y, c2)) {
+    } else if (phase == kFollow || phase == kExtend) {
+      const bool fwd = phase == kFollow;
+      if (!end) {
+        if (!ok) {
+          end = true;
+        } else {
+          if (upd) {
+            if (fwd) {
+              hl[n1++] = h;
+              row_out = r;
+            } else {
               chi2 = chi2 + c2;
               hl[n1 + ne] = h;
               ++ne;
-              out = st;
               row_ref = r;
-              took = true;
             }
+            aux = st;
+            miss = 0;
+          } else if (++miss >= P.max_miss) {
+            end = true;
           }
-          if (took) {
-            miss2 = 0;
-          } else if (++miss2 >= P.max_miss) {
-            break;
-          }
+          r += fwd ? 1 : -1;
         }
+      }
+      if (end && fwd) {
+        // end of pass 1: keep its state in the record, restart for pass 2
+        tpcca_tracklet_t &o = B.trk[t];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) o.p_out[q] = aux.p[q];
+#pragma unroll
+        for (int q = 0; q < 15; ++q) o.cov_out[q] = aux.C[q];
+        o.x_out = aux.x;
+        st = aux;
+        kf_restart(P, st);
+        chi2 = 0.0f;
+        k = n1 - 1;
+        phase = kRefit;
+      } else if (end) {
+        tpcca_tracklet_t &o = B.trk[t];
+        o.start_id = start_id;
+        o.n_chain = n_chain;
         o.n_hits = n1 + ne;
         o.n_pass1 = n1;
-        o.ndf = 2 * o.n_hits - 5;
+        o.ndf = 2 * (n1 + ne) - 5;
         o.row_ref = row_ref;
         o.row_out = row_out;
-        o.x_ref = out.x;
-        o.x_out = saved.x;
+        o.x_ref = aux.x;
         o.chi2 = chi2;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-          o.p[k] = out.p[k];
-          o.p_out[k] = saved.p[k];
-        }
+        for (int q = 0; q < 5; ++q) o.p[q] = aux.p[q];
 #pragma unroll
-        for (int k = 0; k < 15; ++k) {
-          o.cov[k] = out.C[k];
-          o.cov_out[k] = saved.C[k];
-        }
-        o.status = o.n_hits < P.min_hits ? 1 : 0;
+        for (int q = 0; q < 15; ++q) o.cov[q] = aux.C[q];
+        o.status = (n1 + ne) < P.min_hits ? 1 : 0;
+        phase = kIdle;
       }
     }
-    B.trk[t] = o;
+  }
+  // work counters (one atomic per wave)
+  unsigned long long s64 = wave_sum((unsigned long long)steps);
+  unsigned long long c64 = wave_sum((unsigned long long)cands);
+  if (lane == 0) {
+    atomicAdd(&rd.kf_steps, s64);
+    atomicAdd(&rd.kf_cands, c64);
   }
 }
 
@@ -862,35 +1144,48 @@ __device__ __forceinline__ unsigned long long select_key(const tpcca_tracklet_t 
          (unsigned long long)(0xFFFFFFu - (unsigned int)o.start_id);
 }
 
+// One wave per tracklet: the lanes claim its hits together (coalesced reads
+// of the hit slots, 64-bit atomicMax per hit).
 __global__ __launch_bounds__(kBlock) void k_claim(Bufs B, ParamsDev P, int run) {
   const RunDev &rd = B.runs[run];
   const int R = P.n_rows;
-  for (int tl = blockIdx.x * blockDim.x + threadIdx.x; tl < rd.n_trk; tl += gridDim.x * blockDim.x) {
-    const int t = rd.trk0 + tl;
+  const int lane = threadIdx.x & 63;
+  const int nw = (gridDim.x * blockDim.x) >> 6;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < rd.n_trk; i += nw) {
+    const int t = B.kf_order[rd.trk0 + i];  // grid order: nearby hits
     const tpcca_tracklet_t &o = B.trk[t];
     if (o.status != 0) continue;
     const unsigned long long key = select_key(o);
     const int32_t *hl = B.trk_hits + (int64_t)t * R;
-    for (int k = 0; k < o.n_hits; ++k) atomicMax(&B.owner[hl[k]], key);
+    for (int j = lane; j < o.n_hits; j += 64) atomicMax(&B.owner[hl[j]], key);
   }
 }
 
+// One wave per tracklet: count the hits it won; accept or reject.
 __global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
   const RunDev &rd = B.runs[run];
   const int R = P.n_rows;
-  for (int tl = blockIdx.x * blockDim.x + threadIdx.x; tl < rd.n_trk; tl += gridDim.x * blockDim.x) {
-    const int t = rd.trk0 + tl;
+  const int lane = threadIdx.x & 63;
+  const int nw = (gridDim.x * blockDim.x) >> 6;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < rd.n_trk; i += nw) {
+    const int t = B.kf_order[rd.trk0 + i];
+    const int tl = t - rd.trk0;
     const tpcca_tracklet_t &o = B.trk[t];
     unsigned long long v = 0;
     if (o.status == 0) {
       const unsigned long long key = select_key(o);
       const int32_t *hl = B.trk_hits + (int64_t)t * R;
       int won = 0;
-      for (int k = 0; k < o.n_hits; ++k) won += B.owner[hl[k]] == key;
+      for (int j0 = 0; j0 < o.n_hits; j0 += 64) {
+        const int j = j0 + lane;
+        const unsigned long long m = __ballot(j < o.n_hits && B.owner[hl[j]] == key);
+        if (lane == 0) B.wonmask[(int64_t)t * 4 + (j0 >> 6)] = m;
+        won += __popcll(m);
+      }
       if (won >= P.min_hits && won * 100 >= P.own_pct * o.n_hits)
         v = (1ull << 40) | (unsigned long long)won;
     }
-    B.accv[tl] = v;
+    if (lane == 0) B.accv[tl] = v;
   }
 }
 
@@ -990,46 +1285,62 @@ __global__ void k_unit_results(Bufs B, int run) {
   }
 }
 
-// Compaction of accepted tracks: parameters, won hits in ascending rows
-// (inward hits were stored after the pass-1 hits in descending rows), and
-// the per-cluster assignment (unit-local track index).
+// Compaction of accepted tracks, one wave per tracklet: parameters, won hits
+// in ascending rows (inward hits were stored after the pass-1 hits in
+// descending rows) and the per-cluster assignment (unit-local track index).
 __global__ __launch_bounds__(kBlock) void k_output(Bufs B, ParamsDev P, int run) {
   const RunDev &rd = B.runs[run];
   const int R = P.n_rows;
-  for (int tl = blockIdx.x * blockDim.x + threadIdx.x; tl < rd.n_trk; tl += gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int nw = (gridDim.x * blockDim.x) >> 6;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < rd.n_trk; i += nw) {
+    const int t = B.kf_order[rd.trk0 + i];
+    const int tl = t - rd.trk0;
     if (B.accv[tl] == 0) continue;
-    const int t = rd.trk0 + tl;
     const tpcca_tracklet_t &o = B.trk[t];
     const int u = B.trk_unit[t];
-    const UnitDev U = B.units[u];
-    const tpcca_unit_result_t ur = B.unit_res[u];
+    const int ucl = B.units[u].cl_begin;
+    const tpcca_unit_result_t &ur = B.unit_res[u];
     const unsigned long long ex = B.accx[tl];
     const int k = rd.trk0 + acc_count(ex);
     const int64_t h0 = rd.cl0 + acc_hits(ex);
-    const unsigned long long key = select_key(o);
     const int32_t *hl = B.trk_hits + (int64_t)t * R;
-    const int n1 = o.n_pass1, ne = o.n_hits - o.n_pass1;
+    const int n1 = o.n_pass1, nh = o.n_hits, ne = nh - n1;
     const int local_track = k - (int)ur.track_begin;
     int w = 0;
-    for (int j = 0; j < o.n_hits; ++j) {
-      const int gh = j < ne ? hl[n1 + ne - 1 - j] : hl[j - ne];
-      if (B.owner[gh] != key) continue;
-      const int id = B.sid[gh];
-      B.hits_out[h0 + w] = id;
-      B.assign[U.cl_begin + id] = local_track;
-      ++w;
+    const unsigned long long *wm = B.wonmask + (int64_t)t * 4;
+    for (int j0 = 0; j0 < nh; j0 += 64) {
+      const int j = j0 + lane;
+      int gh = -1;
+      bool won = false;
+      if (j < nh) {
+        // slot of the j-th hit in row order: inward hits were stored last,
+        // in descending rows
+        const int slot = j < ne ? n1 + ne - 1 - j : j - ne;
+        gh = hl[slot];
+        won = (wm[slot >> 6] >> (slot & 63)) & 1ull;
+      }
+      const unsigned long long m = __ballot(won);
+      if (won) {
+        const int id = B.sid[gh];
+        B.hits_out[h0 + w + __popcll(m & ((1ull << lane) - 1))] = id;
+        B.assign[ucl + id] = local_track;
+      }
+      w += __popcll(m);
     }
-    tpcca_track_t tr;
-    tr.x_ref = o.x_ref;
-    for (int q = 0; q < 5; ++q) tr.p[q] = o.p[q];
-    for (int q = 0; q < 15; ++q) tr.cov[q] = o.cov[q];
-    tr.chi2 = o.chi2;
-    tr.ndf = o.ndf;
-    tr.n_hits = w;
-    tr.hit_offset = (int32_t)(h0 - ur.hit_begin);
-    tr.sector = U.sector;
-    tr.start_id = o.start_id;
-    B.tracks[k] = tr;
+    if (lane == 0) {
+      tpcca_track_t tr;
+      tr.x_ref = o.x_ref;
+      for (int q = 0; q < 5; ++q) tr.p[q] = o.p[q];
+      for (int q = 0; q < 15; ++q) tr.cov[q] = o.cov[q];
+      tr.chi2 = o.chi2;
+      tr.ndf = o.ndf;
+      tr.n_hits = w;
+      tr.hit_offset = (int32_t)(h0 - ur.hit_begin);
+      tr.sector = B.units[u].sector;
+      tr.start_id = o.start_id;
+      B.tracks[k] = tr;
+    }
   }
 }
 
@@ -1099,34 +1410,57 @@ hipError_t launch_grid(const Bufs &B, const ParamsDev &P, int run, const RunHost
 
 hipError_t launch_links(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
                         hipStream_t s) {
-  const int nch = h.c1 - h.c0;
-  if (nch > 0) k_links<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, P, run);
+  const int nt = h.tile1 - h.tile0;
+  if (nt > 0) {
+    int g = grid_for(nt, 1, 8192);
+    g = (g + 7) & ~7;  // a multiple of the 8 XCDs
+    k_links<<<g, kTile, 0, s>>>(B, P, run);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_clean(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
                         hipStream_t s) {
   (void)P;
-  const int64_t n = h.cl1 - h.cl0;
-  if (n > 0) k_clean<<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(B, run);
+  const int nch = h.c1 - h.c0;
+  if (nch > 0) k_clean<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
   return hipGetLastError();
 }
 
 hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
                          hipStream_t s) {
   const int nch = h.c1 - h.c0, nu = h.u1 - h.u0;
+  hipError_t e = launch_fill_i32(B.flag + h.cl0, h.cl1 - h.cl0, 0, s);
+  if (e != hipSuccess) return e;
+  // sval is a byte array: clear it as 32-bit words (its range is padded)
+  e = launch_fill_i32(reinterpret_cast<int32_t *>(B.sval + (h.cl0 & ~3)),
+                      ((int64_t)h.cl1 - (h.cl0 & ~3) + 3) / 4, 0, s);
+  if (e != hipSuccess) return e;
   if (nch > 0) {
-    k_chain<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, P, run);
+    k_chain<<<grid_for(nch, 1, 16384), 64, 0, s>>>(B, P, run);
     k_flag_sums<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
     k_scan_tiles<<<1, 1024, 0, s>>>(B.scan_tmp, nch);
     k_flag_apply<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
+    k_order_sums<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
+    k_scan_tiles<<<1, 1024, 0, s>>>(B.scan_tmp, nch);
+    k_order_apply<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
   }
   if (nu > 0) k_empty_units<<<grid_for(nu, 64, 1024), 64, 0, s>>>(B, run);
   return hipGetLastError();
 }
 
 hipError_t launch_kf(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s) {
-  if (h.trk_cap > 0) k_kf<<<grid_for(h.trk_cap, kKfBlock, 4096), kKfBlock, 0, s>>>(B, P, run);
+  // persistent: exactly the resident capacity of the chip, work taken from a
+  // counter
+  static int resident = 0;
+  if (resident == 0) {
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_kf, kKfBlock, 0);
+    resident = std::max(1, cus * std::max(1, per));
+  }
+  if (h.trk_cap > 0) k_kf<<<grid_for(h.trk_cap, kKfBlock, resident), kKfBlock, 0, s>>>(B, P, run);
   return hipGetLastError();
 }
 
@@ -1138,7 +1472,7 @@ hipError_t launch_select(const Bufs &B, const ParamsDev &P, int run, const RunHo
   e = launch_fill_i32(B.assign + h.cl0, n, -1, s);
   if (e != hipSuccess) return e;
   const int nu = h.u1 - h.u0;
-  const int tg = grid_for(h.trk_cap, kBlock, 4096);
+  const int tg = grid_for((int64_t)h.trk_cap * 64, kBlock, 8192);  // one wave per tracklet
   const int64_t tiles = (h.trk_cap + kScanTile - 1) / kScanTile;
   if (h.trk_cap > 0) {
     k_claim<<<tg, kBlock, 0, s>>>(B, P, run);

@@ -29,6 +29,7 @@ struct UnitHost {
 
 int64_t bins_cap_of(int64_t n, int hpb, int R) { return n / hpb + 2 * (int64_t)(R + 1) + 1; }
 int64_t trk_cap_of(int64_t n, int min_chain) { return n / std::max(1, min_chain) + 1; }
+int64_t tile_cap_of(int64_t n, int R) { return n / kTile + R + 2; }
 
 struct DevBuf {
   void *p = nullptr;
@@ -54,13 +55,13 @@ struct tpcca_ctx {
   std::vector<int32_t> unit_chunk0;  // first chunk of each unit
   std::vector<RunHost> runs;
   std::map<std::pair<int, int>, int> index;
-  int64_t n_total = 0, bins_total = 0, trk_total = 0, in_used = 0;
+  int64_t n_total = 0, bins_total = 0, trk_total = 0, tiles_total = 0, in_used = 0;
   bool tables_dirty = true;
   std::vector<int> pending_runs;  // runs launched since the last sync
 
   // device buffers
   DevBuf row_x_d, units_d, chunks_d, runs_d, rowtab, row_cnt, zmm, bincnt, binbeg, yz, sid, up,
-      dn, upc, dnc, flag, trk_start, trk_unit, unit_tbegin, trk, trk_hits, owner, accv, accx,
+      dn, upc, dnc, flag, starts, chunk_nstart, tiles, sval, tofg, kf_order, srow, cinfo, trk_start, trk_unit, unit_tbegin, trk, trk_hits, owner, accv, wonmask, accx,
       tracks, hits_out, assign, unit_res, scan_tmp, in_cl, in_row;
   Bufs B{};
 
@@ -144,11 +145,19 @@ static void refresh_bufs(tpcca_ctx *c) {
   B.binbeg = ptr<int32_t>(c->binbeg);
   B.yz = ptr<float2>(c->yz);
   B.sid = ptr<int32_t>(c->sid);
+  B.srow = ptr<uint8_t>(c->srow);
+  B.cinfo = ptr<int2>(c->cinfo);
   B.up = ptr<int32_t>(c->up);
   B.dn = ptr<int32_t>(c->dn);
   B.upc = ptr<int32_t>(c->upc);
   B.dnc = ptr<int32_t>(c->dnc);
   B.flag = ptr<int32_t>(c->flag);
+  B.starts = ptr<int2>(c->starts);
+  B.chunk_nstart = ptr<int32_t>(c->chunk_nstart);
+  B.tiles = ptr<int4>(c->tiles);
+  B.sval = ptr<uint8_t>(c->sval);
+  B.tofg = ptr<int32_t>(c->tofg);
+  B.kf_order = ptr<int32_t>(c->kf_order);
   B.trk_start = ptr<int32_t>(c->trk_start);
   B.trk_unit = ptr<int32_t>(c->trk_unit);
   B.unit_tbegin = ptr<int32_t>(c->unit_tbegin);
@@ -156,6 +165,7 @@ static void refresh_bufs(tpcca_ctx *c) {
   B.trk_hits = ptr<int32_t>(c->trk_hits);
   B.owner = ptr<unsigned long long>(c->owner);
   B.accv = ptr<unsigned long long>(c->accv);
+  B.wonmask = ptr<unsigned long long>(c->wonmask);
   B.accx = ptr<unsigned long long>(c->accx);
   B.tracks = ptr<tpcca_track_t>(c->tracks);
   B.hits_out = ptr<int32_t>(c->hits_out);
@@ -188,20 +198,29 @@ static int ensure_work(tpcca_ctx *c, int64_t n_cl, int64_t n_units, int64_t n_bi
   ENS(binbeg, NB, sizeof(int32_t), keepB);
   ENS(yz, N, sizeof(float2), keepN);
   ENS(sid, N, sizeof(int32_t), keepN);
+  ENS(srow, N, sizeof(uint8_t), keepN);
+  ENS(cinfo, N, sizeof(int2), keepN);
   ENS(up, N, sizeof(int32_t), keepN);
   ENS(dn, N, sizeof(int32_t), keepN);
   ENS(upc, N, sizeof(int32_t), keepN);
   ENS(dnc, N, sizeof(int32_t), keepN);
   ENS(flag, N, sizeof(int32_t), keepN);
+  ENS(starts, N, sizeof(int2), 0);
+  ENS(chunk_nstart, NC, sizeof(int32_t), 0);
+  ENS(tiles, (size_t)(N / kTile + U * (R + 2) + 1), sizeof(int4), (size_t)c->tiles_total);
   ENS(owner, N, sizeof(unsigned long long), keepN);
   ENS(hits_out, N, sizeof(int32_t), keepN);
   ENS(assign, N, sizeof(int32_t), keepN);
   ENS(trk_start, T, sizeof(int32_t), keepT);
+  ENS(kf_order, T, sizeof(int32_t), keepT);
+  ENS(sval, N, sizeof(uint8_t), keepN);
+  ENS(tofg, N, sizeof(int32_t), keepN);
   ENS(trk_unit, T, sizeof(int32_t), keepT);
   ENS(unit_tbegin, U + 1, sizeof(int32_t), keepU);
   ENS(trk, T, sizeof(tpcca_tracklet_t), keepT);
   ENS(trk_hits, T * (size_t)R, sizeof(int32_t), keepT * (size_t)R);
   ENS(accv, T + 1, sizeof(unsigned long long), 0);
+  ENS(wonmask, 4 * T, sizeof(unsigned long long), 0);
   ENS(accx, T + 1, sizeof(unsigned long long), 0);
   ENS(tracks, T, sizeof(tpcca_track_t), keepT);
   ENS(unit_res, U, sizeof(tpcca_unit_result_t), keepU);
@@ -239,6 +258,8 @@ static int write_run(tpcca_ctx *c, int run) {
   d.bin1 = h.bin1;
   d.trk0 = h.trk0;
   d.trk_cap = h.trk_cap;
+  d.tile0 = h.tile0;
+  d.tile1 = h.tile1;
   // pageable source: the copy completes before return
   HIPCHK(c, hipMemcpy(ptr<RunDev>(c->runs_d) + run, &d, sizeof(d), hipMemcpyHostToDevice));
   return TPCCA_OK;
@@ -257,6 +278,8 @@ static RunHost make_run(tpcca_ctx *c, int u0, int u1) {
   h.bin1 = L.bin_base + bins_cap_of(L.n, c->P.hits_per_bin, c->R);
   h.trk0 = c->units[u0].trk_base;
   h.trk_cap = (int32_t)(L.trk_base + trk_cap_of(L.n, c->P.min_chain) - h.trk0);
+  h.tile0 = c->units[u0].tile_base;
+  h.tile1 = (int32_t)(L.tile_base + tile_cap_of(L.n, c->R));
   return h;
 }
 
@@ -403,6 +426,7 @@ static int load_unit(tpcca_ctx *c, int32_t slot, int32_t sector, const tpcca_clu
   U.cl_begin = (int32_t)c->n_total;
   U.bin_base = c->bins_total;
   U.trk_base = (int32_t)c->trk_total;
+  U.tile_base = (int32_t)c->tiles_total;
   if ((flags & 1) == TPCCA_MEM_DEVICE) {
     U.cl = reinterpret_cast<const float4 *>(cl);
     U.row = row;
@@ -443,6 +467,7 @@ static int load_unit(tpcca_ctx *c, int32_t slot, int32_t sector, const tpcca_clu
   c->n_total += n;
   c->bins_total += bins_cap_of(n, c->P.hits_per_bin, c->R);
   c->trk_total += trk_cap_of(n, c->P.min_chain);
+  c->tiles_total += tile_cap_of(n, c->R);
   c->tables_dirty = true;
   return TPCCA_OK;
 }
@@ -473,7 +498,7 @@ void tpcca_params_default(tpcca_params_t *p) {
   p->min_track_hits = 10;
   p->own_frac_pct = 90;
   p->refit_inflate = 100.0f;
-  p->grid_hits_per_bin = 2;
+  p->grid_hits_per_bin = 1;
 }
 
 const char *tpcca_error_string(int s) {
@@ -565,8 +590,8 @@ int tpcca_destroy(tpcca_ctx_t *c) {
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   DevBuf *all[] = {&c->row_x_d, &c->units_d, &c->chunks_d, &c->runs_d, &c->rowtab, &c->row_cnt,
                    &c->zmm, &c->bincnt, &c->binbeg, &c->yz, &c->sid, &c->up, &c->dn, &c->upc,
-                   &c->dnc, &c->flag, &c->trk_start, &c->trk_unit, &c->unit_tbegin, &c->trk,
-                   &c->trk_hits, &c->owner, &c->accv, &c->accx, &c->tracks, &c->hits_out,
+                   &c->dnc, &c->flag, &c->starts, &c->chunk_nstart, &c->tiles, &c->sval, &c->tofg, &c->kf_order, &c->srow, &c->cinfo, &c->trk_start, &c->trk_unit, &c->unit_tbegin, &c->trk,
+                   &c->trk_hits, &c->owner, &c->accv, &c->wonmask, &c->accx, &c->tracks, &c->hits_out,
                    &c->assign, &c->unit_res, &c->scan_tmp, &c->in_cl, &c->in_row};
   for (DevBuf *b : all)
     if (b->p) hipFree(b->p);
@@ -588,7 +613,7 @@ int tpcca_reset(tpcca_ctx_t *c) {
   c->runs.clear();
   c->index.clear();
   c->pending_runs.clear();
-  c->n_total = c->bins_total = c->trk_total = c->in_used = 0;
+  c->n_total = c->bins_total = c->trk_total = c->tiles_total = c->in_used = 0;
   c->tables_dirty = true;
   c->have_times = false;
   return TPCCA_OK;
@@ -842,9 +867,10 @@ int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
   capr.cl1 = (int32_t)capN;
   capr.bin1 = capB;
   capr.trk_cap = (int32_t)capT;
+  capr.tile1 = (int32_t)(capN / kTile + capU * (c->R + 2) + 1);
   const bool reuse = c->gexec && c->gen_captured == c->generation && c->gcap.u1 == capr.u1 &&
                      c->gcap.c1 == capr.c1 && c->gcap.cl1 == capr.cl1 && c->gcap.bin1 == capr.bin1 &&
-                     c->gcap.trk_cap == capr.trk_cap;
+                     c->gcap.trk_cap == capr.trk_cap && c->gcap.tile1 == capr.tile1;
   if (!reuse) {
     if (c->gexec) {
       hipGraphExecDestroy(c->gexec);
@@ -894,6 +920,31 @@ int tpcca_batch_totals(tpcca_ctx_t *c, int32_t *n_units, int64_t *n_clusters, in
   }
   if (n_tracks) *n_tracks = nt;
   if (n_hits) *n_hits = nh;
+  return TPCCA_OK;
+}
+
+int tpcca_work_stats(tpcca_ctx_t *c, tpcca_work_stats_t *out) {
+  if (!c || !out) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  int rc = check_errors(c);
+  if (rc != TPCCA_OK) return rc;
+  std::memset(out, 0, sizeof(*out));
+  out->clusters = c->n_total;
+  for (size_t r = 0; r < c->runs.size(); ++r) {
+    RunDev d;
+    HIPCHK(c, hipMemcpy(&d, ptr<RunDev>(c->runs_d) + r, sizeof(d), hipMemcpyDeviceToHost));
+    int lo = kSelected;
+    for (int u = c->runs[r].u0; u < c->runs[r].u1; ++u) lo = std::min(lo, c->uh[u].state);
+    if (lo >= kTracklets) {
+      out->tracklets += d.n_trk;
+      out->fit_steps += (int64_t)d.kf_steps;
+      out->fit_candidates += (int64_t)d.kf_cands;
+    }
+    if (lo >= kSelected) {
+      out->tracks += d.n_acc;
+      out->track_hits += d.n_acc_hits;
+    }
+  }
   return TPCCA_OK;
 }
 

@@ -52,6 +52,11 @@ class DeviceResults(ctypes.Structure):
     _fields_ = [("tracks", c_vp), ("hits", c_vp), ("assignment", c_vp), ("units", c_vp), ("n_units", c_i32)]
 
 
+class WorkStats(ctypes.Structure):
+    _fields_ = [("clusters", c_i64), ("tracklets", c_i64), ("tracks", c_i64), ("track_hits", c_i64),
+                ("fit_steps", c_i64), ("fit_candidates", c_i64)]
+
+
 class Timeframe(ctypes.Structure):
     _fields_ = [("n_units", c_i32), ("sector", c_vp), ("begin", c_vp), ("n", c_vp), ("cl", c_vp),
                 ("row", c_vp), ("tracks", c_vp), ("tracks_cap", c_i64), ("hits", c_vp),
@@ -90,6 +95,7 @@ SYMBOLS = (
     "tpcca_last_error", "tpcca_stage_times", "tpcca_set_timing", "tpcca_server_create",
     "tpcca_server_submit", "tpcca_server_poll", "tpcca_server_wait", "tpcca_server_release",
     "tpcca_server_stats", "tpcca_server_reset_stats", "tpcca_server_destroy", "tpcca_now",
+    "tpcca_work_stats",
 )
 
 _lib = None
@@ -140,6 +146,7 @@ def lib():
         "tpcca_server_reset_stats": (c_i32, [c_vp]),
         "tpcca_server_destroy": (c_i32, [c_vp]),
         "tpcca_now": (ctypes.c_double, []),
+        "tpcca_work_stats": (c_i32, [c_vp, ctypes.POINTER(WorkStats)]),
     }
     missing = [n for n in SYMBOLS if not hasattr(L, n)]
     if missing:
@@ -324,6 +331,11 @@ class Context:
                                              hits.shape[0], _p(asg), asg.shape[0]),
                "tpcca_get_batch_results", self.h)
         return units, tracks[:nt], hits[:nh], asg[:nc]
+
+    def work_stats(self) -> dict:
+        w = WorkStats()
+        _check(lib().tpcca_work_stats(self.h, ctypes.byref(w)), "tpcca_work_stats", self.h)
+        return {k: getattr(w, k) for k, _ in WorkStats._fields_}
 
     def device_results(self):
         d = DeviceResults()
