@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3")
+    ap.add_argument("--retune", action="store_true", help="re-run the schedule autotuner")
     return ap.parse_args()
 
 
@@ -98,6 +99,9 @@ def main():
 
     # ------------------------------------------------- batched (headline)
     ctx = tpcca.Context(rx, device=0)
+    from paper_1709_00618_amd import autotune
+    knobs, knob_src = autotune.tuned(ctx, dcl, drow, tf.units, tf.n_clusters, log=log, retune=args.retune)
+    log(f"schedule ({knob_src}): {knobs}")
     for _ in range(args.warmup):
         ctx.run_batch(dcl, drow, tf.units, device=True, graph=True)
         ctx.sync()
@@ -187,6 +191,8 @@ def main():
                                f"36 sector units, {ncl} clusters, device-resident, graph replay",
                    "clusters": ncl, "units": nu, "tracks": ntr, "assigned_clusters": nhits},
         "tracks_per_s": round(ntr / dt, 1),
+        "schedule": {"knobs": knobs, "source": knob_src},
+        "work": work,
         "per_event": {"workload": f"central Pb-Pb event, 8000 tracks, {ev.n_clusters} clusters, one launch per "
                                   "kernel per event, device-resident",
                       "value": round(per_event, 1), "unit": "clusters/s", "ms_per_event": round(pe_dt * 1e3, 4)},

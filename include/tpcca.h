@@ -227,6 +227,20 @@ int tpcca_work_stats(tpcca_ctx_t *ctx, tpcca_work_stats_t *out);
 /* Device pointers to the batch results (no copy; synchronises). */
 int tpcca_device_results(tpcca_ctx_t *ctx, tpcca_device_results_t *out);
 
+/* Launch schedule knobs.  None of them changes any result (every decision
+   compares cluster IDs and the same operation sequence runs per tracklet);
+   they only trade occupancy, load balance and grid granularity.  Picked by
+   the autotuner (paper_1709_00618_amd/autotune.py); 0 = default. */
+typedef struct {
+  int32_t fit_pool;          /* tracklets a wave of the fit kernel claims at once (64) */
+  int32_t fit_blocks_per_cu; /* resident fit blocks per CU (0: occupancy limit) */
+  int32_t grid_hits_per_bin; /* z-bin occupancy of the row grid (1); applies after reset */
+  int32_t link_blocks_per_cu;/* resident neighbour-finding blocks per CU (0: 32) */
+  int32_t fit_min_waves;     /* register budget of the fit kernel: 0 compiler's, 6 or 8 waves/SIMD */
+} tpcca_tuning_t;
+int tpcca_set_tuning(tpcca_ctx_t *ctx, const tpcca_tuning_t *t);
+int tpcca_get_tuning(tpcca_ctx_t *ctx, tpcca_tuning_t *t);
+
 /* Error text of a status code, and the last HIP/runtime message of ctx. */
 const char *tpcca_error_string(int status);
 const char *tpcca_last_error(tpcca_ctx_t *ctx);

@@ -1,0 +1,115 @@
+"""Autotuner of the launch schedule of the batched tracker.
+
+The knobs (``tpcca_tuning_t``) change occupancy, load balance and grid
+granularity, never a result: every decision compares cluster IDs and each
+tracklet sees the same operation sequence whatever the schedule.  The tuner
+replays the batch graph of a sample batch for every point of a small grid of
+schedules, keeps the fastest, and caches it in ``tuning_cache.json`` keyed by
+device name and a size bucket of the batch (clusters, units).
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuning_cache.json")
+
+SPACE = {
+    "fit_pool": [32, 64, 128],
+    "fit_min_waves": [0, 6, 8],
+    "grid_hits_per_bin": [1, 2],
+    "link_blocks_per_cu": [16, 32],
+}
+
+
+def bucket(n_clusters: int, n_units: int) -> str:
+    return f"cl2^{max(0, int(math.log2(max(1, n_clusters))))}_u{'1' if n_units <= 1 else '36' if n_units <= 36 else 'many'}"
+
+
+def device_name() -> str:
+    try:
+        import torch
+        return torch.cuda.get_device_name(0)
+    except Exception:  # plumbing only
+        return "unknown"
+
+
+def load_cache() -> dict:
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def lookup(n_clusters: int, n_units: int, dev: str | None = None):
+    return load_cache().get(dev or device_name(), {}).get(bucket(n_clusters, n_units))
+
+
+def store(entry: dict, n_clusters: int, n_units: int, dev: str | None = None, path: str = CACHE):
+    cache = load_cache()
+    cache.setdefault(dev or device_name(), {})[bucket(n_clusters, n_units)] = entry
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+
+
+def _time(ctx, run, reps):
+    run()
+    ctx.sync()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        run()
+        ctx.sync()
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune(ctx, cl, row, units, device=True, reps=3, space=None, log=None):
+    """Sweep the schedule grid on one batch; returns (best dict, table)."""
+    space = space or SPACE
+    names = list(space)
+    table = []
+
+    def run():
+        ctx.run_batch(cl, row, units, device=device, graph=True)
+
+    for combo in itertools.product(*(space[n] for n in names)):
+        knobs = dict(zip(names, combo))
+        ctx.reset()
+        ctx.set_tuning(**knobs)
+        t = _time(ctx, run, reps)
+        table.append((t, knobs))
+        if log:
+            log(f"autotune {knobs}: {t * 1e3:.3f} ms")
+    table.sort(key=lambda x: x[0])
+    best = dict(table[0][1])
+    ctx.reset()
+    ctx.set_tuning(**best)
+    return best, table
+
+
+def tuned(ctx, cl, row, units, n_clusters, device=True, log=None, retune=False):
+    """Apply the cached schedule for this device and size, tuning first if
+    there is none.  Returns (knobs, source)."""
+    n_units = len(units)
+    entry = None if retune else lookup(n_clusters, n_units)
+    if entry is not None:
+        ctx.reset()
+        ctx.set_tuning(**entry["knobs"])
+        return entry["knobs"], "cache"
+    best, table = tune(ctx, cl, row, units, device=device, log=log)
+    store({"knobs": best, "ms": round(table[0][0] * 1e3, 4),
+           "default_ms": round(next(t for t, k in table if k == _default(table)) * 1e3, 4)
+           if _default(table) else None},
+          n_clusters, n_units)
+    return best, "tuned"
+
+
+def _default(table):
+    d = {"fit_pool": 64, "fit_min_waves": 0, "grid_hits_per_bin": 1, "link_blocks_per_cu": 32}
+    return d if any(k == d for _, k in table) else None

@@ -28,6 +28,7 @@ struct UnitDev {
 };
 
 constexpr int kTile = 256;  // hits of one row per neighbour-finding tile
+constexpr int kMaxBinsRow = 8192;  // z bins per row (the row sort keeps them in LDS)
 
 // A chunk of <= kChunk consecutive clusters of one unit.
 struct Chunk {
@@ -79,6 +80,11 @@ struct ParamsDev {
   int32_t max_miss, min_hits, own_pct;
   float inflate;
   int32_t hits_per_bin;
+  // schedule (no effect on results)
+  int32_t kf_pool;
+  int32_t kf_blocks_per_cu;
+  int32_t link_blocks_per_cu;
+  int32_t kf_min_waves;
 };
 
 // Device buffers of a context (all indices global).
@@ -89,8 +95,9 @@ struct Bufs {
   RunDev *runs;
   RowTab *rowtab;        // units x (n_rows + 1)
   int32_t *row_cnt;      // units x (n_rows + 1)
+  int32_t *row_fill;     // units x (n_rows + 1): reservation cursors of the row scatter
+  int4 *rtmp;            // row-grouped staging records (y, z, id, row) by global index
   int32_t *zmm;          // units x 2 (ordered-int min, max)
-  int32_t *bincnt;       // bins
   int32_t *binbeg;       // bins
   float2 *yz;            // sorted hits
   int32_t *sid;          // sorted -> unit-local cluster ID

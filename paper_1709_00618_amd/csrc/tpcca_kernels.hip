@@ -111,8 +111,10 @@ __global__ void k_run_reset(Bufs B, int run, int R) {
   RunDev &rd = B.runs[run];
   const int units = rd.u1 - rd.u0;
   const int nrow = units * (R + 1);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nrow; i += gridDim.x * blockDim.x)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nrow; i += gridDim.x * blockDim.x) {
     B.row_cnt[(int64_t)rd.u0 * (R + 1) + i] = 0;
+    B.row_fill[(int64_t)rd.u0 * (R + 1) + i] = 0;
+  }
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < units; i += gridDim.x * blockDim.x) {
     B.zmm[2 * (rd.u0 + i)] = 0x7FFFFFFF;
     B.zmm[2 * (rd.u0 + i) + 1] = (int)0x80000000;
@@ -194,7 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(Bufs B, int run, int R, int hit
     int32_t tot;
     const int32_t begin = block_exclusive_scan<int32_t>(cnt, lds32, &tot);
     int nb = 0;
-    if (r < R) nb = max(1, min(cnt / hits_per_bin, 1 << 20));
+    if (r < R) nb = max(1, min(cnt / hits_per_bin, kMaxBinsRow));
     else if (r == R) nb = 1;
     const int64_t width = r <= R ? (int64_t)nb + 1 : 0;
     int64_t wtot;
@@ -232,45 +234,131 @@ __global__ __launch_bounds__(kBlock) void k_plan(Bufs B, int run, int R, int hit
   }
 }
 
-// Pass 3: occupancy of every bin.
-__global__ __launch_bounds__(kBlock) void k_bin_count(Bufs B, int run, int R) {
+// Pass 3: group the clusters by (unit, row) into the staging buffer.  A
+// block takes up to four consecutive chunks (kGroup), sorts their clusters
+// by (unit, row) in LDS, reserves one contiguous range per (unit, row) in
+// the row's segment, and writes runs of records.  The order inside a row
+// is arbitrary (every later decision compares cluster IDs, never positions).
+constexpr int kGroup = 4;
+
+__global__ __launch_bounds__(kBlock) void k_rowscatter(Bufs B, int run, int R) {
+  __shared__ int hist[kGroup * (kMaxRows + 1)];
+  __shared__ int cursor[kGroup * (kMaxRows + 1)];
+  __shared__ int slot_unit[kGroup];
   const RunDev &rd = B.runs[run];
-  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
-    const Chunk ch = B.chunks[c];
-    const UnitDev U = B.units[ch.unit];
-    const RowTab *rt = B.rowtab + (int64_t)ch.unit * (R + 1);
-    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
-      const int li = ch.begin + i;
-      const float4 c4 = U.cl[li];
-      const int r = valid_row(c4, U.row[li], B.row_x, R);
-      const RowTab t = rt[r];
-      atomicAdd(&B.bincnt[t.bin0 + zbin(t, c4.z)], 1);
+  const int nslots = kGroup * (R + 1);
+  const int ngroups = (rd.c1 - rd.c0 + kGroup - 1) / kGroup;
+  for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
+    const int c0 = rd.c0 + gi * kGroup;
+    const int c1 = min(rd.c1, c0 + kGroup);
+    for (int k = threadIdx.x; k < nslots; k += blockDim.x) hist[k] = 0;
+    if (threadIdx.x == 0) {
+      // distinct units of the group get consecutive slots
+      int us = -1, prev = -1;
+      for (int c = c0; c < c1; ++c) {
+        const int u = B.chunks[c].unit;
+        if (u != prev) {
+          ++us;
+          prev = u;
+        }
+        slot_unit[c - c0] = us;
+      }
     }
+    __syncthreads();
+    // pass a: histogram of (unit slot, row)
+    for (int c = c0; c < c1; ++c) {
+      const Chunk ch = B.chunks[c];
+      const UnitDev U = B.units[ch.unit];
+      const int so = slot_unit[c - c0] * (R + 1);
+      for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
+        const int li = ch.begin + i;
+        const int r = valid_row(U.cl[li], U.row[li], B.row_x, R);
+        atomicAdd(&hist[so + r], 1);
+      }
+    }
+    __syncthreads();
+    // reserve one range per non-empty (unit, row)
+    for (int k = threadIdx.x; k < nslots; k += blockDim.x) {
+      const int cnt = hist[k];
+      cursor[k] = 0;
+      if (cnt) {
+        const int us = k / (R + 1), r = k - us * (R + 1);
+        int u = -1;
+        for (int c = c0; c < c1; ++c)
+          if (slot_unit[c - c0] == us) {
+            u = B.chunks[c].unit;
+            break;
+          }
+        const int64_t rr = (int64_t)u * (R + 1) + r;
+        cursor[k] = B.rowtab[rr].begin + atomicAdd(&B.row_fill[rr], cnt);
+      }
+    }
+    __syncthreads();
+    // pass b: write the records into the reserved runs
+    for (int c = c0; c < c1; ++c) {
+      const Chunk ch = B.chunks[c];
+      const UnitDev U = B.units[ch.unit];
+      const int so = slot_unit[c - c0] * (R + 1);
+      for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
+        const int li = ch.begin + i;
+        const float4 c4 = U.cl[li];
+        const int r = valid_row(c4, U.row[li], B.row_x, R);
+        const int pos = atomicAdd(&cursor[so + r], 1);
+        B.rtmp[pos] = make_int4(__float_as_int(c4.y), __float_as_int(c4.z), li, r);
+      }
+    }
+    __syncthreads();
   }
 }
 
-// Pass 4 is a device scan of the bin counts into B.binbeg (see below).
-
-// Pass 5: scatter hits into bin order (order inside a bin is arbitrary: all
-// later decisions compare cluster IDs, never positions).
-__global__ __launch_bounds__(kBlock) void k_scatter(Bufs B, int run, int R) {
+// Pass 4, one block per (unit, row): counting sort of the row's records by
+// z bin in LDS; writes the row's bin offsets and its sorted hits.  The
+// scattered writes stay inside the row's own segment.
+__global__ __launch_bounds__(kBlock) void k_rowsort(Bufs B, int run, int R) {
+  __shared__ int hist[kMaxBinsRow];
+  __shared__ int lds[kBlock / 64 + 1];
   const RunDev &rd = B.runs[run];
-  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
-    const Chunk ch = B.chunks[c];
-    const UnitDev U = B.units[ch.unit];
-    const RowTab *rt = B.rowtab + (int64_t)ch.unit * (R + 1);
-    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
-      const int li = ch.begin + i;
-      const float4 c4 = U.cl[li];
-      const int r = valid_row(c4, U.row[li], B.row_x, R);
-      const RowTab t = rt[r];
-      const int64_t g = t.bin0 + zbin(t, c4.z);
-      const int k = atomicSub(&B.bincnt[g], 1) - 1;
-      const int pos = B.binbeg[g] + k;
-      B.yz[pos] = make_float2(c4.y, c4.z);
-      B.sid[pos] = li;
-      B.srow[pos] = (uint8_t)r;
+  const int nrows = (rd.u1 - rd.u0) * (R + 1);
+  constexpr int per = kMaxBinsRow / kBlock;
+  for (int w = blockIdx.x; w < nrows; w += gridDim.x) {
+    const int64_t rr = (int64_t)rd.u0 * (R + 1) + w;
+    const RowTab t = B.rowtab[rr];
+    for (int k = threadIdx.x; k < t.nb; k += blockDim.x) hist[k] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < t.count; i += blockDim.x) {
+      const int4 rec = B.rtmp[t.begin + i];
+      atomicAdd(&hist[zbin(t, __int_as_float(rec.y))], 1);
     }
+    __syncthreads();
+    // exclusive scan of the nb bin counts (per consecutive entries per thread)
+    int v[per];
+    int loc = 0;
+    for (int q = 0; q < per; ++q) {
+      const int k = threadIdx.x * per + q;
+      v[q] = k < t.nb ? hist[k] : 0;
+      loc += v[q];
+    }
+    int tot;
+    int ex = block_exclusive_scan<int>(loc, lds, &tot);
+    for (int q = 0; q < per; ++q) {
+      const int k = threadIdx.x * per + q;
+      if (k < t.nb) {
+        hist[k] = ex;
+        B.binbeg[t.bin0 + k] = t.begin + ex;
+      }
+      ex += v[q];
+    }
+    if (threadIdx.x == 0) B.binbeg[t.bin0 + t.nb] = t.begin + t.count;
+    __syncthreads();
+    for (int i = threadIdx.x; i < t.count; i += blockDim.x) {
+      const int4 rec = B.rtmp[t.begin + i];
+      const float z = __int_as_float(rec.y);
+      const int pos = t.begin + atomicAdd(&hist[zbin(t, z)], 1);
+      B.yz[pos] = make_float2(__int_as_float(rec.x), z);
+      B.sid[pos] = rec.z;
+      B.srow[pos] = (uint8_t)rec.w;
+    }
+    __syncthreads();
   }
 }
 
@@ -519,27 +607,6 @@ __global__ __launch_bounds__(64) void k_chain(Bufs B, ParamsDev P, int run) {
 }
 
 // ---------------------------------------------------------------- scans ---
-// Tile sums of a plain int32 array segment [a, b) (tiles of kScanTile).
-__global__ __launch_bounds__(kBlock) void k_scan_sums_i32(const int32_t *in, int64_t a, int64_t b,
-                                                          int64_t *sums) {
-  const int64_t ntiles = (b - a + kScanTile - 1) / kScanTile;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t s = a + t * kScanTile, e = min(b, s + kScanTile);
-    int64_t v = 0;
-    for (int64_t i = s + threadIdx.x; i < e; i += blockDim.x) v += in[i];
-    v = wave_sum(v);
-    __shared__ int64_t part[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t tot = 0;
-      for (int w = 0; w < kBlock / 64; ++w) tot += part[w];
-      sums[t] = tot;
-    }
-    __syncthreads();
-  }
-}
-
 // Exclusive scan of n tile sums in place (one block); sums[n] = total.
 __global__ __launch_bounds__(1024) void k_scan_tiles(int64_t *sums, int64_t n) {
   __shared__ int64_t lds[1024 / 64 + 1];
@@ -553,32 +620,6 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(int64_t *sums, int64_t n) {
     carry += tot;
   }
   if (threadIdx.x == 0) sums[n] = carry;
-}
-
-// out[i] = add + exclusive prefix of in over [a, b) (tile offsets from sums).
-__global__ __launch_bounds__(kBlock) void k_scan_apply_i32(const int32_t *in, int32_t *out, int64_t a,
-                                                           int64_t b, const int64_t *sums,
-                                                           int64_t add) {
-  __shared__ int64_t lds[kBlock / 64 + 1];
-  const int64_t ntiles = (b - a + kScanTile - 1) / kScanTile;
-  constexpr int per = kScanTile / kBlock;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t s = a + t * kScanTile;
-    int32_t v[per];
-    int64_t loc = 0;
-    for (int k = 0; k < per; ++k) {
-      const int64_t i = s + threadIdx.x * per + k;
-      v[k] = i < b ? in[i] : 0;
-      loc += v[k];
-    }
-    int64_t tot;
-    int64_t ex = block_exclusive_scan<int64_t>(loc, lds, &tot) + sums[t] + add;
-    for (int k = 0; k < per; ++k) {
-      const int64_t i = s + threadIdx.x * per + k;
-      if (i < b) out[i] = (int32_t)ex;
-      ex += v[k];
-    }
-  }
 }
 
 // Tracklet compaction: per chunk, count flags (tile = chunk).
@@ -923,19 +964,31 @@ __device__ __forceinline__ void kf_restart(const ParamsDev &P, KState &st) {
   }
 }
 
-__global__ __launch_bounds__(kKfBlock) void k_kf(Bufs B, ParamsDev P, int run) {
+template <int kMinWaves>
+__global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P, int run) {
   RunDev &rd = B.runs[run];
   const int R = P.n_rows;
   const int n_trk = rd.n_trk;
   const int lane = threadIdx.x & 63;
   int phase = kIdle;
   bool exhausted = false;
-  constexpr int kPool = 64;
+  const int kPool = P.kf_pool;
   int t = 0, start_id = 0, n_chain = 0, r0 = 0, k = 0, r = 0, miss = 0, n1 = 0, ne = 0;
   int row_out = 0, row_ref = 0, prev = 0;
   const RowTab *rt = nullptr;
   int32_t *hl = nullptr;
-  KState st, aux;  // aux: pass-1 state at the outermost hit, then pass-2 output state
+  KState st;
+  // aux state in LDS (frees registers for occupancy): the pass-1 state at
+  // the outermost hit, then the pass-2 state at the innermost hit
+  __shared__ float s_aux[21][kKfBlock];
+  const int tid = threadIdx.x;
+  auto save_aux = [&]() {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) s_aux[q][tid] = st.p[q];
+#pragma unroll
+    for (int q = 0; q < 15; ++q) s_aux[5 + q][tid] = st.C[q];
+    s_aux[20][tid] = st.x;
+  };
   float chi2 = 0.0f;
   unsigned int steps = 0, cands = 0;
   int pnext = 0, pend = 0;  // wave-private pool of claimed tracklets
@@ -1044,7 +1097,7 @@ __global__ __launch_bounds__(kKfBlock) void k_kf(Bufs B, ParamsDev P, int run) {
         hl[k] = h;
         prev = h;
         if (++k == n_chain) {
-          aux = st;
+          save_aux();
           row_out = r0 + n_chain - 1;
           r = row_out + 1;
           miss = 0;
@@ -1059,7 +1112,7 @@ __global__ __launch_bounds__(kKfBlock) void k_kf(Bufs B, ParamsDev P, int run) {
       } else {
         chi2 = chi2 + c2;
         if (--k < 0) {
-          aux = st;
+          save_aux();
           row_ref = r0;
           ne = 0;
           miss = 0;
@@ -1083,7 +1136,7 @@ __global__ __launch_bounds__(kKfBlock) void k_kf(Bufs B, ParamsDev P, int run) {
               ++ne;
               row_ref = r;
             }
-            aux = st;
+            save_aux();
             miss = 0;
           } else if (++miss >= P.max_miss) {
             end = true;
@@ -1095,11 +1148,10 @@ __global__ __launch_bounds__(kKfBlock) void k_kf(Bufs B, ParamsDev P, int run) {
         // end of pass 1: keep its state in the record, restart for pass 2
         tpcca_tracklet_t &o = B.trk[t];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) o.p_out[q] = aux.p[q];
+        for (int q = 0; q < 5; ++q) o.p_out[q] = st.p[q] = s_aux[q][tid];
 #pragma unroll
-        for (int q = 0; q < 15; ++q) o.cov_out[q] = aux.C[q];
-        o.x_out = aux.x;
-        st = aux;
+        for (int q = 0; q < 15; ++q) o.cov_out[q] = st.C[q] = s_aux[5 + q][tid];
+        o.x_out = st.x = s_aux[20][tid];
         kf_restart(P, st);
         chi2 = 0.0f;
         k = n1 - 1;
@@ -1113,12 +1165,12 @@ __global__ __launch_bounds__(kKfBlock) void k_kf(Bufs B, ParamsDev P, int run) {
         o.ndf = 2 * (n1 + ne) - 5;
         o.row_ref = row_ref;
         o.row_out = row_out;
-        o.x_ref = aux.x;
+        o.x_ref = s_aux[20][tid];
         o.chi2 = chi2;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) o.p[q] = aux.p[q];
+        for (int q = 0; q < 5; ++q) o.p[q] = s_aux[q][tid];
 #pragma unroll
-        for (int q = 0; q < 15; ++q) o.cov[q] = aux.C[q];
+        for (int q = 0; q < 15; ++q) o.cov[q] = s_aux[5 + q][tid];
         o.status = (n1 + ne) < P.min_hits ? 1 : 0;
         phase = kIdle;
       }
@@ -1391,20 +1443,10 @@ hipError_t launch_grid(const Bufs &B, const ParamsDev &P, int run, const RunHost
   const int R = P.n_rows;
   const int nch = h.c1 - h.c0, nu = h.u1 - h.u0;
   k_run_reset<<<grid_for((int64_t)nu * (R + 1), 256, 1024), 256, 0, s>>>(B, run, R);
-  hipError_t e = launch_fill_i32(B.bincnt + h.bin0, h.bin1 - h.bin0, 0, s);
-  if (e != hipSuccess) return e;
   if (nch > 0) k_count<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run, R);
   if (nu > 0) k_plan<<<grid_for(nu, 1, 4096), kBlock, 0, s>>>(B, run, R, P.hits_per_bin);
-  if (nch > 0) k_bin_count<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run, R);
-  const int64_t nb = h.bin1 - h.bin0;
-  const int64_t tiles = (nb + kScanTile - 1) / kScanTile;
-  if (nb > 0) {
-    k_scan_sums_i32<<<grid_for(tiles, 1, 8192), kBlock, 0, s>>>(B.bincnt, h.bin0, h.bin1, B.scan_tmp);
-    k_scan_tiles<<<1, 1024, 0, s>>>(B.scan_tmp, tiles);
-    k_scan_apply_i32<<<grid_for(tiles, 1, 8192), kBlock, 0, s>>>(B.bincnt, B.binbeg, h.bin0, h.bin1,
-                                                                  B.scan_tmp, h.cl0);
-  }
-  if (nch > 0) k_scatter<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run, R);
+  if (nch > 0) k_rowscatter<<<grid_for((nch + kGroup - 1) / kGroup, 1, 8192), kBlock, 0, s>>>(B, run, R);
+  if (nu > 0) k_rowsort<<<grid_for((int64_t)nu * (R + 1), 1, 16384), kBlock, 0, s>>>(B, run, R);
   return hipGetLastError();
 }
 
@@ -1412,7 +1454,7 @@ hipError_t launch_links(const Bufs &B, const ParamsDev &P, int run, const RunHos
                         hipStream_t s) {
   const int nt = h.tile1 - h.tile0;
   if (nt > 0) {
-    int g = grid_for(nt, 1, 8192);
+    int g = grid_for(nt, 1, 256 * (P.link_blocks_per_cu > 0 ? P.link_blocks_per_cu : 32));
     g = (g + 7) & ~7;  // a multiple of the 8 XCDs
     k_links<<<g, kTile, 0, s>>>(B, P, run);
   }
@@ -1452,15 +1494,26 @@ hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHo
 hipError_t launch_kf(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s) {
   // persistent: exactly the resident capacity of the chip, work taken from a
   // counter
-  static int resident = 0;
-  if (resident == 0) {
-    int dev = 0, cus = 0, per = 0;
+  // register budget variants: 1 = compiler's choice, 6 / 8 waves per SIMD
+  const int v = P.kf_min_waves >= 8 ? 2 : P.kf_min_waves >= 6 ? 1 : 0;
+  static int cus = 0, per[3] = {0, 0, 0};
+  if (cus == 0) {
+    int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_kf, kKfBlock, 0);
-    resident = std::max(1, cus * std::max(1, per));
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_kf<1>, kKfBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_kf<6>, kKfBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_kf<8>, kKfBlock, 0);
+    cus = std::max(1, cus);
+    for (int k = 0; k < 3; ++k) per[k] = std::max(1, per[k]);
   }
-  if (h.trk_cap > 0) k_kf<<<grid_for(h.trk_cap, kKfBlock, resident), kKfBlock, 0, s>>>(B, P, run);
+  const int bpc = P.kf_blocks_per_cu > 0 ? std::min(P.kf_blocks_per_cu, per[v]) : per[v];
+  const int g = grid_for(h.trk_cap, kKfBlock, cus * bpc);
+  if (h.trk_cap > 0) {
+    if (v == 2) k_kf<8><<<g, kKfBlock, 0, s>>>(B, P, run);
+    else if (v == 1) k_kf<6><<<g, kKfBlock, 0, s>>>(B, P, run);
+    else k_kf<1><<<g, kKfBlock, 0, s>>>(B, P, run);
+  }
   return hipGetLastError();
 }
 

@@ -60,7 +60,7 @@ struct tpcca_ctx {
   std::vector<int> pending_runs;  // runs launched since the last sync
 
   // device buffers
-  DevBuf row_x_d, units_d, chunks_d, runs_d, rowtab, row_cnt, zmm, bincnt, binbeg, yz, sid, up,
+  DevBuf row_x_d, units_d, chunks_d, runs_d, rowtab, row_cnt, row_fill, rtmp, zmm, binbeg, yz, sid, up,
       dn, upc, dnc, flag, starts, chunk_nstart, tiles, sval, tofg, kf_order, srow, cinfo, trk_start, trk_unit, unit_tbegin, trk, trk_hits, owner, accv, wonmask, accx,
       tracks, hits_out, assign, unit_res, scan_tmp, in_cl, in_row;
   Bufs B{};
@@ -140,8 +140,9 @@ static void refresh_bufs(tpcca_ctx *c) {
   B.runs = ptr<RunDev>(c->runs_d);
   B.rowtab = ptr<RowTab>(c->rowtab);
   B.row_cnt = ptr<int32_t>(c->row_cnt);
+  B.row_fill = ptr<int32_t>(c->row_fill);
+  B.rtmp = ptr<int4>(c->rtmp);
   B.zmm = ptr<int32_t>(c->zmm);
-  B.bincnt = ptr<int32_t>(c->bincnt);
   B.binbeg = ptr<int32_t>(c->binbeg);
   B.yz = ptr<float2>(c->yz);
   B.sid = ptr<int32_t>(c->sid);
@@ -193,8 +194,9 @@ static int ensure_work(tpcca_ctx *c, int64_t n_cl, int64_t n_units, int64_t n_bi
   ENS(runs_d, U + 1, sizeof(RunDev), c->runs.size());
   ENS(rowtab, U * (R + 1), sizeof(RowTab), keepU * (R + 1));
   ENS(row_cnt, U * (R + 1), sizeof(int32_t), keepU * (R + 1));
+  ENS(row_fill, U * (R + 1), sizeof(int32_t), 0);
+  ENS(rtmp, N, sizeof(int4), 0);
   ENS(zmm, 2 * U, sizeof(int32_t), 2 * keepU);
-  ENS(bincnt, NB, sizeof(int32_t), keepB);
   ENS(binbeg, NB, sizeof(int32_t), keepB);
   ENS(yz, N, sizeof(float2), keepN);
   ENS(sid, N, sizeof(int32_t), keepN);
@@ -557,6 +559,10 @@ int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int 
   P.own_pct = params->own_frac_pct;
   P.inflate = params->refit_inflate;
   P.hits_per_bin = params->grid_hits_per_bin;
+  P.kf_pool = 64;
+  P.kf_blocks_per_cu = 0;
+  P.link_blocks_per_cu = 0;
+  P.kf_min_waves = 0;
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -589,7 +595,8 @@ int tpcca_destroy(tpcca_ctx_t *c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   DevBuf *all[] = {&c->row_x_d, &c->units_d, &c->chunks_d, &c->runs_d, &c->rowtab, &c->row_cnt,
-                   &c->zmm, &c->bincnt, &c->binbeg, &c->yz, &c->sid, &c->up, &c->dn, &c->upc,
+                   &c->row_fill, &c->rtmp,
+                   &c->zmm, &c->binbeg, &c->yz, &c->sid, &c->up, &c->dn, &c->upc,
                    &c->dnc, &c->flag, &c->starts, &c->chunk_nstart, &c->tiles, &c->sval, &c->tofg, &c->kf_order, &c->srow, &c->cinfo, &c->trk_start, &c->trk_unit, &c->unit_tbegin, &c->trk,
                    &c->trk_hits, &c->owner, &c->accv, &c->wonmask, &c->accx, &c->tracks, &c->hits_out,
                    &c->assign, &c->unit_res, &c->scan_tmp, &c->in_cl, &c->in_row};
@@ -1000,6 +1007,36 @@ int tpcca_device_results(tpcca_ctx_t *c, tpcca_device_results_t *out) {
   out->assignment = ptr<int32_t>(c->assign);
   out->units = ptr<tpcca_unit_result_t>(c->unit_res);
   out->n_units = (int32_t)c->units.size();
+  return TPCCA_OK;
+}
+
+int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
+  if (!c || !t) return TPCCA_EINVAL;
+  if (t->fit_pool < 0 || t->fit_pool > 4096 || t->fit_blocks_per_cu < 0 || t->grid_hits_per_bin < 0 ||
+      t->link_blocks_per_cu < 0 || t->fit_min_waves < 0)
+    return TPCCA_EINVAL;
+  // the grid layout of loaded units depends on hits per bin
+  if (t->grid_hits_per_bin && !c->units.empty() && t->grid_hits_per_bin != c->P.hits_per_bin)
+    return TPCCA_ESTATE;
+  c->P.kf_min_waves = t->fit_min_waves;
+  c->P.kf_pool = t->fit_pool ? t->fit_pool : 64;
+  c->P.kf_blocks_per_cu = t->fit_blocks_per_cu;
+  c->P.link_blocks_per_cu = t->link_blocks_per_cu;
+  if (t->grid_hits_per_bin) {
+    c->P.hits_per_bin = t->grid_hits_per_bin;
+    c->params.grid_hits_per_bin = t->grid_hits_per_bin;
+  }
+  c->gen_captured = -1;  // launch shapes changed: capture the graph again
+  return TPCCA_OK;
+}
+
+int tpcca_get_tuning(tpcca_ctx_t *c, tpcca_tuning_t *t) {
+  if (!c || !t) return TPCCA_EINVAL;
+  t->fit_pool = c->P.kf_pool;
+  t->fit_blocks_per_cu = c->P.kf_blocks_per_cu;
+  t->grid_hits_per_bin = c->P.hits_per_bin;
+  t->link_blocks_per_cu = c->P.link_blocks_per_cu;
+  t->fit_min_waves = c->P.kf_min_waves;
   return TPCCA_OK;
 }
 

@@ -57,6 +57,14 @@ class WorkStats(ctypes.Structure):
                 ("fit_steps", c_i64), ("fit_candidates", c_i64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("fit_pool", c_i32), ("fit_blocks_per_cu", c_i32), ("grid_hits_per_bin", c_i32),
+                ("link_blocks_per_cu", c_i32), ("fit_min_waves", c_i32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Timeframe(ctypes.Structure):
     _fields_ = [("n_units", c_i32), ("sector", c_vp), ("begin", c_vp), ("n", c_vp), ("cl", c_vp),
                 ("row", c_vp), ("tracks", c_vp), ("tracks_cap", c_i64), ("hits", c_vp),
@@ -95,7 +103,7 @@ SYMBOLS = (
     "tpcca_last_error", "tpcca_stage_times", "tpcca_set_timing", "tpcca_server_create",
     "tpcca_server_submit", "tpcca_server_poll", "tpcca_server_wait", "tpcca_server_release",
     "tpcca_server_stats", "tpcca_server_reset_stats", "tpcca_server_destroy", "tpcca_now",
-    "tpcca_work_stats",
+    "tpcca_work_stats", "tpcca_set_tuning", "tpcca_get_tuning",
 )
 
 _lib = None
@@ -147,6 +155,8 @@ def lib():
         "tpcca_server_destroy": (c_i32, [c_vp]),
         "tpcca_now": (ctypes.c_double, []),
         "tpcca_work_stats": (c_i32, [c_vp, ctypes.POINTER(WorkStats)]),
+        "tpcca_set_tuning": (c_i32, [c_vp, ctypes.POINTER(Tuning)]),
+        "tpcca_get_tuning": (c_i32, [c_vp, ctypes.POINTER(Tuning)]),
     }
     missing = [n for n in SYMBOLS if not hasattr(L, n)]
     if missing:
@@ -341,6 +351,18 @@ class Context:
         d = DeviceResults()
         _check(lib().tpcca_device_results(self.h, ctypes.byref(d)), "tpcca_device_results", self.h)
         return d
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        lib().tpcca_get_tuning(self.h, ctypes.byref(t))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        _check(lib().tpcca_set_tuning(self.h, ctypes.byref(t)), "tpcca_set_tuning", self.h)
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().tpcca_get_tuning(self.h, ctypes.byref(t)), "tpcca_get_tuning", self.h)
+        return t.as_dict()
 
     def set_timing(self, on=True):
         lib().tpcca_set_timing(self.h, 1 if on else 0)

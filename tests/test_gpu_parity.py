@@ -122,6 +122,37 @@ def test_batch_equals_sector_by_sector(tpcca, row_x):
             assert np.array_equal(a, asg[c0:c0 + cl.shape[0]])
 
 
+@pytest.mark.parametrize("knobs", [
+    dict(fit_pool=16, fit_min_waves=0, grid_hits_per_bin=2, link_blocks_per_cu=8),
+    dict(fit_pool=128, fit_min_waves=6, grid_hits_per_bin=1, link_blocks_per_cu=16),
+    dict(fit_pool=32, fit_min_waves=8, fit_blocks_per_cu=2, grid_hits_per_bin=4, link_blocks_per_cu=32),
+])
+def test_schedule_does_not_change_results(tpcca, row_x, knobs):
+    """Every launch schedule gives the default schedule's bytes and the oracle's results."""
+    b = tpcgen.minbias_batch(seed=6, n_events=3)
+    print(f"schedule {knobs}: {b.n_clusters} clusters", flush=True)
+    with tpcca.Context(row_x) as ctx:
+        ctx.run_batch(b.cl, b.row, b.units, graph=True)
+        base = [a.copy() for a in ctx.get_batch_results()]
+    with tpcca.Context(row_x) as ctx:
+        ctx.set_tuning(**knobs)
+        assert all(ctx.get_tuning()[k] == v for k, v in knobs.items())
+        for graph in (False, True):
+            ctx.run_batch(b.cl, b.row, b.units, graph=graph)
+            got = ctx.get_batch_results()
+            for x, y in zip(base, got):
+                assert x.tobytes() == y.tobytes()
+    refs = _parity.oracle_units(b, row_x, which={0, 20, 50})
+    units, tracks, hits, asg = base
+    for u in (0, 20, 50):
+        ur = units[u]
+        t0, nt = int(ur["track_begin"]), int(ur["n_tracks"])
+        h0, nh = int(ur["hit_begin"]), int(ur["n_track_hits"])
+        c0, n = int(ur["cluster_begin"]), int(b.units[u, 1])
+        _parity.compare_tracks(tracks[t0:t0 + nt], hits[h0:h0 + nh], refs[u])
+        assert np.array_equal(asg[c0:c0 + n], refs[u].assignment)
+
+
 def _edge_units(row_x):
     rng = np.random.default_rng(9)
     units = []
