@@ -54,7 +54,8 @@ TRACKLET_DTYPE = np.dtype([
 
 
 class _Stats(ctypes.Structure):
-    _fields_ = [("decisions", ctypes.c_int64), ("near_ties", ctypes.c_int64), ("min_margin", ctypes.c_double)]
+    _fields_ = [("decisions", ctypes.c_int64), ("near_ties", ctypes.c_int64), ("min_margin", ctypes.c_double),
+                ("propagations", ctypes.c_int64), ("tests", ctypes.c_int64), ("updates", ctypes.c_int64)]
 
 
 _lib = None
@@ -118,6 +119,7 @@ class SectorResult:
     decisions: int
     near_ties: int
     min_margin: float
+    work: dict = None            # fit work: propagations, tests, updates
 
     @property
     def n_tracks(self) -> int:
@@ -166,7 +168,8 @@ def run_sector(cl: np.ndarray, row: np.ndarray, row_x: np.ndarray, params: Param
     finally:
         L.tpcref_free(h)
     return SectorResult(up_raw, dn_raw, up, dn, tr, tb, th[:tb[-1]], ki, kb, kh[:kb[-1]], asg,
-                        st.decisions, st.near_ties, st.min_margin)
+                        st.decisions, st.near_ties, st.min_margin,
+                        {"propagations": st.propagations, "tests": st.tests, "updates": st.updates})
 
 
 def refit(cl, row, row_x, hits, k0, n_chain, params=None, precision=64):

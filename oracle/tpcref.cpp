@@ -32,6 +32,8 @@ namespace {
    different rounding could flip the outcome. */
 struct Margins {
   int64_t decisions = 0, near = 0;
+  /* work of the fits: propagations, chi2 tests of searched hits, updates */
+  int64_t props = 0, tests = 0, updates = 0;
   double min_margin = std::numeric_limits<double>::infinity();
   void note(double a, double b) {
     double d = std::fabs(a - b);
@@ -441,7 +443,9 @@ void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F>
   F c2;
   for (int k = 1; k <= L; ++k) {
     const int h = chain[k];
+    ++mg.props;
     if (!propagate(P, st, S.rx[S.row[h]], &mg)) return;
+    ++mg.updates;
     if (!update(P, st, S.y[h], S.z[h], c2)) return;
   }
   State<F> saved = st;
@@ -450,13 +454,16 @@ void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F>
   if (!rp) {
     int miss = 0;
     for (int r = row_out + 1; r < P.n_rows; ++r) {
+      ++mg.props;
       if (!propagate(P, st, S.rx[r], &mg)) break;
       const int h = search_row(S, st, r, mg);
       bool took = false;
       if (h >= 0) {
         F c;
+        ++mg.tests;
         if (chi2_2d(P, st, S.y[h], S.z[h], c)) {
           mg.note((double)c, (double)P.pick_chi2);
+          if (c <= P.pick_chi2) ++mg.updates;
           if (c <= P.pick_chi2 && update(P, st, S.y[h], S.z[h], c2)) {
             pass1.push_back(h);
             saved = st;
@@ -503,7 +510,9 @@ void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F>
   const int n1 = (int)pass1.size();
   for (int k = n1 - 1; k >= 0; --k) {
     const int h = pass1[k];
+    if (k < n1 - 1) ++mg.props;
     if (k < n1 - 1 && !propagate(P, st, S.rx[S.row[h]], &mg)) return;
+    ++mg.updates;
     if (!update(P, st, S.y[h], S.z[h], c2)) return;
     chi2 = chi2 + c2;
   }
@@ -512,13 +521,16 @@ void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F>
   if (!rp) {
     int miss = 0;
     for (int r = S.row[h0] - 1; r >= 0; --r) {
+      ++mg.props;
       if (!propagate(P, st, S.rx[r], &mg)) break;
       const int h = search_row(S, st, r, mg);
       bool took = false;
       if (h >= 0) {
         F c;
+        ++mg.tests;
         if (chi2_2d(P, st, S.y[h], S.z[h], c)) {
           mg.note((double)c, (double)P.pick_chi2);
+          if (c <= P.pick_chi2) ++mg.updates;
           if (c <= P.pick_chi2 && update(P, st, S.y[h], S.z[h], c2)) {
             chi2 = chi2 + c2;
             inward.push_back(h);
@@ -794,6 +806,9 @@ void tpcref_get_stats(const void *r, tpcref_stats_t *s) {
   s->decisions = R->mg.decisions;
   s->near_ties = R->mg.near;
   s->min_margin = R->mg.min_margin;
+  s->propagations = R->mg.props;
+  s->tests = R->mg.tests;
+  s->updates = R->mg.updates;
 }
 
 int32_t tpcref_refit(const tpcref_params_t *p, const float *row_x, const float *cl,

@@ -66,6 +66,9 @@ typedef struct {
   int64_t decisions;  /* comparisons whose outcome shaped the result */
   int64_t near_ties;  /* of those, relative margin below 1e-6 */
   double min_margin;
+  int64_t propagations; /* Kalman row steps of the fits (incl. failed ones) */
+  int64_t tests;        /* chi2 tests of hits picked by the searches */
+  int64_t updates;      /* Kalman updates attempted */
 } tpcref_stats_t;
 
 void tpcref_params_default(tpcref_params_t *p);

@@ -430,6 +430,45 @@ def _invariants(res, cl, row, P):
     assert np.all(np.diff(res.tracklets["start_id"][res.track_tracklet]) > 0)
 
 
+def _predicted_work(res, row, P):
+    """Propagations and updates each fitted tracklet takes by the row rules
+    of the fit (Fig. 1c): the chain's hits one by one, outward until
+    max_miss empty rows follow the outermost hit or the last row, the refit
+    through the pass-1 hits, inward likewise; every update succeeds (S is
+    positive definite).  Valid when no propagation leaves the sector."""
+    R, mm = P.n_rows, P.max_miss
+    props = upd = acc_search = 0
+    for T in res.tracklets:
+        assert T["status"] != 2
+        r0 = int(row[T["start_id"]])
+        nc, n1, ne = int(T["n_chain"]), int(T["n_pass1"]), int(T["n_hits"] - T["n_pass1"])
+        chain_end = r0 + nc - 1
+        props += (nc - 1) + (min(int(T["row_out"]) + mm, R - 1) - chain_end)
+        props += (n1 - 1) + (r0 - max(int(T["row_ref"]) - mm, 0))
+        upd += (nc - 1) + (n1 - nc) + n1 + ne
+        acc_search += (n1 - nc) + ne
+    return props, upd, acc_search
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.1])
+def test_fit_work_counts_follow_the_row_rules(row_x, sigma):
+    """The oracle's work counters (the basis of the fit's FLOP count) equal
+    what the row rules predict from the tracklets it returns."""
+    P = oracle.default_params()
+    for seed in (2, 3):
+        b = tpcgen.one_sector(seed=seed, sigma=sigma, n_tracks=120)
+        cl, row, _, _, _ = b.unit(0)
+        res = oracle.run_sector(cl, row, row_x, P)
+        props, upd, acc_search = _predicted_work(res, row, P)
+        assert res.tracklets.shape[0] > 20
+        assert res.work["propagations"] == props
+        assert res.work["updates"] == upd
+        # every searched hit that was taken passed one chi2 test
+        assert res.work["tests"] >= acc_search
+        if sigma == 0.0:
+            assert res.work["tests"] == acc_search
+
+
 def test_invariants_central_sector(row_x):
     b = tpcgen.central_event(seed=1, n_tracks=8000)
     P = oracle.default_params()
