@@ -32,7 +32,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3     # published vector FP32 (packed); 78.6 without packed FP32
 LINK_BYTES_PER_CLUSTER = 16  # read y, z (8 B) + write up, down (8 B)
+# FP32 operations of the fit per counted event (fma = 2, div / sqrt = 1):
+FIT_FLOPS = {
+    "fit_steps": 154,       # propagation: 52 state + 102 covariance
+    "fit_tests": 20,        # chi2 of a searched hit
+    "fit_updates": 130,     # Kalman update: gain, state, covariance, chi2
+    "fit_candidates": 5,    # window candidate: residuals and squared distance
+}
 
 
 def log(*a):
@@ -50,11 +58,16 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3")
     ap.add_argument("--retune", action="store_true", help="re-run the schedule autotuner")
+    ap.add_argument("--summarize-profile", nargs=4, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "COMMAND"),
+                    help="write the profiles/ summaries from rocprofv3 outputs of --profile runs")
     return ap.parse_args()
 
 
 def main():
     args = parse()
+    if args.summarize_profile:
+        summarize_profile(*args.summarize_profile)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this tracker runs on one GPU; multi-GPU runs are not part of this build "
               "(sectors and time frames are independent: see the sharding note in DESIGN.md)",
@@ -100,34 +113,36 @@ def main():
     # ------------------------------------------------- batched (headline)
     ctx = tpcca.Context(rx, device=0)
     from paper_1709_00618_amd import autotune
-    knobs, knob_src = autotune.tuned(ctx, dcl, drow, tf.units, tf.n_clusters, log=log, retune=args.retune)
+    if args.profile:  # never tune under a profiler
+        entry = autotune.lookup(tf.n_clusters, len(tf.units))
+        knobs, knob_src = (entry["knobs"], "cache") if entry else (ctx.get_tuning(), "default")
+        ctx.set_tuning(**knobs)
+    else:
+        knobs, knob_src = autotune.tuned(ctx, dcl, drow, tf.units, tf.n_clusters, log=log, retune=args.retune)
     log(f"schedule ({knob_src}): {knobs}")
+    # the captured graph carries HIP event nodes at the stage boundaries, on
+    # the stream the kernels run on: every timed replay times its own stages
+    ctx.set_timing(True)
     for _ in range(args.warmup):
         ctx.run_batch(dcl, drow, tf.units, device=True, graph=True)
         ctx.sync()
     torch.cuda.synchronize()
+    stage_runs = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ctx.run_batch(dcl, drow, tf.units, device=True, graph=True)
         ctx.sync()
+        stage_runs.append(ctx.stage_times())
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    ctx.set_timing(False)
     nu, ncl, ntr, nhits = ctx.batch_totals()
     work = ctx.work_stats()
     batched = ncl / dt
     log(f"batched time frame: {dt * 1e3:.2f} ms/step, {batched / 1e9:.3f} G clusters/s, "
         f"{ntr} tracks, {nhits} assigned clusters; work {work}")
-
-    # ------------------------------------- instrumented pass: stage times
-    ctx.set_timing(True)
-    stage_runs = []
-    for _ in range(max(3, args.steps // 2)):
-        ctx.run_batch(dcl, drow, tf.units, device=True, graph=False)
-        ctx.sync()
-        stage_runs.append(ctx.stage_times())
-    ctx.set_timing(False)
     stages = {k: float(np.mean([s[k] for s in stage_runs])) for k in stage_runs[0]}
-    log("stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
+    log("stage ms (timed replays): " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
 
     # --------------------------------------------- per-event plain path
     pe = tpcca.Context(rx, device=0)
@@ -162,12 +177,23 @@ def main():
     ctx.close()
 
     # ---------------------------------------------------------- roofline
+    # dominant kernel: the Kalman fit (ALU / latency bound)
+    traffic = measured_traffic()
+    fit_ms = stages["fit"]
+    flops = sum(FIT_FLOPS[k] * work[k] for k in FIT_FLOPS)
+    fit_tf = flops / (fit_ms * 1e-3) / 1e12
+    roofline = {"kernel": "k_kf (tracklet fit and track following)", "bound": "alu",
+                "achieved": round(fit_tf, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(fit_tf / FP32_PEAK_TFLOPS, 4),
+                "traffic": traffic.get("k_kf"), "flops_per_launch": int(flops),
+                "flops_per_step": round(flops / max(1, work["fit_steps"]), 1), "ms": round(fit_ms, 4)}
     link_ms = stages["links"]
     link_bytes = LINK_BYTES_PER_CLUSTER * ncl
     link_gbs = link_bytes / (link_ms * 1e-3) / 1e9
-    roofline = {"kernel": "k_links (CA neighbour finding)", "bound": "hbm", "achieved": round(link_gbs, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(link_gbs / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_cluster": LINK_BYTES_PER_CLUSTER, "ms": round(link_ms, 4)}
+    roofline_links = {"kernel": "k_links (CA neighbour finding)", "bound": "hbm", "achieved": round(link_gbs, 1),
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(link_gbs / HBM_PEAK_GBS, 4),
+                      "traffic": traffic.get("k_links"), "bytes_per_cluster": LINK_BYTES_PER_CLUSTER,
+                      "ms": round(link_ms, 4)}
 
     # ------------------------------------------------------ cpu baseline
     cpu = None
@@ -200,9 +226,126 @@ def main():
         "served": served,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roofline,
+        "roofline_links": roofline_links,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_timeframe128.json")
+KERNEL_SOURCES = ("paper_1709_00618_amd/csrc/tpcca_kernels.hip", "paper_1709_00618_amd/csrc/tpcca_internal.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of each kernel from the committed counter passes,
+    only while the kernel sources are the ones the counters were taken on."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return {}
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_source_hash():
+        return {}
+    return {k: v["bytes"] for k, v in t["kernels"].items()}
+
+
+def summarize_profile(trace_dir, fetch_dir, write_dir, command):
+    """Turn the rocprofv3 outputs of `bench.py --profile` (a kernel trace and
+    FETCH_SIZE / WRITE_SIZE passes) into the committed summaries: per-kernel
+    durations of the time-frame dispatches and counter bytes scaled by the
+    plain 1 GiB device copy that the profile run makes first."""
+    import csv
+    import glob
+
+    def one(d, pat):
+        fs = glob.glob(os.path.join(d, "**", pat), recursive=True)
+        assert fs, f"no {pat} under {d}"
+        return fs[0]
+
+    def short(name):
+        n = name.split("(")[0].replace("void ", "").strip()
+        return n.replace("tpcca::", "")
+
+    # kernel trace: time-frame dispatches are the first (warmup + steps) of each kernel
+    rows = sorted(csv.DictReader(open(one(trace_dir, "*kernel_trace.csv"))), key=lambda r: int(r["Dispatch_Id"]))
+    per = {}
+    for r in rows:
+        per.setdefault(short(r["Kernel_Name"]), []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    tf_n = 4  # bench.py --profile: 1 warm-up + 3 timed replays of the time frame
+    lines = ["| kernel | TF dispatches | avg us (TF) | share | other dispatches | avg us (other) |",
+             "|---|---|---|---|---|---|"]
+    tf_tot = {k: sum(v[:tf_n]) for k, v in per.items() if k.startswith("k_")}
+    total = sum(tf_tot.values())
+    for k in sorted(tf_tot, key=lambda k: -tf_tot[k]):
+        v = per[k]
+        a, b = v[:tf_n], v[tf_n:]
+        lines.append(f"| {k} | {len(a)} | {np.mean(a):.1f} | {100 * tf_tot[k] / total:.1f}% | {len(b)} | "
+                     f"{(np.mean(b) if b else 0):.1f} |")
+
+    def counters(d, name):
+        vals = {}
+        for r in csv.DictReader(open(one(d, "*counter_collection.csv"))):
+            if r["Counter_Name"] != name:
+                continue
+            vals.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+        return [vals[k] for k in sorted(vals)]
+
+    out = {"source_hash": kernel_source_hash(), "command": command, "kernels": {}}
+    fac = {}
+    for cname, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        seq = counters(d, cname)
+        # the calibration copy: 1 GiB read and written; first dispatches before any tracker kernel
+        cal = []
+        for name, v in seq:
+            if "tpcca" in name:
+                break
+            cal.append((name, v))
+        big = [v for name, v in cal if v > 0.5 * (1 << 20)]  # KiB
+        fac[cname] = (1 << 20) / float(np.median(big)) if big else 1.0
+        byk = {}
+        for name, v in seq:
+            if "tpcca" in name:
+                byk.setdefault(short(name), []).append(v * 1024.0 * fac[cname])
+        for k, v in byk.items():
+            e = out["kernels"].setdefault(k, {})
+            e[cname.lower()] = float(np.mean(v[:tf_n]))
+    for k, e in out["kernels"].items():
+        e["bytes"] = e.get("fetch_size", 0.0) + e.get("write_size", 0.0)
+    out["factor"] = fac
+    # the fit kernel is reported under one name whatever its register variant
+    for k in list(out["kernels"]):
+        if k.startswith("k_kf<"):
+            out["kernels"]["k_kf"] = out["kernels"][k]
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    md = ["# Kernel trace and HBM traffic: batched time frame (128 events, 32.5 M clusters)", "",
+          "Command (repository root on the GPU box; `$R` = repository root):", "", "```", command, "```", "",
+          "`bench.py --profile`: a 1 GiB device copy (counter calibration), then 1 warm-up + 3 timed graph "
+          "replays of the time frame (the TF dispatches below), then the per-event path (other dispatches).", "",
+          "## Durations (kernel trace)", ""] + lines + ["",
+          f"Sum of TF kernel time over {tf_n} replays: {total / 1e3:.2f} ms ({total / tf_n / 1e3:.2f} ms per replay).",
+          "", "## HBM traffic per TF dispatch (FETCH_SIZE + WRITE_SIZE, scaled by the copy)", "",
+          f"Scale factors (1 GiB / counter reading of the copy): FETCH {fac['FETCH_SIZE']:.4f}, "
+          f"WRITE {fac['WRITE_SIZE']:.4f}.", "",
+          "| kernel | fetch MB | write MB | total MB |", "|---|---|---|---|"]
+    for k in sorted(out["kernels"], key=lambda k: -out["kernels"][k]["bytes"]):
+        e = out["kernels"][k]
+        md.append(f"| {k} | {e.get('fetch_size', 0) / 1e6:.1f} | {e.get('write_size', 0) / 1e6:.1f} | "
+                  f"{e['bytes'] / 1e6:.1f} |")
+    md += ["", f"Kernel sources hash: `{out['source_hash']}` (bench.py reports traffic only while it matches)."]
+    path = os.path.join(ROOT, "profiles", "tracker_timeframe128_kernel_trace.md")
+    with open(path, "w") as f:
+        f.write("\n".join(md) + "\n")
+    print(f"wrote {path} and {TRAFFIC_FILE}")
 
 
 def cpu_baseline(ev, rx, seconds):

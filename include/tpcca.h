@@ -217,10 +217,11 @@ int tpcca_batch_totals(tpcca_ctx_t *ctx, int32_t *n_units, int64_t *n_clusters, 
                        int64_t *n_hits);
 /* Work counters of everything processed since the last reset (synchronises):
    clusters, tracklets (fitted candidates), accepted tracks and their hits,
-   Kalman row steps (propagations) and candidate clusters examined by the
-   track-following searches. */
+   Kalman row steps (propagations), candidate clusters examined by the
+   track-following searches, chi2 tests of the hits those searches picked,
+   and Kalman updates. */
 typedef struct {
-  int64_t clusters, tracklets, tracks, track_hits, fit_steps, fit_candidates;
+  int64_t clusters, tracklets, tracks, track_hits, fit_steps, fit_candidates, fit_tests, fit_updates;
 } tpcca_work_stats_t;
 int tpcca_work_stats(tpcca_ctx_t *ctx, tpcca_work_stats_t *out);
 
@@ -236,7 +237,11 @@ typedef struct {
   int32_t fit_blocks_per_cu; /* resident fit blocks per CU (0: occupancy limit) */
   int32_t grid_hits_per_bin; /* z-bin occupancy of the row grid (1); applies after reset */
   int32_t link_blocks_per_cu;/* resident neighbour-finding blocks per CU (0: 32) */
-  int32_t fit_min_waves;     /* register budget of the fit kernel: 0 compiler's, 6 or 8 waves/SIMD */
+  int32_t fit_min_waves;     /* register budget of the fit kernel in resident waves per SIMD: 0 (5), 6 or 8 */
+  int32_t fit_claims;        /* 1: the fit kernel writes the selection's claims as tracklets end
+                                (default); 0: a claim kernel of its own */
+  int32_t fit_xcd_slices;    /* 1: the fit's processing order is cut into one slice per XCD;
+                                0: one shared work counter (default) */
 } tpcca_tuning_t;
 int tpcca_set_tuning(tpcca_ctx_t *ctx, const tpcca_tuning_t *t);
 int tpcca_get_tuning(tpcca_ctx_t *ctx, tpcca_tuning_t *t);
@@ -247,9 +252,12 @@ const char *tpcca_last_error(tpcca_ctx_t *ctx);
 
 /* Stage timing of the last full stage sequence on ctx's stream, via HIP
    events (ms): 0 grid, 1 links (the neighbour kernel alone), 2 clean,
-   3 chains (compaction), 4 Kalman fit (the fit kernel alone), 5 selection.
-   Graph replays record only the whole graph (entry 0).  Returns the number
-   of entries written (0 if timing was off). */
+   3 chains (compaction), 4 Kalman fit (the fit kernel and the clearing of
+   the claim words it writes), 5 selection.  With timing on, a graph run of
+   tpcca_run_batch replays one graph per stage with the events between them
+   on ctx's stream, so each replay times its own stages (the graphs are
+   captured again when timing is switched).  Valid after tpcca_sync; returns
+   the number of entries written (0 if timing was off). */
 int tpcca_stage_times(tpcca_ctx_t *ctx, float *ms, int32_t cap);
 /* Enable/disable per-stage event recording (off by default). */
 int tpcca_set_timing(tpcca_ctx_t *ctx, int32_t enable);

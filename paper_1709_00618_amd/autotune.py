@@ -20,9 +20,9 @@ CACHE = os.path.join(HERE, "tuning_cache.json")
 
 SPACE = {
     "fit_pool": [32, 64, 128],
-    "fit_min_waves": [0, 6, 8],
-    "grid_hits_per_bin": [1, 2],
-    "link_blocks_per_cu": [16, 32],
+    "fit_min_waves": [0, 6],
+    "fit_claims": [0, 1],
+    "fit_xcd_slices": [0, 1],
 }
 
 
@@ -111,5 +111,5 @@ def tuned(ctx, cl, row, units, n_clusters, device=True, log=None, retune=False):
 
 
 def _default(table):
-    d = {"fit_pool": 64, "fit_min_waves": 0, "grid_hits_per_bin": 1, "link_blocks_per_cu": 32}
+    d = {"fit_pool": 64, "fit_min_waves": 0, "fit_claims": 1, "fit_xcd_slices": 0}
     return d if any(k == d for _, k in table) else None

@@ -13,6 +13,7 @@ constexpr int kChunk = 1024;        // clusters per chunk (block work unit)
 constexpr int kBlock = 256;         // threads per block of the cluster kernels
 constexpr int kScanTile = 2048;     // elements per tile of the device scans
 constexpr int kKfBlock = 128;       // threads per block of the Kalman filter
+constexpr int kXcds = 8;            // XCDs of the chip (blocks are dealt round-robin)
 
 // One (slot, sector) unit.  Work arrays are indexed by global cluster index:
 // the unit owns [cl_begin, cl_begin + n) of every per-cluster array.
@@ -65,10 +66,12 @@ struct RunDev {
   int32_t n_acc;
   int64_t n_acc_hits;
   int32_t err;          // 1: invalid cluster seen
-  int32_t kf_next;      // work counter of the fit kernel
+  int32_t kf_next[8];   // work counters of the fit kernel, one per slice of the order
   int32_t n_starts;     // chain start hits found by the cleaning kernel
   unsigned long long kf_steps;   // row steps of the fit (propagations)
   unsigned long long kf_cands;   // candidate hits examined by the fit's searches
+  unsigned long long kf_tests;   // chi2 tests of searched hits
+  unsigned long long kf_updates; // Kalman updates
 };
 
 // Device-side parameters (FP32 copies of tpcca_params_t).
@@ -85,6 +88,8 @@ struct ParamsDev {
   int32_t kf_blocks_per_cu;
   int32_t link_blocks_per_cu;
   int32_t kf_min_waves;
+  int32_t kf_claims;   // 1: the fit writes the selection's claims, 0: a kernel of its own
+  int32_t kf_xcd;      // 1: the fit's order is cut into one slice per XCD
 };
 
 // Device buffers of a context (all indices global).
@@ -106,8 +111,7 @@ struct Bufs {
   int32_t *up, *dn;      // raw links (sorted indices)
   int32_t *upc, *dnc;    // cleaned links
   int32_t *flag;         // by global cluster index: start sorted index + 1, or 0
-  int2 *starts;          // chain start hits: (sorted index, flag index), per chunk region
-  int32_t *chunk_nstart; // start hits found in each chunk
+  int2 *starts;          // chain start hits of a run: (sorted index, flag index)
   int4 *tiles;           // (unit, row, first sorted hit, count) row tiles
   uint8_t *sval;         // sorted: 1 if the hit starts a tracklet
   int32_t *tofg;         // sorted start hit -> tracklet

@@ -124,10 +124,12 @@ __global__ void k_run_reset(Bufs B, int run, int R) {
     rd.n_acc = 0;
     rd.n_acc_hits = 0;
     rd.err = 0;
-    rd.kf_next = 0;
+    for (int q = 0; q < kXcds; ++q) rd.kf_next[q] = 0;
     rd.n_starts = 0;
     rd.kf_steps = 0;
     rd.kf_cands = 0;
+    rd.kf_tests = 0;
+    rd.kf_updates = 0;
   }
 }
 
@@ -550,58 +552,69 @@ __global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
 
 // ---------------------------------------------------------------- clean ---
 // Fig. 1b: keep a link only if its partner links back; a hit with an up
-// link and no down link starts a chain and is listed in its chunk's region
-// of the start list (an LDS counter per chunk, no global atomics).
+// link and no down link starts a chain.  Each chunk lists its start hits in
+// its own region of a staging array (an LDS counter, no global atomics) and
+// stores their count for the scan that compacts the lists.
 __global__ __launch_bounds__(kBlock) void k_clean(Bufs B, int run) {
   __shared__ int cnt;
   const RunDev &rd = B.runs[run];
+  int2 *stage = reinterpret_cast<int2 *>(B.rtmp);  // free after the grid stage
   for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
     const Chunk ch = B.chunks[c];
     const UnitDev U = B.units[ch.unit];
-    const int base = U.cl_begin + ch.begin;
+    const int cb = U.cl_begin + ch.begin;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
-      const int g = base + i;
+      const int g = cb + i;
       const int u = B.up[g], d = B.dn[g];
       const int uc = (u >= 0 && B.dn[u] == g) ? u : -1;
       const int dc = (d >= 0 && B.up[d] == g) ? d : -1;
       B.upc[g] = uc;
       B.dnc[g] = dc;
-      if (uc >= 0 && dc < 0) {
-        const int k = atomicAdd(&cnt, 1);
-        B.starts[base + k] = make_int2(g, U.cl_begin + B.sid[g]);
-      }
+      if (uc >= 0 && dc < 0) stage[cb + atomicAdd(&cnt, 1)] = make_int2(g, U.cl_begin + B.sid[g]);
     }
     __syncthreads();
-    if (threadIdx.x == 0) B.chunk_nstart[c] = cnt;
+    if (threadIdx.x == 0) B.scan_tmp[c - rd.c0] = cnt;
     __syncthreads();
+  }
+}
+
+// The chunks' start lists, concatenated into the run's list at the scanned
+// offsets (block per chunk).
+__global__ __launch_bounds__(kBlock) void k_starts_compact(Bufs B, int run) {
+  RunDev &rd = B.runs[run];
+  const int2 *stage = reinterpret_cast<const int2 *>(B.rtmp);
+  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
+    const Chunk ch = B.chunks[c];
+    const int cb = B.units[ch.unit].cl_begin + ch.begin;
+    const int64_t off = B.scan_tmp[c - rd.c0];
+    const int n = (int)(B.scan_tmp[c - rd.c0 + 1] - off);
+    for (int k = threadIdx.x; k < n; k += blockDim.x) B.starts[rd.cl0 + off + k] = stage[cb + k];
+    if (c == rd.c1 - 1 && threadIdx.x == 0) rd.n_starts = (int32_t)B.scan_tmp[rd.c1 - rd.c0];
   }
 }
 
 // Chains: follow the cleaned up links from every start hit; a chain of at
 // least min_chain hits marks its start in cluster-ID order (flag = sorted
-// index + 1) and records (last hit, length).  One wave per chunk.
-__global__ __launch_bounds__(64) void k_chain(Bufs B, ParamsDev P, int run) {
+// index + 1) and records (last hit, length).  Thread per start hit of the
+// run's list, so that every resident lane chases a chain.
+__global__ __launch_bounds__(kBlock) void k_chain(Bufs B, ParamsDev P, int run) {
   const RunDev &rd = B.runs[run];
-  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
-    const Chunk ch = B.chunks[c];
-    const int base = B.units[ch.unit].cl_begin + ch.begin;
-    const int ns = B.chunk_nstart[c];
-    for (int k = threadIdx.x; k < ns; k += blockDim.x) {
-      const int2 st = B.starts[base + k];
-      const int g = st.x;
-      int n = 1, last = g, nx = B.upc[g];
-      for (int s = 0; nx >= 0 && s < P.n_rows; ++s) {
-        ++n;
-        last = nx;
-        nx = B.upc[nx];
-      }
-      if (n >= P.min_chain) {
-        B.flag[st.y] = g + 1;
-        B.cinfo[g] = make_int2(last, n);
-        B.sval[g] = 1;
-      }
+  const int ns = rd.n_starts;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns; k += gridDim.x * blockDim.x) {
+    const int2 st = B.starts[rd.cl0 + k];
+    const int g = st.x;
+    int n = 1, last = g, nx = B.upc[g];
+    for (int s = 0; nx >= 0 && s < P.n_rows; ++s) {
+      ++n;
+      last = nx;
+      nx = B.upc[nx];
+    }
+    if (n >= P.min_chain) {
+      B.flag[st.y] = g + 1;
+      B.cinfo[g] = make_int2(last, n);
+      B.sval[g] = 1;
     }
   }
 }
@@ -894,16 +907,24 @@ __device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, cons
   int best = -1;
   float bd2 = __builtin_inff();
   cands += (unsigned int)(e - b);
-  for (int i = b; i < e; ++i) {
-    const float2 c = B.yz[i];
-    if (!(fabsf(c.x - s.p[0]) <= wy && fabsf(c.y - s.p[1]) <= wz)) continue;
-    const float dy = c.x - s.p[0];
-    const float dz = c.y - s.p[1];
-    const float d2 = __builtin_fmaf(dy, dy, dz * dz);
-    // equal distances (rare) are decided by the lower cluster ID
-    if (d2 < bd2 || (d2 == bd2 && B.sid[i] < B.sid[best])) {
-      bd2 = d2;
-      best = i;
+  // candidates in ascending sorted index, loaded two at a time (independent
+  // loads in flight); the evaluation order is unchanged
+  for (int i0 = b; i0 < e; i0 += 2) {
+    float2 c[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) c[q] = i0 + q < e ? B.yz[i0 + q] : make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int i = i0 + q;
+      if (!(i < e && fabsf(c[q].x - s.p[0]) <= wy && fabsf(c[q].y - s.p[1]) <= wz)) continue;
+      const float dy = c[q].x - s.p[0];
+      const float dz = c[q].y - s.p[1];
+      const float d2 = __builtin_fmaf(dy, dy, dz * dz);
+      // equal distances (rare) are decided by the lower cluster ID
+      if (d2 < bd2 || (d2 == bd2 && B.sid[i] < B.sid[best])) {
+        bd2 = d2;
+        best = i;
+      }
     }
   }
   return best;
@@ -924,6 +945,16 @@ __device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, cons
 // different lengths and phases share it; each tracklet still sees exactly
 // the operation sequence of the sequential description above.
 enum : int { kIdle = 0, kChain = 1, kFollow = 2, kRefit = 3, kExtend = 4 };
+
+// Claim key of the selection: more hits, then smaller chi2 (FP32 bits of
+// a non-negative float order like its value), then smaller start ID.
+__device__ __forceinline__ unsigned long long claim_key(int n_hits, float chi2, int start_id) {
+  const float c = chi2 > 0.0f ? chi2 : 0.0f;
+  const unsigned int bits = __float_as_uint(c);
+  return ((unsigned long long)(unsigned int)n_hits << 56) |
+         ((unsigned long long)(0xFFFFFFFFu - bits) << 24) |
+         (unsigned long long)(0xFFFFFFu - (unsigned int)start_id);
+}
 
 __device__ __forceinline__ void kf_fail(const Bufs &B, int t, int start_id, int n_chain) {
   tpcca_tracklet_t o;
@@ -990,18 +1021,32 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
     s_aux[20][tid] = st.x;
   };
   float chi2 = 0.0f;
-  unsigned int steps = 0, cands = 0;
+  unsigned int cands = 0;
+  unsigned long long steps = 0, tests = 0, updates = 0;  // wave totals (scalar)
   int pnext = 0, pend = 0;  // wave-private pool of claimed tracklets
+  // The processing order is cut into one slice per XCD.  Block b runs on
+  // XCD b mod 8, whose waves drain that slice first (its L2 then holds the
+  // hits of a few sectors rather than of all of them) and then help drain
+  // the following slices.
+  const int nsl = P.kf_xcd ? kXcds : 1;
+  int part = blockIdx.x % nsl, tried = 0;
   for (;;) {
     const unsigned long long idle = __ballot(phase == kIdle);
-    if (idle && pnext == pend && !exhausted) {
-      // claim the next kPool tracklets with one atomic per wave
+    while (idle && pnext == pend && !exhausted) {
+      // claim the next kPool tracklets of the slice with one atomic per wave
+      const int lo = (int)((int64_t)n_trk * part / nsl);
+      const int hi = (int)((int64_t)n_trk * (part + 1) / nsl);
       int base = 0;
-      if (lane == 0) base = atomicAdd(&rd.kf_next, kPool);
+      if (lane == 0) base = atomicAdd(&rd.kf_next[part], kPool);
       base = __shfl(base, 0, 64);
-      pnext = min(base, n_trk);
-      pend = min(base + kPool, n_trk);
-      if (pend >= n_trk) exhausted = true;
+      if (base < hi - lo) {
+        pnext = lo + base;
+        pend = min(pnext + kPool, hi);
+      } else if (++tried == nsl) {
+        exhausted = true;
+      } else {
+        part = (part + 1) % nsl;
+      }
     }
     if (idle && pnext < pend) {
       const int take = min(__popcll(idle), pend - pnext);
@@ -1072,22 +1117,23 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
     }
     // ---- the step: one propagation, one search, one test, one update
     bool ok = true;
-    if (prop) {
-      ++steps;
-      ok = kf_propagate(P, st, B.row_x[row]);
-    }
+    steps += __popcll(__ballot(prop));
+    if (prop) ok = kf_propagate(P, st, B.row_x[row]);
     int h = given;
     const bool search = act && ok && given < 0;
     if (search) h = kf_search(B, P, rt, st, row, cands);
     bool acc = act && ok && h >= 0;
     float2 c = make_float2(0.0f, 0.0f);
     if (acc) c = B.yz[h];
+    tests += __popcll(__ballot(acc && search));
     if (acc && search) {
       float cc2;
       acc = kf_chi2(P, st, c.x, c.y, cc2) && cc2 <= P.pick_chi2;
     }
     float c2 = 0.0f;
+    updates += __popcll(__ballot(acc));
     const bool upd = acc && kf_update(P, st, c.x, c.y, c2);
+    bool fin = false;  // a tracklet fit ended with enough hits: claim them
     // ---- bookkeeping
     if (phase == kChain) {
       if (!upd) {
@@ -1172,54 +1218,79 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
 #pragma unroll
         for (int q = 0; q < 15; ++q) o.cov[q] = s_aux[5 + q][tid];
         o.status = (n1 + ne) < P.min_hits ? 1 : 0;
+        fin = o.status == 0;
         phase = kIdle;
+      }
+    }
+    // ---- the selection's claims of the tracklets that ended in this step:
+    // the wave writes the claim key of each into the owner word of its hits
+    // (one tracklet at a time, hit slots read by all lanes)
+    unsigned long long fm = P.kf_claims ? __ballot(fin) : 0ull;
+    if (fm) {
+      // the hit slots were written by other lanes of this wave
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      while (fm) {
+        const int src = __builtin_ctzll(fm);
+        fm &= fm - 1;
+        // wave-uniform values of the source lane (scalar registers)
+        const int tt = __builtin_amdgcn_readlane(t, src);
+        const int nn = __builtin_amdgcn_readlane(n1 + ne, src);
+        const unsigned long long kk = claim_key(
+            nn, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(chi2), src)),
+            __builtin_amdgcn_readlane(start_id, src));
+        const int32_t *hh = B.trk_hits + (int64_t)tt * R;
+        for (int j = lane; j < nn; j += 64) atomicMax(&B.owner[hh[j]], kk);
       }
     }
   }
   // work counters (one atomic per wave)
-  unsigned long long s64 = wave_sum((unsigned long long)steps);
   unsigned long long c64 = wave_sum((unsigned long long)cands);
   if (lane == 0) {
-    atomicAdd(&rd.kf_steps, s64);
+    atomicAdd(&rd.kf_steps, steps);
     atomicAdd(&rd.kf_cands, c64);
+    atomicAdd(&rd.kf_tests, tests);
+    atomicAdd(&rd.kf_updates, updates);
   }
 }
 
 // ------------------------------------------------------------ selection ---
-// Claim key: more hits, then smaller chi2 (FP32 bits of a non-negative
-// float order like its value), then smaller start ID.
 __device__ __forceinline__ unsigned long long select_key(const tpcca_tracklet_t &o) {
-  const float c = o.chi2 > 0.0f ? o.chi2 : 0.0f;
-  const unsigned int bits = __float_as_uint(c);
-  return ((unsigned long long)(unsigned int)o.n_hits << 56) |
-         ((unsigned long long)(0xFFFFFFFFu - bits) << 24) |
-         (unsigned long long)(0xFFFFFFu - (unsigned int)o.start_id);
+  return claim_key(o.n_hits, o.chi2, o.start_id);
 }
 
-// One wave per tracklet: the lanes claim its hits together (coalesced reads
-// of the hit slots, 64-bit atomicMax per hit).
+// Thread per tracklet (64 neighbouring tracklets of the processing order
+// per wave): claim its hits with its key (used when the fit does not write
+// the claims itself); hit slots are read eight at a time.
 __global__ __launch_bounds__(kBlock) void k_claim(Bufs B, ParamsDev P, int run) {
   const RunDev &rd = B.runs[run];
   const int R = P.n_rows;
-  const int lane = threadIdx.x & 63;
-  const int nw = (gridDim.x * blockDim.x) >> 6;
-  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < rd.n_trk; i += nw) {
-    const int t = B.kf_order[rd.trk0 + i];  // grid order: nearby hits
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rd.n_trk; i += gridDim.x * blockDim.x) {
+    const int t = B.kf_order[rd.trk0 + i];
     const tpcca_tracklet_t &o = B.trk[t];
     if (o.status != 0) continue;
     const unsigned long long key = select_key(o);
     const int32_t *hl = B.trk_hits + (int64_t)t * R;
-    for (int j = lane; j < o.n_hits; j += 64) atomicMax(&B.owner[hl[j]], key);
+    const int n = o.n_hits;
+    for (int j0 = 0; j0 < n; j0 += 8) {
+      int h[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) h[q] = j0 + q < n ? hl[j0 + q] : -1;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (h[q] >= 0) atomicMax(&B.owner[h[q]], key);
+    }
   }
 }
 
-// One wave per tracklet: count the hits it won; accept or reject.
+// Thread per tracklet (64 neighbouring tracklets of the processing order
+// per wave): count the hits it won, record which, accept or reject.  Hit
+// slots and owner words are read eight at a time so that each lane keeps
+// several independent loads in flight.
 __global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
   const RunDev &rd = B.runs[run];
   const int R = P.n_rows;
-  const int lane = threadIdx.x & 63;
-  const int nw = (gridDim.x * blockDim.x) >> 6;
-  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < rd.n_trk; i += nw) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rd.n_trk; i += gridDim.x * blockDim.x) {
     const int t = B.kf_order[rd.trk0 + i];
     const int tl = t - rd.trk0;
     const tpcca_tracklet_t &o = B.trk[t];
@@ -1227,17 +1298,31 @@ __global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
     if (o.status == 0) {
       const unsigned long long key = select_key(o);
       const int32_t *hl = B.trk_hits + (int64_t)t * R;
+      unsigned long long *wm = B.wonmask + (int64_t)t * 4;
+      const int n = o.n_hits;
+      unsigned long long cur = 0;
       int won = 0;
-      for (int j0 = 0; j0 < o.n_hits; j0 += 64) {
-        const int j = j0 + lane;
-        const unsigned long long m = __ballot(j < o.n_hits && B.owner[hl[j]] == key);
-        if (lane == 0) B.wonmask[(int64_t)t * 4 + (j0 >> 6)] = m;
-        won += __popcll(m);
+      for (int j0 = 0; j0 < n; j0 += 8) {
+        int h[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) h[q] = j0 + q < n ? hl[j0 + q] : -1;
+        unsigned int bits = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const bool w = h[q] >= 0 && B.owner[h[q]] == key;
+          bits |= (w ? 1u : 0u) << q;
+        }
+        won += __popc(bits);
+        cur |= (unsigned long long)bits << (j0 & 63);
+        if (((j0 + 8) & 63) == 0 || j0 + 8 >= n) {  // a 64-slot word is complete
+          wm[j0 >> 6] = cur;
+          cur = 0;
+        }
       }
-      if (won >= P.min_hits && won * 100 >= P.own_pct * o.n_hits)
+      if (won >= P.min_hits && won * 100 >= P.own_pct * n)
         v = (1ull << 40) | (unsigned long long)won;
     }
-    if (lane == 0) B.accv[tl] = v;
+    B.accv[tl] = v;
   }
 }
 
@@ -1337,62 +1422,68 @@ __global__ void k_unit_results(Bufs B, int run) {
   }
 }
 
-// Compaction of accepted tracks, one wave per tracklet: parameters, won hits
-// in ascending rows (inward hits were stored after the pass-1 hits in
+// Compaction of accepted tracks, thread per tracklet: parameters, won hits
+// in ascending rows (inward hits were stored after the pass-1 hits, in
 // descending rows) and the per-cluster assignment (unit-local track index).
+// Won slots are gathered eight at a time for independent loads in flight.
 __global__ __launch_bounds__(kBlock) void k_output(Bufs B, ParamsDev P, int run) {
   const RunDev &rd = B.runs[run];
   const int R = P.n_rows;
-  const int lane = threadIdx.x & 63;
-  const int nw = (gridDim.x * blockDim.x) >> 6;
-  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < rd.n_trk; i += nw) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rd.n_trk; i += gridDim.x * blockDim.x) {
     const int t = B.kf_order[rd.trk0 + i];
     const int tl = t - rd.trk0;
     if (B.accv[tl] == 0) continue;
     const tpcca_tracklet_t &o = B.trk[t];
     const int u = B.trk_unit[t];
     const int ucl = B.units[u].cl_begin;
-    const tpcca_unit_result_t &ur = B.unit_res[u];
+    const int32_t tb = B.unit_res[u].track_begin;
+    const int32_t hb = B.unit_res[u].hit_begin;
     const unsigned long long ex = B.accx[tl];
     const int k = rd.trk0 + acc_count(ex);
     const int64_t h0 = rd.cl0 + acc_hits(ex);
     const int32_t *hl = B.trk_hits + (int64_t)t * R;
     const int n1 = o.n_pass1, nh = o.n_hits, ne = nh - n1;
-    const int local_track = k - (int)ur.track_begin;
+    const int local_track = k - tb;
+    const unsigned long long *wmp = B.wonmask + (int64_t)t * 4;
+    const unsigned long long m0 = wmp[0];
+    const unsigned long long m1 = nh > 64 ? wmp[1] : 0ull;
+    const unsigned long long m2 = nh > 128 ? wmp[2] : 0ull;
+    const unsigned long long m3 = nh > 192 ? wmp[3] : 0ull;
     int w = 0;
-    const unsigned long long *wm = B.wonmask + (int64_t)t * 4;
-    for (int j0 = 0; j0 < nh; j0 += 64) {
-      const int j = j0 + lane;
-      int gh = -1;
-      bool won = false;
-      if (j < nh) {
-        // slot of the j-th hit in row order: inward hits were stored last,
-        // in descending rows
+    for (int j0 = 0; j0 < nh; j0 += 8) {
+      int gh[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = j0 + q;
+        // slot of the j-th hit in row order
         const int slot = j < ne ? n1 + ne - 1 - j : j - ne;
-        gh = hl[slot];
-        won = (wm[slot >> 6] >> (slot & 63)) & 1ull;
+        const unsigned long long m = slot < 64 ? m0 : slot < 128 ? m1 : slot < 192 ? m2 : m3;
+        const bool won = j < nh && ((m >> (slot & 63)) & 1ull);
+        gh[q] = won ? hl[slot] : -1;
       }
-      const unsigned long long m = __ballot(won);
-      if (won) {
-        const int id = B.sid[gh];
-        B.hits_out[h0 + w + __popcll(m & ((1ull << lane) - 1))] = id;
-        B.assign[ucl + id] = local_track;
+      int id[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) id[q] = gh[q] >= 0 ? B.sid[gh[q]] : -1;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (id[q] >= 0) {
+          B.hits_out[h0 + w] = id[q];
+          B.assign[ucl + id[q]] = local_track;
+          ++w;
+        }
       }
-      w += __popcll(m);
     }
-    if (lane == 0) {
-      tpcca_track_t tr;
-      tr.x_ref = o.x_ref;
-      for (int q = 0; q < 5; ++q) tr.p[q] = o.p[q];
-      for (int q = 0; q < 15; ++q) tr.cov[q] = o.cov[q];
-      tr.chi2 = o.chi2;
-      tr.ndf = o.ndf;
-      tr.n_hits = w;
-      tr.hit_offset = (int32_t)(h0 - ur.hit_begin);
-      tr.sector = B.units[u].sector;
-      tr.start_id = o.start_id;
-      B.tracks[k] = tr;
-    }
+    tpcca_track_t tr;
+    tr.x_ref = o.x_ref;
+    for (int q = 0; q < 5; ++q) tr.p[q] = o.p[q];
+    for (int q = 0; q < 15; ++q) tr.cov[q] = o.cov[q];
+    tr.chi2 = o.chi2;
+    tr.ndf = o.ndf;
+    tr.n_hits = w;
+    tr.hit_offset = (int32_t)(h0 - hb);
+    tr.sector = B.units[u].sector;
+    tr.start_id = o.start_id;
+    B.tracks[k] = tr;
   }
 }
 
@@ -1465,7 +1556,11 @@ hipError_t launch_clean(const Bufs &B, const ParamsDev &P, int run, const RunHos
                         hipStream_t s) {
   (void)P;
   const int nch = h.c1 - h.c0;
-  if (nch > 0) k_clean<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
+  if (nch > 0) {
+    k_clean<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
+    k_scan_tiles<<<1, 1024, 0, s>>>(B.scan_tmp, nch);
+    k_starts_compact<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
+  }
   return hipGetLastError();
 }
 
@@ -1479,7 +1574,7 @@ hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHo
                       ((int64_t)h.cl1 - (h.cl0 & ~3) + 3) / 4, 0, s);
   if (e != hipSuccess) return e;
   if (nch > 0) {
-    k_chain<<<grid_for(nch, 1, 16384), 64, 0, s>>>(B, P, run);
+    k_chain<<<grid_for(h.cl1 - h.cl0, kBlock, 4096), kBlock, 0, s>>>(B, P, run);
     k_flag_sums<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
     k_scan_tiles<<<1, 1024, 0, s>>>(B.scan_tmp, nch);
     k_flag_apply<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
@@ -1494,14 +1589,14 @@ hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHo
 hipError_t launch_kf(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s) {
   // persistent: exactly the resident capacity of the chip, work taken from a
   // counter
-  // register budget variants: 1 = compiler's choice, 6 / 8 waves per SIMD
+  // register budgets: 5 (default), 6 or 8 resident waves per SIMD
   const int v = P.kf_min_waves >= 8 ? 2 : P.kf_min_waves >= 6 ? 1 : 0;
   static int cus = 0, per[3] = {0, 0, 0};
   if (cus == 0) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_kf<1>, kKfBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_kf<5>, kKfBlock, 0);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_kf<6>, kKfBlock, 0);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_kf<8>, kKfBlock, 0);
     cus = std::max(1, cus);
@@ -1509,10 +1604,14 @@ hipError_t launch_kf(const Bufs &B, const ParamsDev &P, int run, const RunHost &
   }
   const int bpc = P.kf_blocks_per_cu > 0 ? std::min(P.kf_blocks_per_cu, per[v]) : per[v];
   const int g = grid_for(h.trk_cap, kKfBlock, cus * bpc);
+  // the claim words of the selection start at zero (the fit may write them
+  // as its tracklets end)
+  hipError_t e = launch_fill_u64(B.owner + h.cl0, h.cl1 - h.cl0, 0ull, s);
+  if (e != hipSuccess) return e;
   if (h.trk_cap > 0) {
     if (v == 2) k_kf<8><<<g, kKfBlock, 0, s>>>(B, P, run);
     else if (v == 1) k_kf<6><<<g, kKfBlock, 0, s>>>(B, P, run);
-    else k_kf<1><<<g, kKfBlock, 0, s>>>(B, P, run);
+    else k_kf<5><<<g, kKfBlock, 0, s>>>(B, P, run);
   }
   return hipGetLastError();
 }
@@ -1520,15 +1619,13 @@ hipError_t launch_kf(const Bufs &B, const ParamsDev &P, int run, const RunHost &
 hipError_t launch_select(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
                          hipStream_t s) {
   const int64_t n = h.cl1 - h.cl0;
-  hipError_t e = launch_fill_u64(B.owner + h.cl0, n, 0ull, s);
-  if (e != hipSuccess) return e;
-  e = launch_fill_i32(B.assign + h.cl0, n, -1, s);
+  hipError_t e = launch_fill_i32(B.assign + h.cl0, n, -1, s);
   if (e != hipSuccess) return e;
   const int nu = h.u1 - h.u0;
-  const int tg = grid_for((int64_t)h.trk_cap * 64, kBlock, 8192);  // one wave per tracklet
+  const int tg = grid_for((int64_t)h.trk_cap, kBlock, 8192);  // thread per tracklet
   const int64_t tiles = (h.trk_cap + kScanTile - 1) / kScanTile;
   if (h.trk_cap > 0) {
-    k_claim<<<tg, kBlock, 0, s>>>(B, P, run);
+    if (!P.kf_claims) k_claim<<<tg, kBlock, 0, s>>>(B, P, run);
     k_won<<<tg, kBlock, 0, s>>>(B, P, run);
     k_acc_sums<<<grid_for(tiles, 1, 8192), kBlock, 0, s>>>(B, run);
   }

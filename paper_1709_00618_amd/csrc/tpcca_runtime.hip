@@ -61,12 +61,12 @@ struct tpcca_ctx {
 
   // device buffers
   DevBuf row_x_d, units_d, chunks_d, runs_d, rowtab, row_cnt, row_fill, rtmp, zmm, binbeg, yz, sid, up,
-      dn, upc, dnc, flag, starts, chunk_nstart, tiles, sval, tofg, kf_order, srow, cinfo, trk_start, trk_unit, unit_tbegin, trk, trk_hits, owner, accv, wonmask, accx,
+      dn, upc, dnc, flag, starts, tiles, sval, tofg, kf_order, srow, cinfo, trk_start, trk_unit, unit_tbegin, trk, trk_hits, owner, accv, wonmask, accx,
       tracks, hits_out, assign, unit_res, scan_tmp, in_cl, in_row;
   Bufs B{};
 
   // graph replay of the batch path
-  hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec[6] = {};  // whole sequence, or the six timed segments
   RunHost gcap{};
   int generation = 0;
   int gen_captured = -1;
@@ -75,11 +75,22 @@ struct tpcca_ctx {
   hipEvent_t ev[7] = {};
   float stage_ms[6] = {};
   bool have_times = false;
+  bool capturing = false;       // a graph capture is in progress
+  bool gtiming = false;         // the captured graph holds stage events
 
   std::string last_error;
 };
 
 // --------------------------------------------------------------- errors ---
+// Destroys the captured batch graphs; the next graph run captures again.
+static void drop_graphs(tpcca_ctx *c) {
+  for (auto &g : c->gexec) {
+    if (g) hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+  c->gen_captured = -1;
+}
+
 static int dev_err(tpcca_ctx *c, hipError_t e, const char *what) {
   if (c) {
     c->last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -154,7 +165,6 @@ static void refresh_bufs(tpcca_ctx *c) {
   B.dnc = ptr<int32_t>(c->dnc);
   B.flag = ptr<int32_t>(c->flag);
   B.starts = ptr<int2>(c->starts);
-  B.chunk_nstart = ptr<int32_t>(c->chunk_nstart);
   B.tiles = ptr<int4>(c->tiles);
   B.sval = ptr<uint8_t>(c->sval);
   B.tofg = ptr<int32_t>(c->tofg);
@@ -208,7 +218,6 @@ static int ensure_work(tpcca_ctx *c, int64_t n_cl, int64_t n_units, int64_t n_bi
   ENS(dnc, N, sizeof(int32_t), keepN);
   ENS(flag, N, sizeof(int32_t), keepN);
   ENS(starts, N, sizeof(int2), 0);
-  ENS(chunk_nstart, NC, sizeof(int32_t), 0);
   ENS(tiles, (size_t)(N / kTile + U * (R + 2) + 1), sizeof(int4), (size_t)c->tiles_total);
   ENS(owner, N, sizeof(unsigned long long), keepN);
   ENS(hits_out, N, sizeof(int32_t), keepN);
@@ -301,39 +310,36 @@ static std::vector<std::pair<int, int>> select_ranges(tpcca_ctx *c, int slot, in
   return out;
 }
 
+// Stage boundary k (events 0..6 bracket the six timed segments).
 static void record_event(tpcca_ctx *c, int k) {
-  if (c->timing) hipEventRecord(c->ev[k], c->stream);
+  if (c->timing && !c->capturing) (void)hipEventRecord(c->ev[k], c->stream);
 }
+
+// The six timed segments: 0 grid, 1 links, 2 clean, 3 chains, 4 fit,
+// 5 selection.  Stage calls map to segments 1 -> {0, 1}, 2 -> {2},
+// 3 -> {3, 4}, 4 -> {5}.
+static hipError_t launch_segment(tpcca_ctx *c, int run, const RunHost &h, int seg) {
+  hipStream_t s = c->stream;
+  switch (seg) {
+    case 0: return launch_grid(c->B, c->P, run, h, s);
+    case 1: return launch_links(c->B, c->P, run, h, s);
+    case 2: return launch_clean(c->B, c->P, run, h, s);
+    case 3: return launch_chains(c->B, c->P, run, h, s);
+    case 4: return launch_kf(c->B, c->P, run, h, s);
+    default: return launch_select(c->B, c->P, run, h, s);
+  }
+}
+static const int kSegFirst[5] = {0, 0, 2, 3, 5};  // first segment of stage 1..4
+static const int kSegEnd[5] = {0, 2, 3, 5, 6};    // one past its last
 
 // Launch stages [first, last] (1 = grid + links, 2 = clean, 3 = tracklets,
 // 4 = selection) for one run.
 static int launch_stages(tpcca_ctx *c, int run, const RunHost &h, int first, int last) {
   hipError_t e = hipSuccess;
-  hipStream_t s = c->stream;
-  for (int st = first; st <= last && e == hipSuccess; ++st) {
-    switch (st) {
-      case 1:
-        record_event(c, 0);
-        e = launch_grid(c->B, c->P, run, h, s);
-        record_event(c, 1);
-        if (e == hipSuccess) e = launch_links(c->B, c->P, run, h, s);
-        record_event(c, 2);
-        break;
-      case 2:
-        e = launch_clean(c->B, c->P, run, h, s);
-        record_event(c, 3);
-        break;
-      case 3:
-        e = launch_chains(c->B, c->P, run, h, s);
-        record_event(c, 4);
-        if (e == hipSuccess) e = launch_kf(c->B, c->P, run, h, s);
-        record_event(c, 5);
-        break;
-      case 4:
-        e = launch_select(c->B, c->P, run, h, s);
-        record_event(c, 6);
-        break;
-    }
+  if (first == 1) record_event(c, 0);
+  for (int seg = kSegFirst[first]; seg < kSegEnd[last] && e == hipSuccess; ++seg) {
+    e = launch_segment(c, run, h, seg);
+    record_event(c, seg + 1);
   }
   if (e != hipSuccess) return dev_err(c, e, "kernel launch");
   if (c->timing && first == 1 && last == 4) c->have_times = true;
@@ -563,6 +569,8 @@ int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int 
   P.kf_blocks_per_cu = 0;
   P.link_blocks_per_cu = 0;
   P.kf_min_waves = 0;
+  P.kf_claims = 1;
+  P.kf_xcd = 0;
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -593,11 +601,11 @@ int tpcca_destroy(tpcca_ctx_t *c) {
   if (!c) return TPCCA_EINVAL;
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  drop_graphs(c);
   DevBuf *all[] = {&c->row_x_d, &c->units_d, &c->chunks_d, &c->runs_d, &c->rowtab, &c->row_cnt,
                    &c->row_fill, &c->rtmp,
                    &c->zmm, &c->binbeg, &c->yz, &c->sid, &c->up, &c->dn, &c->upc,
-                   &c->dnc, &c->flag, &c->starts, &c->chunk_nstart, &c->tiles, &c->sval, &c->tofg, &c->kf_order, &c->srow, &c->cinfo, &c->trk_start, &c->trk_unit, &c->unit_tbegin, &c->trk,
+                   &c->dnc, &c->flag, &c->starts, &c->tiles, &c->sval, &c->tofg, &c->kf_order, &c->srow, &c->cinfo, &c->trk_start, &c->trk_unit, &c->unit_tbegin, &c->trk,
                    &c->trk_hits, &c->owner, &c->accv, &c->wonmask, &c->accx, &c->tracks, &c->hits_out,
                    &c->assign, &c->unit_res, &c->scan_tmp, &c->in_cl, &c->in_row};
   for (DevBuf *b : all)
@@ -875,34 +883,56 @@ int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
   capr.bin1 = capB;
   capr.trk_cap = (int32_t)capT;
   capr.tile1 = (int32_t)(capN / kTile + capU * (c->R + 2) + 1);
-  const bool reuse = c->gexec && c->gen_captured == c->generation && c->gcap.u1 == capr.u1 &&
+  const bool reuse = c->gexec[0] && c->gen_captured == c->generation && c->gcap.u1 == capr.u1 &&
                      c->gcap.c1 == capr.c1 && c->gcap.cl1 == capr.cl1 && c->gcap.bin1 == capr.bin1 &&
-                     c->gcap.trk_cap == capr.trk_cap && c->gcap.tile1 == capr.tile1;
+                     c->gcap.trk_cap == capr.trk_cap && c->gcap.tile1 == capr.tile1 &&
+                     c->gtiming == c->timing;
   if (!reuse) {
-    if (c->gexec) {
-      hipGraphExecDestroy(c->gexec);
-      c->gexec = nullptr;
+    drop_graphs(c);
+    // one graph of the whole sequence, or with timing on one graph per timed
+    // segment (HIP events between the replays of the segments)
+    const int nseg = c->timing ? 6 : 1;
+    for (int k = 0; k < nseg; ++k) {
+      hipGraph_t g = nullptr;
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      c->capturing = true;
+      hipError_t le = hipSuccess;
+      if (nseg == 1) {
+        for (int seg = 0; seg < 6 && le == hipSuccess; ++seg) le = launch_segment(c, 0, capr, seg);
+      } else {
+        le = launch_segment(c, 0, capr, k);
+      }
+      c->capturing = false;
+      // always end the capture, also after a failed launch
+      hipError_t e = hipStreamEndCapture(c->stream, &g);
+      if (le != hipSuccess || e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        drop_graphs(c);
+        return le != hipSuccess ? dev_err(c, le, "kernel launch under capture")
+                                : dev_err(c, e, "hipStreamEndCapture");
+      }
+      e = hipGraphInstantiate(&c->gexec[k], g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        c->gexec[k] = nullptr;
+        drop_graphs(c);  // also the segments captured before
+        return dev_err(c, e, "hipGraphInstantiate");
+      }
     }
-    hipGraph_t g = nullptr;
-    const bool tm = c->timing;
-    c->timing = false;
-    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    int lrc = launch_stages(c, 0, capr, 1, 4);
-    hipError_t e = hipStreamEndCapture(c->stream, &g);
-    c->timing = tm;
-    if (lrc != TPCCA_OK) return lrc;
-    if (e != hipSuccess) return dev_err(c, e, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    if (e != hipSuccess) return dev_err(c, e, "hipGraphInstantiate");
     c->gcap = capr;
+    c->gtiming = c->timing;
     c->gen_captured = c->generation;
   }
-  record_event(c, 0);
-  HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
-  if (c->timing) {
-    for (int k = 1; k <= 6; ++k) hipEventRecord(c->ev[k], c->stream);
+  if (!c->gtiming) {
+    HIPCHK(c, hipGraphLaunch(c->gexec[0], c->stream));
+  } else {
+    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    for (int k = 0; k < 6; ++k) {
+      HIPCHK(c, hipGraphLaunch(c->gexec[k], c->stream));
+      HIPCHK(c, hipEventRecord(c->ev[k + 1], c->stream));
+    }
   }
+  c->have_times = c->gtiming;
   return TPCCA_OK;
 }
 
@@ -946,6 +976,8 @@ int tpcca_work_stats(tpcca_ctx_t *c, tpcca_work_stats_t *out) {
       out->tracklets += d.n_trk;
       out->fit_steps += (int64_t)d.kf_steps;
       out->fit_candidates += (int64_t)d.kf_cands;
+      out->fit_tests += (int64_t)d.kf_tests;
+      out->fit_updates += (int64_t)d.kf_updates;
     }
     if (lo >= kSelected) {
       out->tracks += d.n_acc;
@@ -1013,12 +1045,15 @@ int tpcca_device_results(tpcca_ctx_t *c, tpcca_device_results_t *out) {
 int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
   if (!c || !t) return TPCCA_EINVAL;
   if (t->fit_pool < 0 || t->fit_pool > 4096 || t->fit_blocks_per_cu < 0 || t->grid_hits_per_bin < 0 ||
-      t->link_blocks_per_cu < 0 || t->fit_min_waves < 0)
+      t->link_blocks_per_cu < 0 || t->fit_min_waves < 0 || t->fit_claims < 0 || t->fit_claims > 1 ||
+      t->fit_xcd_slices < 0 || t->fit_xcd_slices > 1)
     return TPCCA_EINVAL;
   // the grid layout of loaded units depends on hits per bin
   if (t->grid_hits_per_bin && !c->units.empty() && t->grid_hits_per_bin != c->P.hits_per_bin)
     return TPCCA_ESTATE;
   c->P.kf_min_waves = t->fit_min_waves;
+  c->P.kf_claims = t->fit_claims;
+  c->P.kf_xcd = t->fit_xcd_slices;
   c->P.kf_pool = t->fit_pool ? t->fit_pool : 64;
   c->P.kf_blocks_per_cu = t->fit_blocks_per_cu;
   c->P.link_blocks_per_cu = t->link_blocks_per_cu;
@@ -1037,6 +1072,8 @@ int tpcca_get_tuning(tpcca_ctx_t *c, tpcca_tuning_t *t) {
   t->grid_hits_per_bin = c->P.hits_per_bin;
   t->link_blocks_per_cu = c->P.link_blocks_per_cu;
   t->fit_min_waves = c->P.kf_min_waves;
+  t->fit_claims = c->P.kf_claims;
+  t->fit_xcd_slices = c->P.kf_xcd;
   return TPCCA_OK;
 }
 

@@ -67,6 +67,12 @@ def test_central_event_one_launch_per_stage(tpcca, torch_cuda, row_x):
         for u in range(b.units.shape[0]):
             cl, row, slot, sec, _ = b.unit(u)
             _parity.compare_unit_stagewise(ctx, slot, sec, cl, row, refs[u])
+        # the fit's work counters (the basis of its FLOP count) are the oracle's
+        w = ctx.work_stats()
+        assert w["fit_steps"] == sum(r.work["propagations"] for r in refs)
+        assert w["fit_tests"] == sum(r.work["tests"] for r in refs)
+        assert w["fit_updates"] == sum(r.work["updates"] for r in refs)
+        assert w["tracklets"] == sum(r.tracklets.shape[0] for r in refs)
     assert sum(r.n_tracks for r in refs) > 15000
 
 
@@ -97,6 +103,28 @@ def test_graph_replays_track_changing_batches(tpcca, torch_cuda, row_x):
             _parity.compare_batch(units, tracks, hits, asg, b, refs)
 
 
+def test_timed_graph_replays_give_the_same_results(tpcca, row_x):
+    """Stage timing in graph mode (one graph per stage, events between)
+    changes nothing in the results and reports every stage."""
+    b = tpcgen.minbias_batch(seed=7, n_events=2)
+    with tpcca.Context(row_x) as ctx:
+        ctx.run_batch(b.cl, b.row, b.units, graph=True)
+        base = [a.copy() for a in ctx.get_batch_results()]
+        ctx.set_timing(True)
+        for _ in range(2):
+            ctx.run_batch(b.cl, b.row, b.units, graph=True)
+            ctx.sync()
+            got = ctx.get_batch_results()
+            st = ctx.stage_times()
+            assert len(st) == 6 and all(v > 0 for v in st.values()), st
+            for x, y in zip(base, got):
+                assert x.tobytes() == y.tobytes()
+        ctx.set_timing(False)
+        ctx.run_batch(b.cl, b.row, b.units, graph=True)
+        for x, y in zip(base, ctx.get_batch_results()):
+            assert x.tobytes() == y.tobytes()
+
+
 def test_batch_equals_sector_by_sector(tpcca, row_x):
     """A unit's results do not depend on the batch it runs in."""
     b = tpcgen.minbias_batch(seed=5, n_events=3)
@@ -123,9 +151,12 @@ def test_batch_equals_sector_by_sector(tpcca, row_x):
 
 
 @pytest.mark.parametrize("knobs", [
-    dict(fit_pool=16, fit_min_waves=0, grid_hits_per_bin=2, link_blocks_per_cu=8),
-    dict(fit_pool=128, fit_min_waves=6, grid_hits_per_bin=1, link_blocks_per_cu=16),
-    dict(fit_pool=32, fit_min_waves=8, fit_blocks_per_cu=2, grid_hits_per_bin=4, link_blocks_per_cu=32),
+    dict(fit_pool=16, fit_min_waves=0, grid_hits_per_bin=2, link_blocks_per_cu=8, fit_claims=1,
+         fit_xcd_slices=0),
+    dict(fit_pool=128, fit_min_waves=6, grid_hits_per_bin=1, link_blocks_per_cu=16, fit_claims=0,
+         fit_xcd_slices=1),
+    dict(fit_pool=32, fit_min_waves=8, fit_blocks_per_cu=2, grid_hits_per_bin=4, link_blocks_per_cu=32,
+         fit_claims=1, fit_xcd_slices=1),
 ])
 def test_schedule_does_not_change_results(tpcca, row_x, knobs):
     """Every launch schedule gives the default schedule's bytes and the oracle's results."""
