@@ -237,7 +237,8 @@ typedef struct {
   int32_t fit_blocks_per_cu; /* resident fit blocks per CU (0: occupancy limit) */
   int32_t grid_hits_per_bin; /* z-bin occupancy of the row grid (1); applies after reset */
   int32_t link_blocks_per_cu;/* resident neighbour-finding blocks per CU (0: 32) */
-  int32_t fit_min_waves;     /* register budget of the fit kernel in resident waves per SIMD: 0 (5), 6 or 8 */
+  int32_t fit_min_waves;     /* register budget of the fit kernel in resident waves per SIMD:
+                                0 (5), 4 or 6 (larger values act as 6) */
   int32_t fit_claims;        /* 1: the fit kernel writes the selection's claims as tracklets end
                                 (default); 0: a claim kernel of its own */
   int32_t fit_xcd_slices;    /* 1: the fit's processing order is cut into one slice per XCD;

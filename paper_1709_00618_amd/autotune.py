@@ -20,7 +20,7 @@ CACHE = os.path.join(HERE, "tuning_cache.json")
 
 SPACE = {
     "fit_pool": [32, 64, 128],
-    "fit_min_waves": [0, 6],
+    "fit_min_waves": [0, 4, 6],
     "fit_claims": [0, 1],
     "fit_xcd_slices": [0, 1],
 }

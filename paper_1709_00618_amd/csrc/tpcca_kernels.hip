@@ -895,8 +895,18 @@ __device__ __forceinline__ bool kf_update(const ParamsDev &P, KState &s, float y
 
 // Nearest hit (dy^2 + dz^2, ties to the lower ID) inside the prediction
 // window of row r; -1 if none.
+// A tracklet's hit slot holds the hit's unit-local sorted index (24 bits:
+// units hold fewer than 2^24 clusters) and its pad row (top 8 bits), so the
+// refit needs no row lookup.
+__device__ __forceinline__ int32_t slot_enc(int g, int ucl, int row) {
+  return (int32_t)(((uint32_t)row << 24) | (uint32_t)(g - ucl));
+}
+__device__ __forceinline__ int slot_hit(int32_t v, int ucl) { return ucl + (int)((uint32_t)v & 0xFFFFFFu); }
+__device__ __forceinline__ int slot_row(int32_t v) { return (int)((uint32_t)v >> 24); }
+
+// Nearest hit of row r inside the window; its coordinates are returned in bc.
 __device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, const RowTab *rt,
-                                         const KState &s, int r, unsigned int &cands) {
+                                         const KState &s, int r, unsigned int &cands, float2 &bc) {
   float wy = P.nsig * sqrtf(s.C[0] + P.ery);
   float wz = P.nsig * sqrtf(s.C[2] + P.erz);
   if (wy > P.wmax) wy = P.wmax;
@@ -924,6 +934,7 @@ __device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, cons
       if (d2 < bd2 || (d2 == bd2 && B.sid[i] < B.sid[best])) {
         bd2 = d2;
         best = i;
+        bc = c[q];
       }
     }
   }
@@ -1005,9 +1016,12 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
   bool exhausted = false;
   const int kPool = P.kf_pool;
   int t = 0, start_id = 0, n_chain = 0, r0 = 0, k = 0, r = 0, miss = 0, n1 = 0, ne = 0;
-  int row_out = 0, row_ref = 0, prev = 0;
-  const RowTab *rt = nullptr;
-  int32_t *hl = nullptr;
+  int prev = 0;
+  int u = 0, ucl = 0;  // the tracklet's unit and its first global cluster index
+  // the row positions, staged once per block
+  __shared__ float s_rx[kMaxRows + 1];
+  for (int i = threadIdx.x; i < R; i += blockDim.x) s_rx[i] = B.row_x[i];
+  __syncthreads();
   KState st;
   // aux state in LDS (frees registers for occupancy): the pass-1 state at
   // the outermost hit, then the pass-2 state at the innermost hit
@@ -1022,7 +1036,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
   };
   float chi2 = 0.0f;
   unsigned int cands = 0;
-  unsigned long long steps = 0, tests = 0, updates = 0;  // wave totals (scalar)
+  unsigned int steps = 0, tests = 0, updates = 0;  // wave totals (scalar)
   int pnext = 0, pend = 0;  // wave-private pool of claimed tracklets
   // The processing order is cut into one slice per XCD.  Block b runs on
   // XCD b mod 8, whose waves drain that slice first (its L2 then holds the
@@ -1059,16 +1073,15 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
           if (rank < take) {
             t = B.kf_order[rd.trk0 + tl];
             const int g0 = B.trk_start[t];
-            const int u = B.trk_unit[t];
-            rt = B.rowtab + (int64_t)u * (R + 1);
-            hl = B.trk_hits + (int64_t)t * R;
+            u = B.trk_unit[t];
+            ucl = B.units[u].cl_begin;
             const int2 ci = B.cinfo[g0];
             const int gL = ci.x;
             n_chain = ci.y;
             r0 = B.srow[g0];
             start_id = B.sid[g0];
             const float2 h0 = B.yz[g0], hL = B.yz[gL];
-            const float x0 = B.row_x[r0], xL = B.row_x[r0 + n_chain - 1];
+            const float x0 = s_rx[r0], xL = s_rx[r0 + n_chain - 1];
             const float dxs = xL - x0;
             const float ty = (hL.x - h0.x) / dxs;
             const float sn = ty / sqrtf(__builtin_fmaf(ty, ty, 1.0f));
@@ -1087,7 +1100,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
             st.C[9] = P.c33;
             st.C[14] = P.c44;
             st.x = x0;
-            hl[0] = g0;
+            B.trk_hits[(int64_t)t * R] = slot_enc(g0, ucl, r0);
             prev = g0;
             k = 1;
             chi2 = 0.0f;
@@ -1107,8 +1120,9 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
       given = B.upc[prev];
       row = r0 + k;
     } else if (phase == kRefit) {
-      given = hl[k];
-      row = B.srow[given];
+      const int32_t v = B.trk_hits[(int64_t)t * R + k];
+      given = slot_hit(v, ucl);
+      row = slot_row(v);
       prop = k < n1 - 1;
     } else if (phase == kFollow || phase == kExtend) {
       end = phase == kFollow ? r >= R : r < 0;
@@ -1118,13 +1132,13 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
     // ---- the step: one propagation, one search, one test, one update
     bool ok = true;
     steps += __popcll(__ballot(prop));
-    if (prop) ok = kf_propagate(P, st, B.row_x[row]);
+    if (prop) ok = kf_propagate(P, st, s_rx[row]);
     int h = given;
     const bool search = act && ok && given < 0;
-    if (search) h = kf_search(B, P, rt, st, row, cands);
-    bool acc = act && ok && h >= 0;
     float2 c = make_float2(0.0f, 0.0f);
-    if (acc) c = B.yz[h];
+    if (search) h = kf_search(B, P, B.rowtab + (int64_t)u * (R + 1), st, row, cands, c);
+    bool acc = act && ok && h >= 0;
+    if (acc && !search) c = B.yz[h];
     tests += __popcll(__ballot(acc && search));
     if (acc && search) {
       float cc2;
@@ -1140,12 +1154,11 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
         kf_fail(B, t, start_id, n_chain);
         phase = kIdle;
       } else {
-        hl[k] = h;
+        B.trk_hits[(int64_t)t * R + k] = slot_enc(h, ucl, row);
         prev = h;
         if (++k == n_chain) {
           save_aux();
-          row_out = r0 + n_chain - 1;
-          r = row_out + 1;
+          r = r0 + n_chain;
           miss = 0;
           n1 = n_chain;
           phase = kFollow;
@@ -1159,7 +1172,6 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
         chi2 = chi2 + c2;
         if (--k < 0) {
           save_aux();
-          row_ref = r0;
           ne = 0;
           miss = 0;
           r = r0 - 1;
@@ -1174,13 +1186,11 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
         } else {
           if (upd) {
             if (fwd) {
-              hl[n1++] = h;
-              row_out = r;
+              B.trk_hits[(int64_t)t * R + n1++] = slot_enc(h, ucl, r);
             } else {
               chi2 = chi2 + c2;
-              hl[n1 + ne] = h;
+              B.trk_hits[(int64_t)t * R + n1 + ne] = slot_enc(h, ucl, r);
               ++ne;
-              row_ref = r;
             }
             save_aux();
             miss = 0;
@@ -1209,8 +1219,10 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
         o.n_hits = n1 + ne;
         o.n_pass1 = n1;
         o.ndf = 2 * (n1 + ne) - 5;
-        o.row_ref = row_ref;
-        o.row_out = row_out;
+        // outermost pass-1 hit and innermost hit, from their slots' rows
+        const int32_t *hl = B.trk_hits + (int64_t)t * R;
+        o.row_out = slot_row(hl[n1 - 1]);
+        o.row_ref = ne > 0 ? slot_row(hl[n1 + ne - 1]) : r0;
         o.x_ref = s_aux[20][tid];
         o.chi2 = chi2;
 #pragma unroll
@@ -1239,18 +1251,19 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
         const unsigned long long kk = claim_key(
             nn, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(chi2), src)),
             __builtin_amdgcn_readlane(start_id, src));
+        const int uc = __builtin_amdgcn_readlane(ucl, src);
         const int32_t *hh = B.trk_hits + (int64_t)tt * R;
-        for (int j = lane; j < nn; j += 64) atomicMax(&B.owner[hh[j]], kk);
+        for (int j = lane; j < nn; j += 64) atomicMax(&B.owner[slot_hit(hh[j], uc)], kk);
       }
     }
   }
   // work counters (one atomic per wave)
   unsigned long long c64 = wave_sum((unsigned long long)cands);
   if (lane == 0) {
-    atomicAdd(&rd.kf_steps, steps);
+    atomicAdd(&rd.kf_steps, (unsigned long long)steps);
     atomicAdd(&rd.kf_cands, c64);
-    atomicAdd(&rd.kf_tests, tests);
-    atomicAdd(&rd.kf_updates, updates);
+    atomicAdd(&rd.kf_tests, (unsigned long long)tests);
+    atomicAdd(&rd.kf_updates, (unsigned long long)updates);
   }
 }
 
@@ -1271,11 +1284,12 @@ __global__ __launch_bounds__(kBlock) void k_claim(Bufs B, ParamsDev P, int run) 
     if (o.status != 0) continue;
     const unsigned long long key = select_key(o);
     const int32_t *hl = B.trk_hits + (int64_t)t * R;
+    const int ucl = B.units[B.trk_unit[t]].cl_begin;
     const int n = o.n_hits;
     for (int j0 = 0; j0 < n; j0 += 8) {
       int h[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) h[q] = j0 + q < n ? hl[j0 + q] : -1;
+      for (int q = 0; q < 8; ++q) h[q] = j0 + q < n ? slot_hit(hl[j0 + q], ucl) : -1;
 #pragma unroll
       for (int q = 0; q < 8; ++q)
         if (h[q] >= 0) atomicMax(&B.owner[h[q]], key);
@@ -1298,6 +1312,7 @@ __global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
     if (o.status == 0) {
       const unsigned long long key = select_key(o);
       const int32_t *hl = B.trk_hits + (int64_t)t * R;
+      const int ucl = B.units[B.trk_unit[t]].cl_begin;
       unsigned long long *wm = B.wonmask + (int64_t)t * 4;
       const int n = o.n_hits;
       unsigned long long cur = 0;
@@ -1305,7 +1320,7 @@ __global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
       for (int j0 = 0; j0 < n; j0 += 8) {
         int h[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) h[q] = j0 + q < n ? hl[j0 + q] : -1;
+        for (int q = 0; q < 8; ++q) h[q] = j0 + q < n ? slot_hit(hl[j0 + q], ucl) : -1;
         unsigned int bits = 0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -1459,7 +1474,7 @@ __global__ __launch_bounds__(kBlock) void k_output(Bufs B, ParamsDev P, int run)
         const int slot = j < ne ? n1 + ne - 1 - j : j - ne;
         const unsigned long long m = slot < 64 ? m0 : slot < 128 ? m1 : slot < 192 ? m2 : m3;
         const bool won = j < nh && ((m >> (slot & 63)) & 1ull);
-        gh[q] = won ? hl[slot] : -1;
+        gh[q] = won ? slot_hit(hl[slot], ucl) : -1;
       }
       int id[8];
 #pragma unroll
@@ -1589,16 +1604,17 @@ hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHo
 hipError_t launch_kf(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s) {
   // persistent: exactly the resident capacity of the chip, work taken from a
   // counter
-  // register budgets: 5 (default), 6 or 8 resident waves per SIMD
-  const int v = P.kf_min_waves >= 8 ? 2 : P.kf_min_waves >= 6 ? 1 : 0;
+  // register budgets: 5 (default), 4 or 6 resident waves per SIMD (more
+  // are not reachable: the block's LDS allows 7)
+  const int v = P.kf_min_waves >= 6 ? 2 : P.kf_min_waves == 4 ? 1 : 0;
   static int cus = 0, per[3] = {0, 0, 0};
   if (cus == 0) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_kf<5>, kKfBlock, 0);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_kf<6>, kKfBlock, 0);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_kf<8>, kKfBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_kf<4>, kKfBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_kf<6>, kKfBlock, 0);
     cus = std::max(1, cus);
     for (int k = 0; k < 3; ++k) per[k] = std::max(1, per[k]);
   }
@@ -1609,9 +1625,11 @@ hipError_t launch_kf(const Bufs &B, const ParamsDev &P, int run, const RunHost &
   hipError_t e = launch_fill_u64(B.owner + h.cl0, h.cl1 - h.cl0, 0ull, s);
   if (e != hipSuccess) return e;
   if (h.trk_cap > 0) {
-    if (v == 2) k_kf<8><<<g, kKfBlock, 0, s>>>(B, P, run);
-    else if (v == 1) k_kf<6><<<g, kKfBlock, 0, s>>>(B, P, run);
-    else k_kf<5><<<g, kKfBlock, 0, s>>>(B, P, run);
+    switch (v) {
+      case 2: k_kf<6><<<g, kKfBlock, 0, s>>>(B, P, run); break;
+      case 1: k_kf<4><<<g, kKfBlock, 0, s>>>(B, P, run); break;
+      default: k_kf<5><<<g, kKfBlock, 0, s>>>(B, P, run); break;
+    }
   }
   return hipGetLastError();
 }

@@ -755,8 +755,9 @@ int tpcca_get_tracklets(tpcca_ctx_t *c, int32_t slot, int32_t sector, tpcca_trac
       const int n1 = trk[t].n_pass1, ne = trk[t].n_hits - trk[t].n_pass1;
       const int32_t *hl = slots.data() + (size_t)t * c->R;
       for (int j = 0; j < trk[t].n_hits; ++j) {
-        const int g = j < ne ? hl[n1 + ne - 1 - j] : hl[j - ne];
-        if (hits) hits[off] = sid[g - U.cl_begin];
+        // slots hold the unit-local sorted index in their low 24 bits
+        const int32_t v = j < ne ? hl[n1 + ne - 1 - j] : hl[j - ne];
+        if (hits) hits[off] = sid[(uint32_t)v & 0xFFFFFFu];
         ++off;
       }
     }
