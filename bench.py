@@ -338,6 +338,8 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command):
           f"WRITE {fac['WRITE_SIZE']:.4f}.", "",
           "| kernel | fetch MB | write MB | total MB |", "|---|---|---|---|"]
     for k in sorted(out["kernels"], key=lambda k: -out["kernels"][k]["bytes"]):
+        if k == "k_kf" and any(q.startswith("k_kf<") for q in out["kernels"]):
+            continue  # alias of the fit kernel's register variant
         e = out["kernels"][k]
         md.append(f"| {k} | {e.get('fetch_size', 0) / 1e6:.1f} | {e.get('write_size', 0) / 1e6:.1f} | "
                   f"{e['bytes'] / 1e6:.1f} |")
