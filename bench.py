@@ -186,7 +186,9 @@ def main():
                 "achieved": round(fit_tf, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(fit_tf / FP32_PEAK_TFLOPS, 4),
                 "traffic": traffic.get("k_kf"), "flops_per_launch": int(flops),
-                "flops_per_step": round(flops / max(1, work["fit_steps"]), 1), "ms": round(fit_ms, 4)}
+                "flops_per_step": round(flops / max(1, work["fit_steps"]), 1),
+                "lane_use": round(work["fit_steps"] / max(1, 64 * work["fit_wave_iterations"]), 4),
+                "ms": round(fit_ms, 4)}
     link_ms = stages["links"]
     link_bytes = LINK_BYTES_PER_CLUSTER * ncl
     link_gbs = link_bytes / (link_ms * 1e-3) / 1e9

@@ -219,9 +219,11 @@ int tpcca_batch_totals(tpcca_ctx_t *ctx, int32_t *n_units, int64_t *n_clusters, 
    clusters, tracklets (fitted candidates), accepted tracks and their hits,
    Kalman row steps (propagations), candidate clusters examined by the
    track-following searches, chi2 tests of the hits those searches picked,
-   and Kalman updates. */
+   Kalman updates, and the fit kernel's loop iterations summed over its
+   64-lane waves (fit_steps / (64 x fit_wave_iterations) is its lane use). */
 typedef struct {
-  int64_t clusters, tracklets, tracks, track_hits, fit_steps, fit_candidates, fit_tests, fit_updates;
+  int64_t clusters, tracklets, tracks, track_hits, fit_steps, fit_candidates, fit_tests, fit_updates,
+      fit_wave_iterations;
 } tpcca_work_stats_t;
 int tpcca_work_stats(tpcca_ctx_t *ctx, tpcca_work_stats_t *out);
 
@@ -243,6 +245,8 @@ typedef struct {
                                 (default); 0: a claim kernel of its own */
   int32_t fit_xcd_slices;    /* 1: the fit's processing order is cut into one slice per XCD;
                                 0: one shared work counter (default) */
+  int32_t link_stage;        /* LDS staging capacity of the neighbour kernel: 0 large (default),
+                                1 medium, 2 small (more blocks per CU, more global fallbacks) */
 } tpcca_tuning_t;
 int tpcca_set_tuning(tpcca_ctx_t *ctx, const tpcca_tuning_t *t);
 int tpcca_get_tuning(tpcca_ctx_t *ctx, tpcca_tuning_t *t);

@@ -72,6 +72,7 @@ struct RunDev {
   unsigned long long kf_cands;   // candidate hits examined by the fit's searches
   unsigned long long kf_tests;   // chi2 tests of searched hits
   unsigned long long kf_updates; // Kalman updates
+  unsigned long long kf_iters;   // state-machine iterations summed over the fit's waves
 };
 
 // Device-side parameters (FP32 copies of tpcca_params_t).
@@ -90,6 +91,7 @@ struct ParamsDev {
   int32_t kf_min_waves;
   int32_t kf_claims;   // 1: the fit writes the selection's claims, 0: a kernel of its own
   int32_t kf_xcd;      // 1: the fit's order is cut into one slice per XCD
+  int32_t link_stage;  // staging capacity variant of the neighbour kernel (0..2)
 };
 
 // Device buffers of a context (all indices global).

@@ -130,6 +130,7 @@ __global__ void k_run_reset(Bufs B, int run, int R) {
     rd.kf_cands = 0;
     rd.kf_tests = 0;
     rd.kf_updates = 0;
+    rd.kf_iters = 0;
   }
 }
 
@@ -387,21 +388,25 @@ __device__ __forceinline__ int row_of(const RowTab *t, int R, int g) {
 // ranges exceed the LDS capacity read the candidates from global memory.
 // Tiles are walked XCD by XCD so that neighbouring rows of a unit share an
 // L2.
-constexpr int kNbrCap = 1536;   // staged hits per neighbour row
-constexpr int kBinCap = 1024;   // staged bin offsets per neighbour row
+// Staging capacities come in variants (tuning knob link_stage): larger ones
+// fall back to global memory less often, smaller ones let more blocks share
+// a CU's LDS.
+template <int kV> struct LinkCaps;
+template <> struct LinkCaps<0> { static constexpr int nbr = 1536, bins = 1024, keep = 8; };
+template <> struct LinkCaps<1> { static constexpr int nbr = 768, bins = 512, keep = 4; };
+template <> struct LinkCaps<2> { static constexpr int nbr = 512, bins = 256, keep = 4; };
 
 // Candidates inside the window are first collected per side (up to kKeep
 // each, in LDS), then paired: the pair loop runs over the short lists, so
 // lanes with different candidate counts do not multiply their trip counts.
 // A side with more than kKeep window hits falls back to the full double loop.
-constexpr int kKeep = 8;
 
 template <bool kLds>
 __device__ __forceinline__ float2 cand(const Bufs &B, const float2 *src, int i, int off) {
   return kLds ? src[i - off] : B.yz[i];
 }
 
-template <bool kLds>
+template <bool kLds, int kKeep>
 __device__ __forceinline__ void link_hit(const Bufs &B, const ParamsDev &P, float2 h, float luy,
                                          float luz, float ldy, float ldz, float w, int ub, int ue,
                                          int db, int de, const float2 *cu_src, const float2 *cd_src,
@@ -458,7 +463,9 @@ __device__ __forceinline__ void link_hit(const Bufs &B, const ParamsDev &P, floa
   }
 }
 
+template <int kV>
 __global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
+  constexpr int kNbrCap = LinkCaps<kV>::nbr, kBinCap = LinkCaps<kV>::bins, kKeep = LinkCaps<kV>::keep;
   __shared__ float2 s_up[kNbrCap], s_dn[kNbrCap];
   __shared__ int32_t s_bup[kBinCap + 1], s_bdn[kBinCap + 1];
   __shared__ int s_red[2 * (kTile / 64)];
@@ -535,12 +542,12 @@ __global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
       if (lds) {
         const int ub = s_bup[bu0 - ublo], ue = s_bup[bu1 + 1 - ublo];
         const int db = s_bdn[bd0 - dblo], de = s_bdn[bd1 + 1 - dblo];
-        link_hit<true>(B, P, h, luy, luz, ldy, ldz, w, ub, ue, db, de, s_up, s_dn, ua, da,
+        link_hit<true, kKeep>(B, P, h, luy, luz, ldy, ldz, w, ub, ue, db, de, s_up, s_dn, ua, da,
                        s_keep + i, s_keep + kKeep * kTile + i, bu, bd);
       } else {
         const int ub = B.binbeg[tu.bin0 + bu0], ue = B.binbeg[tu.bin0 + bu1 + 1];
         const int db = B.binbeg[td.bin0 + bd0], de = B.binbeg[td.bin0 + bd1 + 1];
-        link_hit<false>(B, P, h, luy, luz, ldy, ldz, w, ub, ue, db, de, nullptr, nullptr, 0, 0,
+        link_hit<false, kKeep>(B, P, h, luy, luz, ldy, ldz, w, ub, ue, db, de, nullptr, nullptr, 0, 0,
                         s_keep + i, s_keep + kKeep * kTile + i, bu, bd);
       }
       B.up[g] = bu;
@@ -1036,7 +1043,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
   };
   float chi2 = 0.0f;
   unsigned int cands = 0;
-  unsigned int steps = 0, tests = 0, updates = 0;  // wave totals (scalar)
+  unsigned int steps = 0, tests = 0, updates = 0, iters = 0;  // wave totals (scalar)
   int pnext = 0, pend = 0;  // wave-private pool of claimed tracklets
   // The processing order is cut into one slice per XCD.  Block b runs on
   // XCD b mod 8, whose waves drain that slice first (its L2 then holds the
@@ -1132,6 +1139,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
     // ---- the step: one propagation, one search, one test, one update
     bool ok = true;
     steps += __popcll(__ballot(prop));
+    ++iters;
     if (prop) ok = kf_propagate(P, st, s_rx[row]);
     int h = given;
     const bool search = act && ok && given < 0;
@@ -1264,6 +1272,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
     atomicAdd(&rd.kf_cands, c64);
     atomicAdd(&rd.kf_tests, (unsigned long long)tests);
     atomicAdd(&rd.kf_updates, (unsigned long long)updates);
+    atomicAdd(&rd.kf_iters, (unsigned long long)iters);
   }
 }
 
@@ -1562,7 +1571,11 @@ hipError_t launch_links(const Bufs &B, const ParamsDev &P, int run, const RunHos
   if (nt > 0) {
     int g = grid_for(nt, 1, 256 * (P.link_blocks_per_cu > 0 ? P.link_blocks_per_cu : 32));
     g = (g + 7) & ~7;  // a multiple of the 8 XCDs
-    k_links<<<g, kTile, 0, s>>>(B, P, run);
+    switch (P.link_stage) {
+      case 2: k_links<2><<<g, kTile, 0, s>>>(B, P, run); break;
+      case 1: k_links<1><<<g, kTile, 0, s>>>(B, P, run); break;
+      default: k_links<0><<<g, kTile, 0, s>>>(B, P, run); break;
+    }
   }
   return hipGetLastError();
 }

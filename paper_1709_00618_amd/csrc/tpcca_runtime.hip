@@ -571,6 +571,7 @@ int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int 
   P.kf_min_waves = 0;
   P.kf_claims = 1;
   P.kf_xcd = 0;
+  P.link_stage = 0;
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -979,6 +980,7 @@ int tpcca_work_stats(tpcca_ctx_t *c, tpcca_work_stats_t *out) {
       out->fit_candidates += (int64_t)d.kf_cands;
       out->fit_tests += (int64_t)d.kf_tests;
       out->fit_updates += (int64_t)d.kf_updates;
+      out->fit_wave_iterations += (int64_t)d.kf_iters;
     }
     if (lo >= kSelected) {
       out->tracks += d.n_acc;
@@ -1047,7 +1049,7 @@ int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
   if (!c || !t) return TPCCA_EINVAL;
   if (t->fit_pool < 0 || t->fit_pool > 4096 || t->fit_blocks_per_cu < 0 || t->grid_hits_per_bin < 0 ||
       t->link_blocks_per_cu < 0 || t->fit_min_waves < 0 || t->fit_claims < 0 || t->fit_claims > 1 ||
-      t->fit_xcd_slices < 0 || t->fit_xcd_slices > 1)
+      t->fit_xcd_slices < 0 || t->fit_xcd_slices > 1 || t->link_stage < 0 || t->link_stage > 2)
     return TPCCA_EINVAL;
   // the grid layout of loaded units depends on hits per bin
   if (t->grid_hits_per_bin && !c->units.empty() && t->grid_hits_per_bin != c->P.hits_per_bin)
@@ -1055,6 +1057,7 @@ int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
   c->P.kf_min_waves = t->fit_min_waves;
   c->P.kf_claims = t->fit_claims;
   c->P.kf_xcd = t->fit_xcd_slices;
+  c->P.link_stage = t->link_stage;
   c->P.kf_pool = t->fit_pool ? t->fit_pool : 64;
   c->P.kf_blocks_per_cu = t->fit_blocks_per_cu;
   c->P.link_blocks_per_cu = t->link_blocks_per_cu;
@@ -1075,6 +1078,7 @@ int tpcca_get_tuning(tpcca_ctx_t *c, tpcca_tuning_t *t) {
   t->fit_min_waves = c->P.kf_min_waves;
   t->fit_claims = c->P.kf_claims;
   t->fit_xcd_slices = c->P.kf_xcd;
+  t->link_stage = c->P.link_stage;
   return TPCCA_OK;
 }
 
