@@ -320,6 +320,9 @@ int tpcca_server_wait(tpcca_server_t *srv, uint64_t req_id, double timeout_s, tp
 /* Forget a completed request's record. */
 int tpcca_server_release(tpcca_server_t *srv, uint64_t req_id);
 int tpcca_server_stats(tpcca_server_t *srv, tpcca_stats_t *st);
+/* Text of the last failed batch (lane, size, failing step and HIP error),
+   "" if none; the pointer stays valid until the calling thread's next call. */
+const char *tpcca_server_last_error(tpcca_server_t *srv);
 int tpcca_server_reset_stats(tpcca_server_t *srv);
 /* Stop accepting, finish in-flight work, free everything. */
 int tpcca_server_destroy(tpcca_server_t *srv);

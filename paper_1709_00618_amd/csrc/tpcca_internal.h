@@ -46,9 +46,9 @@ struct RowTab {
   int32_t begin;  // global sorted index of the row's first hit
   int32_t count;
   int32_t nb;
-  int32_t pad_;
-  int64_t bin0;
+  int32_t bin0;   // first bin-begin entry of the row (the bin table has < 2^31 entries)
   float z0, inv;  // bin(z) = clamp(floor((z - z0) * inv), 0, nb - 1)
+  int32_t pad_[2];
 };
 
 // Everything one launch needs to know about the units it processes.  The

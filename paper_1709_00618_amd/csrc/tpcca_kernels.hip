@@ -23,6 +23,8 @@
 #include "tpcca_kernels.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 namespace tpcca {
 
@@ -217,8 +219,8 @@ __global__ __launch_bounds__(kBlock) void k_plan(Bufs B, int run, int R, int hit
       t.begin = U.cl_begin + begin;
       t.count = cnt;
       t.nb = nb;
-      t.pad_ = 0;
-      t.bin0 = U.bin_base + boff;
+      t.bin0 = (int32_t)(U.bin_base + boff);
+      t.pad_[0] = t.pad_[1] = 0;
       t.z0 = z0;
       t.inv = (float)nb / span;
       B.rowtab[(int64_t)u * (R + 1) + r] = t;
@@ -911,14 +913,14 @@ __device__ __forceinline__ int32_t slot_enc(int g, int ucl, int row) {
 __device__ __forceinline__ int slot_hit(int32_t v, int ucl) { return ucl + (int)((uint32_t)v & 0xFFFFFFu); }
 __device__ __forceinline__ int slot_row(int32_t v) { return (int)((uint32_t)v >> 24); }
 
-// Nearest hit of row r inside the window; its coordinates are returned in bc.
-__device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, const RowTab *rt,
-                                         const KState &s, int r, unsigned int &cands, float2 &bc) {
+// Nearest hit of the row described by t inside the window; its coordinates
+// are returned in bc.
+__device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, const RowTab &t,
+                                         const KState &s, unsigned int &cands, float2 &bc) {
   float wy = P.nsig * sqrtf(s.C[0] + P.ery);
   float wz = P.nsig * sqrtf(s.C[2] + P.erz);
   if (wy > P.wmax) wy = P.wmax;
   if (wz > P.wmax) wz = P.wmax;
-  const RowTab t = rt[r];
   int b, e;
   bin_range(t, B.binbeg, s.p[1], wz, b, e);
   int best = -1;
@@ -1136,6 +1138,13 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
       row = r;
       if (end) act = prop = false;
     }
+    // loads that do not depend on the propagation are issued before it, so
+    // that their latency overlaps its arithmetic: the given hit, or the
+    // grid description of the row to search
+    float2 c = make_float2(0.0f, 0.0f);
+    RowTab trow;
+    if (given >= 0) c = B.yz[given];
+    else if (act) trow = B.rowtab[(int64_t)u * (R + 1) + row];
     // ---- the step: one propagation, one search, one test, one update
     bool ok = true;
     steps += __popcll(__ballot(prop));
@@ -1143,10 +1152,8 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
     if (prop) ok = kf_propagate(P, st, s_rx[row]);
     int h = given;
     const bool search = act && ok && given < 0;
-    float2 c = make_float2(0.0f, 0.0f);
-    if (search) h = kf_search(B, P, B.rowtab + (int64_t)u * (R + 1), st, row, cands, c);
+    if (search) h = kf_search(B, P, trow, st, cands, c);
     bool acc = act && ok && h >= 0;
-    if (acc && !search) c = B.yz[h];
     tests += __popcll(__ballot(acc && search));
     if (acc && search) {
       float cc2;
@@ -1536,8 +1543,8 @@ __global__ void k_links_by_id(const int32_t *sid, const int32_t *up, const int32
 // ============================================================ launchers ===
 static inline int grid_for(int64_t work, int per_block, int cap) {
   int64_t g = (work + per_block - 1) / per_block;
-  if (g < 1) g = 1;
   if (g > cap) g = cap;
+  if (g < 1) g = 1;  // never an empty grid
   return (int)g;
 }
 
@@ -1614,24 +1621,42 @@ hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHo
   return hipGetLastError();
 }
 
+// Compute units and resident fit blocks per CU of the current device, for
+// each register variant; queried once per device (contexts on several host
+// threads launch concurrently, hence the lock).
+struct KfOccupancy {
+  int cus = 1;
+  int per[3] = {1, 1, 1};
+};
+
+static const KfOccupancy &kf_occupancy() {
+  static std::mutex mu;
+  static std::map<int, KfOccupancy> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  KfOccupancy o;
+  int cus = 0, per[3] = {0, 0, 0};
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_kf<5>, kKfBlock, 0);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_kf<4>, kKfBlock, 0);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_kf<6>, kKfBlock, 0);
+  o.cus = std::max(1, cus);
+  for (int k = 0; k < 3; ++k) o.per[k] = std::max(1, per[k]);
+  return cache.emplace(dev, o).first->second;
+}
+
 hipError_t launch_kf(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s) {
   // persistent: exactly the resident capacity of the chip, work taken from a
   // counter
   // register budgets: 5 (default), 4 or 6 resident waves per SIMD (more
   // are not reachable: the block's LDS allows 7)
   const int v = P.kf_min_waves >= 6 ? 2 : P.kf_min_waves == 4 ? 1 : 0;
-  static int cus = 0, per[3] = {0, 0, 0};
-  if (cus == 0) {
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_kf<5>, kKfBlock, 0);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_kf<4>, kKfBlock, 0);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_kf<6>, kKfBlock, 0);
-    cus = std::max(1, cus);
-    for (int k = 0; k < 3; ++k) per[k] = std::max(1, per[k]);
-  }
-  const int bpc = P.kf_blocks_per_cu > 0 ? std::min(P.kf_blocks_per_cu, per[v]) : per[v];
+  const KfOccupancy &o = kf_occupancy();
+  const int cus = o.cus;
+  const int bpc = P.kf_blocks_per_cu > 0 ? std::min(P.kf_blocks_per_cu, o.per[v]) : o.per[v];
   const int g = grid_for(h.trk_cap, kKfBlock, cus * bpc);
   // the claim words of the selection start at zero (the fit may write them
   // as its tracklets end)

@@ -4,7 +4,13 @@
 
 #include "tpcca.h"
 
+#include <mutex>
+
 namespace tpcca {
 hipStream_t ctx_stream(tpcca_ctx_t *c);
 size_t ctx_allocated(tpcca_ctx_t *c);
+// Held by every call that may synchronise the device (allocation, release,
+// stream and context set-up) and by graph capture, so that no capture on
+// one thread meets such a call from another.
+std::recursive_mutex &device_ops_lock();
 }  // namespace tpcca

@@ -76,6 +76,7 @@ struct tpcca_ctx {
   float stage_ms[6] = {};
   bool have_times = false;
   bool capturing = false;       // a graph capture is in progress
+  int64_t graph_fallbacks = 0;  // batches run without a graph after a failed capture
   bool gtiming = false;         // the captured graph holds stage events
 
   std::string last_error;
@@ -97,11 +98,27 @@ static int dev_err(tpcca_ctx *c, hipError_t e, const char *what) {
   }
   return TPCCA_EDEVICE;
 }
+#define RCCHK(call)                  \
+  do {                               \
+    int rc_ = (call);                \
+    if (rc_ != TPCCA_OK) return rc_; \
+  } while (0)
+
 #define HIPCHK(ctx, call)                                   \
   do {                                                      \
     hipError_t e_ = (call);                                 \
     if (e_ != hipSuccess) return dev_err((ctx), e_, #call); \
   } while (0)
+
+// Copy in stream order on the context's own (non-blocking) stream and wait
+// for it: no library call touches the legacy stream, which other threads'
+// graph captures forbid.
+static int copy_sync(tpcca_ctx *c, void *dst, const void *src, size_t bytes, hipMemcpyKind kind) {
+  if (bytes == 0) return TPCCA_OK;
+  HIPCHK(c, hipMemcpyAsync(dst, src, bytes, kind, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TPCCA_OK;
+}
 
 // Grow a device buffer to at least `bytes` (x1.25 headroom), preserving the
 // first `keep` bytes.  Budget-checked.
@@ -116,6 +133,9 @@ static int ensure(tpcca_ctx *c, DevBuf &b, size_t bytes, size_t keep) {
       return TPCCA_ENOMEM;
     }
   }
+  // allocation and release may synchronise the device: never during another
+  // context's graph capture
+  std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
   void *p = nullptr;
   hipError_t e = hipMalloc(&p, nb);
   if (e != hipSuccess) {
@@ -272,7 +292,7 @@ static int write_run(tpcca_ctx *c, int run) {
   d.tile0 = h.tile0;
   d.tile1 = h.tile1;
   // pageable source: the copy completes before return
-  HIPCHK(c, hipMemcpy(ptr<RunDev>(c->runs_d) + run, &d, sizeof(d), hipMemcpyHostToDevice));
+  RCCHK(copy_sync(c, ptr<RunDev>(c->runs_d) + run, &d, sizeof(d), hipMemcpyHostToDevice));
   return TPCCA_OK;
 }
 
@@ -399,7 +419,7 @@ static int check_errors(tpcca_ctx *c) {
   int rc = TPCCA_OK;
   for (int run : c->pending_runs) {
     RunDev d;
-    HIPCHK(c, hipMemcpy(&d, ptr<RunDev>(c->runs_d) + run, sizeof(d), hipMemcpyDeviceToHost));
+    RCCHK(copy_sync(c, &d, ptr<RunDev>(c->runs_d) + run, sizeof(d), hipMemcpyDeviceToHost));
     if (d.err) {
       c->last_error = "invalid cluster (row out of range, non-finite value, or x off its row)";
       rc = TPCCA_EINVAL;
@@ -427,6 +447,8 @@ static int load_unit(tpcca_ctx *c, int32_t slot, int32_t sector, const tpcca_clu
   }
   if (c->index.count({slot, sector})) return TPCCA_ESTATE;
   if (c->n_total + n > (int64_t)0x7FFFFFFF) return TPCCA_ENOMEM;
+  // the grid's bin table is addressed with 32-bit indices
+  if (c->bins_total + bins_cap_of(n, c->P.hits_per_bin, c->R) > (int64_t)0x7FFFFFFF) return TPCCA_ENOMEM;
   UnitDev U{};
   U.n = n;
   U.slot = slot;
@@ -572,6 +594,7 @@ int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int 
   P.kf_claims = 1;
   P.kf_xcd = 0;
   P.link_stage = 0;
+  std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -585,10 +608,7 @@ int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int 
   for (int k = 0; k < 7; ++k) hipEventCreate(&c->ev[k]);
   c->unit_chunk0.push_back(0);
   int rc = ensure(c, c->row_x_d, sizeof(float) * c->R, 0);
-  if (rc == TPCCA_OK) {
-    e = hipMemcpy(c->row_x_d.p, c->row_x.data(), sizeof(float) * c->R, hipMemcpyHostToDevice);
-    if (e != hipSuccess) rc = dev_err(c, e, "hipMemcpy(row_x)");
-  }
+  if (rc == TPCCA_OK) rc = copy_sync(c, c->row_x_d.p, c->row_x.data(), sizeof(float) * c->R, hipMemcpyHostToDevice);
   if (rc != TPCCA_OK) {
     tpcca_destroy(c);
     return rc;
@@ -601,6 +621,7 @@ int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int 
 int tpcca_destroy(tpcca_ctx_t *c) {
   if (!c) return TPCCA_EINVAL;
   hipSetDevice(c->device);
+  std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
   if (c->stream) hipStreamSynchronize(c->stream);
   drop_graphs(c);
   DevBuf *all[] = {&c->row_x_d, &c->units_d, &c->chunks_d, &c->runs_d, &c->rowtab, &c->row_cnt,
@@ -686,7 +707,10 @@ int tpcca_get_links(tpcca_ctx_t *c, int32_t slot, int32_t sector, int32_t which,
   if (rc != TPCCA_OK) return rc;
   if (n == 0) return TPCCA_OK;
   int32_t *tmp = nullptr;
-  HIPCHK(c, hipMalloc(&tmp, sizeof(int32_t) * 2 * (size_t)n));
+  {
+    std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
+    HIPCHK(c, hipMalloc(&tmp, sizeof(int32_t) * 2 * (size_t)n));
+  }
   const UnitDev &U = c->units[u];
   hipError_t e = launch_links_by_id(c->B, which ? c->B.upc : c->B.up, which ? c->B.dnc : c->B.dn,
                                     tmp, tmp + n, U.cl_begin, n, c->stream);
@@ -694,7 +718,10 @@ int tpcca_get_links(tpcca_ctx_t *c, int32_t slot, int32_t sector, int32_t which,
   if (e == hipSuccess)
     e = hipMemcpyAsync(down, tmp + n, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  hipFree(tmp);
+  {
+    std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
+    hipFree(tmp);
+  }
   if (e != hipSuccess) return dev_err(c, e, "get_links");
   return TPCCA_OK;
 }
@@ -704,13 +731,13 @@ static int unit_tracklets(tpcca_ctx *c, int u, int32_t *t0, int32_t *t1) {
   const int run = c->uh[u].run;
   const RunHost &h = c->runs[run];
   int32_t tb[2];
-  HIPCHK(c, hipMemcpy(&tb[0], ptr<int32_t>(c->unit_tbegin) + u, sizeof(int32_t), hipMemcpyDeviceToHost));
+  RCCHK(copy_sync(c, &tb[0], ptr<int32_t>(c->unit_tbegin) + u, sizeof(int32_t), hipMemcpyDeviceToHost));
   if (u + 1 < h.u1) {
-    HIPCHK(c, hipMemcpy(&tb[1], ptr<int32_t>(c->unit_tbegin) + u + 1, sizeof(int32_t),
+    RCCHK(copy_sync(c, &tb[1], ptr<int32_t>(c->unit_tbegin) + u + 1, sizeof(int32_t),
                         hipMemcpyDeviceToHost));
   } else {
     RunDev d;
-    HIPCHK(c, hipMemcpy(&d, ptr<RunDev>(c->runs_d) + run, sizeof(d), hipMemcpyDeviceToHost));
+    RCCHK(copy_sync(c, &d, ptr<RunDev>(c->runs_d) + run, sizeof(d), hipMemcpyDeviceToHost));
     tb[1] = d.trk0 + d.n_trk;
   }
   *t0 = tb[0];
@@ -732,7 +759,7 @@ int tpcca_get_tracklets(tpcca_ctx_t *c, int32_t slot, int32_t sector, tpcca_trac
   const int T = t1 - t0;
   std::vector<tpcca_tracklet_t> trk(T);
   if (T > 0)
-    HIPCHK(c, hipMemcpy(trk.data(), ptr<tpcca_tracklet_t>(c->trk) + t0, sizeof(tpcca_tracklet_t) * T,
+    RCCHK(copy_sync(c, trk.data(), ptr<tpcca_tracklet_t>(c->trk) + t0, sizeof(tpcca_tracklet_t) * T,
                         hipMemcpyDeviceToHost));
   int64_t nh = 0;
   for (auto &t : trk) nh += t.n_hits;
@@ -744,11 +771,11 @@ int tpcca_get_tracklets(tpcca_ctx_t *c, int32_t slot, int32_t sector, tpcca_trac
     const UnitDev &U = c->units[u];
     std::vector<int32_t> sid(U.n);
     if (U.n)
-      HIPCHK(c, hipMemcpy(sid.data(), ptr<int32_t>(c->sid) + U.cl_begin, sizeof(int32_t) * U.n,
+      RCCHK(copy_sync(c, sid.data(), ptr<int32_t>(c->sid) + U.cl_begin, sizeof(int32_t) * U.n,
                           hipMemcpyDeviceToHost));
     std::vector<int32_t> slots((size_t)T * c->R);
     if (T)
-      HIPCHK(c, hipMemcpy(slots.data(), ptr<int32_t>(c->trk_hits) + (int64_t)t0 * c->R,
+      RCCHK(copy_sync(c, slots.data(), ptr<int32_t>(c->trk_hits) + (int64_t)t0 * c->R,
                           sizeof(int32_t) * slots.size(), hipMemcpyDeviceToHost));
     int64_t off = 0;
     for (int t = 0; t < T; ++t) {
@@ -776,15 +803,15 @@ int tpcca_get_tracks(tpcca_ctx_t *c, int32_t slot, int32_t sector, tpcca_track_t
   int rc = check_errors(c);
   if (rc != TPCCA_OK) return rc;
   tpcca_unit_result_t r;
-  HIPCHK(c, hipMemcpy(&r, ptr<tpcca_unit_result_t>(c->unit_res) + u, sizeof(r), hipMemcpyDeviceToHost));
+  RCCHK(copy_sync(c, &r, ptr<tpcca_unit_result_t>(c->unit_res) + u, sizeof(r), hipMemcpyDeviceToHost));
   *n_out = r.n_tracks;
   if (n_hits_out) *n_hits_out = r.n_track_hits;
   if (cap < r.n_tracks || (hits && hits_cap < r.n_track_hits)) return TPCCA_ECAPACITY;
   if (out && r.n_tracks)
-    HIPCHK(c, hipMemcpy(out, ptr<tpcca_track_t>(c->tracks) + r.track_begin,
+    RCCHK(copy_sync(c, out, ptr<tpcca_track_t>(c->tracks) + r.track_begin,
                         sizeof(tpcca_track_t) * r.n_tracks, hipMemcpyDeviceToHost));
   if (hits && r.n_track_hits)
-    HIPCHK(c, hipMemcpy(hits, ptr<int32_t>(c->hits_out) + r.hit_begin, sizeof(int32_t) * r.n_track_hits,
+    RCCHK(copy_sync(c, hits, ptr<int32_t>(c->hits_out) + r.hit_begin, sizeof(int32_t) * r.n_track_hits,
                         hipMemcpyDeviceToHost));
   return TPCCA_OK;
 }
@@ -798,7 +825,7 @@ int tpcca_get_assignment(tpcca_ctx_t *c, int32_t slot, int32_t sector, int32_t *
   int rc = check_errors(c);
   if (rc != TPCCA_OK) return rc;
   if (n)
-    HIPCHK(c, hipMemcpy(a, ptr<int32_t>(c->assign) + c->units[u].cl_begin, sizeof(int32_t) * n,
+    RCCHK(copy_sync(c, a, ptr<int32_t>(c->assign) + c->units[u].cl_begin, sizeof(int32_t) * n,
                         hipMemcpyDeviceToHost));
   return TPCCA_OK;
 }
@@ -890,6 +917,7 @@ int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
                      c->gcap.trk_cap == capr.trk_cap && c->gcap.tile1 == capr.tile1 &&
                      c->gtiming == c->timing;
   if (!reuse) {
+    std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
     drop_graphs(c);
     // one graph of the whole sequence, or with timing on one graph per timed
     // segment (HIP events between the replays of the segments)
@@ -908,10 +936,14 @@ int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
       // always end the capture, also after a failed launch
       hipError_t e = hipStreamEndCapture(c->stream, &g);
       if (le != hipSuccess || e != hipSuccess) {
+        // the capture was invalidated (for instance by a device-wide
+        // synchronisation from a thread outside this library): run this
+        // batch without a graph; a real launch error shows there again
         if (g) hipGraphDestroy(g);
         drop_graphs(c);
-        return le != hipSuccess ? dev_err(c, le, "kernel launch under capture")
-                                : dev_err(c, e, "hipStreamEndCapture");
+        (void)hipGetLastError();
+        ++c->graph_fallbacks;
+        return launch_stages(c, 0, c->runs[0], 1, 4);
       }
       e = hipGraphInstantiate(&c->gexec[k], g, nullptr, nullptr, 0);
       hipGraphDestroy(g);
@@ -949,7 +981,7 @@ int tpcca_batch_totals(tpcca_ctx_t *c, int32_t *n_units, int64_t *n_clusters, in
   int64_t nt = 0, nh = 0;
   for (size_t r = 0; r < c->runs.size(); ++r) {
     RunDev d;
-    HIPCHK(c, hipMemcpy(&d, ptr<RunDev>(c->runs_d) + r, sizeof(d), hipMemcpyDeviceToHost));
+    RCCHK(copy_sync(c, &d, ptr<RunDev>(c->runs_d) + r, sizeof(d), hipMemcpyDeviceToHost));
     bool selected = true;
     for (int u = c->runs[r].u0; u < c->runs[r].u1; ++u) selected &= c->uh[u].state >= kSelected;
     if (selected) {
@@ -971,7 +1003,7 @@ int tpcca_work_stats(tpcca_ctx_t *c, tpcca_work_stats_t *out) {
   out->clusters = c->n_total;
   for (size_t r = 0; r < c->runs.size(); ++r) {
     RunDev d;
-    HIPCHK(c, hipMemcpy(&d, ptr<RunDev>(c->runs_d) + r, sizeof(d), hipMemcpyDeviceToHost));
+    RCCHK(copy_sync(c, &d, ptr<RunDev>(c->runs_d) + r, sizeof(d), hipMemcpyDeviceToHost));
     int lo = kSelected;
     for (int u = c->runs[r].u0; u < c->runs[r].u1; ++u) lo = std::min(lo, c->uh[u].state);
     if (lo >= kTracklets) {
@@ -1002,7 +1034,7 @@ int tpcca_get_batch_results(tpcca_ctx_t *c, tpcca_unit_result_t *units, tpcca_tr
     if (c->uh[u].state < kSelected) return TPCCA_ESTATE;
   std::vector<tpcca_unit_result_t> ur(U);
   if (U)
-    HIPCHK(c, hipMemcpy(ur.data(), c->unit_res.p, sizeof(tpcca_unit_result_t) * U, hipMemcpyDeviceToHost));
+    RCCHK(copy_sync(c, ur.data(), c->unit_res.p, sizeof(tpcca_unit_result_t) * U, hipMemcpyDeviceToHost));
   int64_t nt = 0, nh = 0;
   for (auto &r : ur) {
     nt += r.n_tracks;
@@ -1100,6 +1132,10 @@ int tpcca_stage_times(tpcca_ctx_t *c, float *ms, int32_t cap) {
 
 // ------------------------------------------------ internal (server) hooks ---
 namespace tpcca {
+std::recursive_mutex &device_ops_lock() {
+  static std::recursive_mutex mu;
+  return mu;
+}
 hipStream_t ctx_stream(tpcca_ctx *c) { return c->stream; }
 size_t ctx_allocated(tpcca_ctx *c) { return c->allocated; }
 }  // namespace tpcca

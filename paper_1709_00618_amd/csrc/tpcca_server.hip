@@ -25,6 +25,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <string>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -88,6 +89,7 @@ struct tpcca_server {
   int active = 0;
   double busy_since = 0, busy_total = 0;
   std::vector<double> latencies;
+  std::string last_error;  // text of the last failed batch
 };
 
 namespace {
@@ -131,8 +133,10 @@ void lane_main(tpcca_server *S, int lane) {
       S->bytes_in_flight += ncl * kBytesPerCluster;
     }
     int rc = TPCCA_OK;
+    std::string fail_text;
     // inputs: one device span per batch, unit slices copied from the frames
     if (ncl > d_cap) {
+      std::lock_guard<std::recursive_mutex> dlock(tpcca::device_ops_lock());
       if (d_cl) hipFree(d_cl);
       if (d_row) hipFree(d_row);
       d_cap = std::max<int64_t>(ncl, d_cap + d_cap / 2);
@@ -175,14 +179,23 @@ void lane_main(tpcca_server *S, int lane) {
       b.row = d_row;
       b.flags = TPCCA_MEM_DEVICE | TPCCA_BATCH_GRAPH;
       rc = tpcca_run_batch(ctx, &b);
+      if (rc != TPCCA_OK) fail_text = std::string("run_batch: ") + tpcca_last_error(ctx);
+    } else {
+      fail_text = "input staging";
     }
     tpcca_device_results_t dr{};
-    if (rc == TPCCA_OK) rc = tpcca_device_results(ctx, &dr);  // synchronises
+    if (rc == TPCCA_OK) {
+      rc = tpcca_device_results(ctx, &dr);  // synchronises
+      if (rc != TPCCA_OK) fail_text = std::string("device_results: ") + tpcca_last_error(ctx);
+    }
     if (rc == TPCCA_OK) {
       ur.resize(U);
-      if (hipMemcpy(ur.data(), dr.units, sizeof(tpcca_unit_result_t) * U, hipMemcpyDeviceToHost) !=
-          hipSuccess)
+      if (hipMemcpyAsync(ur.data(), dr.units, sizeof(tpcca_unit_result_t) * U, hipMemcpyDeviceToHost, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
         rc = TPCCA_EDEVICE;
+        fail_text = "unit results copy";
+      }
     }
     // outputs: reserve ranges in each frame's buffers, then copy
     std::vector<int64_t> tpos(U, 0), hpos(U, 0);
@@ -217,11 +230,23 @@ void lane_main(tpcca_server *S, int lane) {
       if (e == hipSuccess && r.n[u] && r.tf.assignment)
         e = hipMemcpyAsync(r.tf.assignment + r.cl_offset[u], dr.assignment + ur[i].cluster_begin,
                            sizeof(int32_t) * r.n[u], hipMemcpyDeviceToHost, st);
-      if (e != hipSuccess) rc = TPCCA_EDEVICE;
+      if (e != hipSuccess) {
+        rc = TPCCA_EDEVICE;
+        fail_text = std::string("result copy: ") + hipGetErrorString(e);
+      }
     }
-    if (rc == TPCCA_OK && hipStreamSynchronize(st) != hipSuccess) rc = TPCCA_EDEVICE;
+    if (rc == TPCCA_OK) {
+      const hipError_t e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        rc = TPCCA_EDEVICE;
+        fail_text = std::string("result copy: ") + hipGetErrorString(e);
+      }
+    }
     {
       std::lock_guard<std::mutex> lk(S->mu);
+      if (rc != TPCCA_OK)
+        S->last_error = "lane " + std::to_string(lane) + ", batch of " + std::to_string(U) + " units, " +
+                        std::to_string(ncl) + " clusters: " + fail_text;
       const double t = now_s();
       for (int i = 0; i < U; ++i) {
         Request &r = *items[i].req;
@@ -257,8 +282,11 @@ void lane_main(tpcca_server *S, int lane) {
     S->cv_done.notify_all();
     S->cv_work.notify_all();
   }
-  if (d_cl) hipFree(d_cl);
-  if (d_row) hipFree(d_row);
+  {
+    std::lock_guard<std::recursive_mutex> dlock(tpcca::device_ops_lock());
+    if (d_cl) hipFree(d_cl);
+    if (d_row) hipFree(d_row);
+  }
   tpcca_destroy(ctx);
   (void)lane;
 }
@@ -386,6 +414,14 @@ int tpcca_server_release(tpcca_server_t *S, uint64_t id) {
   if (!it->second->done) return TPCCA_ESTATE;
   S->all.erase(it);
   return TPCCA_OK;
+}
+
+const char *tpcca_server_last_error(tpcca_server_t *S) {
+  static thread_local std::string copy;
+  if (!S) return "";
+  std::lock_guard<std::mutex> lk(S->mu);
+  copy = S->last_error;
+  return copy.c_str();
 }
 
 int tpcca_server_stats(tpcca_server_t *S, tpcca_stats_t *st) {

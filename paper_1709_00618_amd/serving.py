@@ -100,6 +100,10 @@ class Server:
     def reset_stats(self):
         tpcca.lib().tpcca_server_reset_stats(self.h)
 
+    def last_error(self) -> str:
+        t = tpcca.lib().tpcca_server_last_error(self.h)
+        return t.decode(errors="replace") if t else ""
+
     def close(self):
         if getattr(self, "h", None):
             tpcca.lib().tpcca_server_destroy(self.h)
@@ -155,7 +159,7 @@ def _finish(srv, rid):
     r = srv.wait(rid)
     srv.release(rid)
     if r.status != tpcca.OK:
-        raise tpcca.TpccaError(r.status, f"served request {rid}")
+        raise tpcca.TpccaError(r.status, f"served request {rid}", srv.last_error())
 
 
 def bench_served(row_x, n_tf=48, ring=8, n_streams=3, seed=0, log=print):

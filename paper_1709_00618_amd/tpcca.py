@@ -105,6 +105,7 @@ SYMBOLS = (
     "tpcca_last_error", "tpcca_stage_times", "tpcca_set_timing", "tpcca_server_create",
     "tpcca_server_submit", "tpcca_server_poll", "tpcca_server_wait", "tpcca_server_release",
     "tpcca_server_stats", "tpcca_server_reset_stats", "tpcca_server_destroy", "tpcca_now",
+    "tpcca_server_last_error",
     "tpcca_work_stats", "tpcca_set_tuning", "tpcca_get_tuning",
 )
 
@@ -153,6 +154,7 @@ def lib():
         "tpcca_server_wait": (c_i32, [c_vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(Result)]),
         "tpcca_server_release": (c_i32, [c_vp, ctypes.c_uint64]),
         "tpcca_server_stats": (c_i32, [c_vp, ctypes.POINTER(Stats)]),
+        "tpcca_server_last_error": (ctypes.c_char_p, [c_vp]),
         "tpcca_server_reset_stats": (c_i32, [c_vp]),
         "tpcca_server_destroy": (c_i32, [c_vp]),
         "tpcca_now": (ctypes.c_double, []),
