@@ -316,11 +316,17 @@ __global__ __launch_bounds__(kBlock) void k_rowscatter(Bufs B, int run, int R) {
   }
 }
 
+// LDS index of bin k in the row sort's histogram: one padding word per 32
+// bins, so that the scan's per-thread runs of 32 consecutive bins start in
+// different banks.
+__device__ __forceinline__ int hpad(int k) { return k + (k >> 5); }
+
 // Pass 4, one block per (unit, row): counting sort of the row's records by
 // z bin in LDS; writes the row's bin offsets and its sorted hits.  The
 // scattered writes stay inside the row's own segment.
+
 __global__ __launch_bounds__(kBlock) void k_rowsort(Bufs B, int run, int R) {
-  __shared__ int hist[kMaxBinsRow];
+  __shared__ int hist[kMaxBinsRow + kMaxBinsRow / 32];
   __shared__ int lds[kBlock / 64 + 1];
   const RunDev &rd = B.runs[run];
   const int nrows = (rd.u1 - rd.u0) * (R + 1);
@@ -328,11 +334,11 @@ __global__ __launch_bounds__(kBlock) void k_rowsort(Bufs B, int run, int R) {
   for (int w = blockIdx.x; w < nrows; w += gridDim.x) {
     const int64_t rr = (int64_t)rd.u0 * (R + 1) + w;
     const RowTab t = B.rowtab[rr];
-    for (int k = threadIdx.x; k < t.nb; k += blockDim.x) hist[k] = 0;
+    for (int k = threadIdx.x; k < t.nb; k += blockDim.x) hist[hpad(k)] = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < t.count; i += blockDim.x) {
       const int4 rec = B.rtmp[t.begin + i];
-      atomicAdd(&hist[zbin(t, __int_as_float(rec.y))], 1);
+      atomicAdd(&hist[hpad(zbin(t, __int_as_float(rec.y)))], 1);
     }
     __syncthreads();
     // exclusive scan of the nb bin counts (per consecutive entries per thread)
@@ -340,25 +346,25 @@ __global__ __launch_bounds__(kBlock) void k_rowsort(Bufs B, int run, int R) {
     int loc = 0;
     for (int q = 0; q < per; ++q) {
       const int k = threadIdx.x * per + q;
-      v[q] = k < t.nb ? hist[k] : 0;
+      v[q] = k < t.nb ? hist[hpad(k)] : 0;
       loc += v[q];
     }
     int tot;
     int ex = block_exclusive_scan<int>(loc, lds, &tot);
     for (int q = 0; q < per; ++q) {
       const int k = threadIdx.x * per + q;
-      if (k < t.nb) {
-        hist[k] = ex;
-        B.binbeg[t.bin0 + k] = t.begin + ex;
-      }
+      if (k < t.nb) hist[hpad(k)] = ex;
       ex += v[q];
     }
-    if (threadIdx.x == 0) B.binbeg[t.bin0 + t.nb] = t.begin + t.count;
     __syncthreads();
+    // bin begins, written in coalesced order
+    for (int k = threadIdx.x; k < t.nb; k += blockDim.x) B.binbeg[t.bin0 + k] = t.begin + hist[hpad(k)];
+    if (threadIdx.x == 0) B.binbeg[t.bin0 + t.nb] = t.begin + t.count;
+    __syncthreads();  // every begin is read before the scatter moves the cursors
     for (int i = threadIdx.x; i < t.count; i += blockDim.x) {
       const int4 rec = B.rtmp[t.begin + i];
       const float z = __int_as_float(rec.y);
-      const int pos = t.begin + atomicAdd(&hist[zbin(t, z)], 1);
+      const int pos = t.begin + atomicAdd(&hist[hpad(zbin(t, z))], 1);
       B.yz[pos] = make_float2(__int_as_float(rec.x), z);
       B.sid[pos] = rec.z;
       B.srow[pos] = (uint8_t)rec.w;
