@@ -103,6 +103,7 @@ struct Bufs {
   RowTab *rowtab;        // units x (n_rows + 1)
   int32_t *row_cnt;      // units x (n_rows + 1)
   int32_t *row_fill;     // units x (n_rows + 1): reservation cursors of the row scatter
+  int32_t *chunk_hist;   // chunks x (n_rows + 1): clusters of each chunk per row (count pass)
   int4 *rtmp;            // row-grouped staging records (y, z, id, row) by global index
   int32_t *zmm;          // units x 2 (ordered-int min, max)
   int32_t *binbeg;       // bins

@@ -183,8 +183,10 @@ __global__ __launch_bounds__(kBlock) void k_count(Bufs B, int run, int R) {
       }
       if (serr) B.runs[run].err = 1;
     }
-    for (int r = threadIdx.x; r <= R; r += blockDim.x)
+    for (int r = threadIdx.x; r <= R; r += blockDim.x) {
+      B.chunk_hist[(int64_t)c * (R + 1) + r] = hist[r];
       if (hist[r]) atomicAdd(&B.row_cnt[(int64_t)ch.unit * (R + 1) + r], hist[r]);
+    }
     __syncthreads();
   }
 }
@@ -240,10 +242,11 @@ __global__ __launch_bounds__(kBlock) void k_plan(Bufs B, int run, int R, int hit
 }
 
 // Pass 3: group the clusters by (unit, row) into the staging buffer.  A
-// block takes up to four consecutive chunks (kGroup), sorts their clusters
-// by (unit, row) in LDS, reserves one contiguous range per (unit, row) in
-// the row's segment, and writes runs of records.  The order inside a row
-// is arbitrary (every later decision compares cluster IDs, never positions).
+// block takes up to four consecutive chunks (kGroup), adds up their row
+// histograms from the count pass, reserves one contiguous range per
+// (unit, row) in the row's segment, and writes the records there through
+// LDS cursors.  The order inside a row is arbitrary (every later decision
+// compares cluster IDs, never positions).
 constexpr int kGroup = 4;
 
 __global__ __launch_bounds__(kBlock) void k_rowscatter(Bufs B, int run, int R) {
@@ -270,18 +273,12 @@ __global__ __launch_bounds__(kBlock) void k_rowscatter(Bufs B, int run, int R) {
       }
     }
     __syncthreads();
-    // pass a: histogram of (unit slot, row)
+    // histogram of (unit slot, row): the count pass's per-chunk histograms
     for (int c = c0; c < c1; ++c) {
-      const Chunk ch = B.chunks[c];
-      const UnitDev U = B.units[ch.unit];
       const int so = slot_unit[c - c0] * (R + 1);
-      for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
-        const int li = ch.begin + i;
-        const int r = valid_row(U.cl[li], U.row[li], B.row_x, R);
-        atomicAdd(&hist[so + r], 1);
-      }
+      for (int r = threadIdx.x; r <= R; r += blockDim.x) hist[so + r] += B.chunk_hist[(int64_t)c * (R + 1) + r];
+      __syncthreads();  // chunks of one unit add into the same slots
     }
-    __syncthreads();
     // reserve one range per non-empty (unit, row)
     for (int k = threadIdx.x; k < nslots; k += blockDim.x) {
       const int cnt = hist[k];
@@ -299,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_rowscatter(Bufs B, int run, int R) {
       }
     }
     __syncthreads();
-    // pass b: write the records into the reserved runs
+    // write the records into the reserved runs
     for (int c = c0; c < c1; ++c) {
       const Chunk ch = B.chunks[c];
       const UnitDev U = B.units[ch.unit];
@@ -336,6 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsort(Bufs B, int run, int R) {
     const RowTab t = B.rowtab[rr];
     for (int k = threadIdx.x; k < t.nb; k += blockDim.x) hist[hpad(k)] = 0;
     __syncthreads();
+#pragma unroll 4
     for (int i = threadIdx.x; i < t.count; i += blockDim.x) {
       const int4 rec = B.rtmp[t.begin + i];
       atomicAdd(&hist[hpad(zbin(t, __int_as_float(rec.y)))], 1);
@@ -361,6 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsort(Bufs B, int run, int R) {
     for (int k = threadIdx.x; k < t.nb; k += blockDim.x) B.binbeg[t.bin0 + k] = t.begin + hist[hpad(k)];
     if (threadIdx.x == 0) B.binbeg[t.bin0 + t.nb] = t.begin + t.count;
     __syncthreads();  // every begin is read before the scatter moves the cursors
+#pragma unroll 4
     for (int i = threadIdx.x; i < t.count; i += blockDim.x) {
       const int4 rec = B.rtmp[t.begin + i];
       const float z = __int_as_float(rec.y);

@@ -60,7 +60,7 @@ struct tpcca_ctx {
   std::vector<int> pending_runs;  // runs launched since the last sync
 
   // device buffers
-  DevBuf row_x_d, units_d, chunks_d, runs_d, rowtab, row_cnt, row_fill, rtmp, zmm, binbeg, yz, sid, up,
+  DevBuf row_x_d, units_d, chunks_d, runs_d, rowtab, row_cnt, row_fill, chunk_hist, rtmp, zmm, binbeg, yz, sid, up,
       dn, upc, dnc, flag, starts, tiles, sval, tofg, kf_order, srow, cinfo, trk_start, trk_unit, unit_tbegin, trk, trk_hits, owner, accv, wonmask, accx,
       tracks, hits_out, assign, unit_res, scan_tmp, in_cl, in_row;
   Bufs B{};
@@ -172,6 +172,7 @@ static void refresh_bufs(tpcca_ctx *c) {
   B.rowtab = ptr<RowTab>(c->rowtab);
   B.row_cnt = ptr<int32_t>(c->row_cnt);
   B.row_fill = ptr<int32_t>(c->row_fill);
+  B.chunk_hist = ptr<int32_t>(c->chunk_hist);
   B.rtmp = ptr<int4>(c->rtmp);
   B.zmm = ptr<int32_t>(c->zmm);
   B.binbeg = ptr<int32_t>(c->binbeg);
@@ -225,6 +226,7 @@ static int ensure_work(tpcca_ctx *c, int64_t n_cl, int64_t n_units, int64_t n_bi
   ENS(rowtab, U * (R + 1), sizeof(RowTab), keepU * (R + 1));
   ENS(row_cnt, U * (R + 1), sizeof(int32_t), keepU * (R + 1));
   ENS(row_fill, U * (R + 1), sizeof(int32_t), 0);
+  ENS(chunk_hist, NC * (R + 1), sizeof(int32_t), 0);
   ENS(rtmp, N, sizeof(int4), 0);
   ENS(zmm, 2 * U, sizeof(int32_t), 2 * keepU);
   ENS(binbeg, NB, sizeof(int32_t), keepB);
@@ -625,7 +627,7 @@ int tpcca_destroy(tpcca_ctx_t *c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   drop_graphs(c);
   DevBuf *all[] = {&c->row_x_d, &c->units_d, &c->chunks_d, &c->runs_d, &c->rowtab, &c->row_cnt,
-                   &c->row_fill, &c->rtmp,
+                   &c->row_fill, &c->chunk_hist, &c->rtmp,
                    &c->zmm, &c->binbeg, &c->yz, &c->sid, &c->up, &c->dn, &c->upc,
                    &c->dnc, &c->flag, &c->starts, &c->tiles, &c->sval, &c->tofg, &c->kf_order, &c->srow, &c->cinfo, &c->trk_start, &c->trk_unit, &c->unit_tbegin, &c->trk,
                    &c->trk_hits, &c->owner, &c->accv, &c->wonmask, &c->accx, &c->tracks, &c->hits_out,
