@@ -247,6 +247,8 @@ typedef struct {
                                 0: one shared work counter (default) */
   int32_t link_stage;        /* LDS staging capacity of the neighbour kernel: 0 large (default),
                                 1 medium, 2 small (more blocks per CU, more global fallbacks) */
+  int32_t fit_long_first;    /* tracklets whose chain has at least this many hits are fitted
+                                first (shorter fits drain the end of the kernel); 0: off */
 } tpcca_tuning_t;
 int tpcca_set_tuning(tpcca_ctx_t *ctx, const tpcca_tuning_t *t);
 int tpcca_get_tuning(tpcca_ctx_t *ctx, tpcca_tuning_t *t);

@@ -19,10 +19,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning_cache.json")
 
 SPACE = {
-    "fit_pool": [32, 64, 128],
+    "fit_pool": [64, 128],
     "fit_min_waves": [0, 4],
     "fit_claims": [0, 1],
-    "link_stage": [0, 1, 2],
+    "fit_long_first": [0, 20, 40, 80],
 }
 
 
@@ -111,5 +111,5 @@ def tuned(ctx, cl, row, units, n_clusters, device=True, log=None, retune=False):
 
 
 def _default(table):
-    d = {"fit_pool": 64, "fit_min_waves": 0, "fit_claims": 1, "link_stage": 0}
+    d = {"fit_pool": 64, "fit_min_waves": 0, "fit_claims": 1, "fit_long_first": 0}
     return d if any(k == d for _, k in table) else None

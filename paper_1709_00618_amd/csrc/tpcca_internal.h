@@ -92,6 +92,7 @@ struct ParamsDev {
   int32_t kf_claims;   // 1: the fit writes the selection's claims, 0: a kernel of its own
   int32_t kf_xcd;      // 1: the fit's order is cut into one slice per XCD
   int32_t link_stage;  // staging capacity variant of the neighbour kernel (0..2)
+  int32_t kf_split;    // chains of at least this many hits are fitted first (0: off)
 };
 
 // Device buffers of a context (all indices global).

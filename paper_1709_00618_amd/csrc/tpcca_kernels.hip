@@ -628,7 +628,8 @@ __global__ __launch_bounds__(kBlock) void k_chain(Bufs B, ParamsDev P, int run) 
     if (n >= P.min_chain) {
       B.flag[st.y] = g + 1;
       B.cinfo[g] = make_int2(last, n);
-      B.sval[g] = 1;
+      // 2: a long chain, fitted in the first part of the processing order
+      B.sval[g] = (P.kf_split > 0 && n >= P.kf_split) ? 2 : 1;
     }
   }
 }
@@ -705,21 +706,37 @@ __global__ __launch_bounds__(kBlock) void k_flag_apply(Bufs B, int run) {
 // (unit, row, z bin) of their start hit, so that the lanes of a wave follow
 // nearby tracks and share cache lines.  Per chunk of sorted hits: count,
 // then (after the tile scan) write the ranks.
+// Processing order of the fit: the start hits in grid order, tracklets of
+// long chains (sval 2) before the others (sval 1) when a split is set.
+// Per chunk the two counts, scanned as one array [long..., short...].
 __global__ __launch_bounds__(kBlock) void k_order_sums(Bufs B, int run) {
-  __shared__ int64_t part[kBlock / 64];
+  __shared__ int64_t part[2][kBlock / 64];
   const RunDev &rd = B.runs[run];
+  const int nch = rd.c1 - rd.c0;
   for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
     const Chunk ch = B.chunks[c];
     const int base = B.units[ch.unit].cl_begin + ch.begin;
-    int64_t v = 0;
-    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) v += B.sval[base + i];
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    int64_t a = 0, b = 0;
+    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
+      const int v = B.sval[base + i];
+      a += v == 2;
+      b += v == 1;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if ((threadIdx.x & 63) == 0) {
+      part[0][threadIdx.x >> 6] = a;
+      part[1][threadIdx.x >> 6] = b;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-      int64_t tot = 0;
-      for (int w = 0; w < kBlock / 64; ++w) tot += part[w];
-      B.scan_tmp[c - rd.c0] = tot;
+      int64_t ta = 0, tb = 0;
+      for (int w = 0; w < kBlock / 64; ++w) {
+        ta += part[0][w];
+        tb += part[1][w];
+      }
+      B.scan_tmp[c - rd.c0] = ta;
+      B.scan_tmp[nch + c - rd.c0] = tb;
     }
     __syncthreads();
   }
@@ -728,24 +745,29 @@ __global__ __launch_bounds__(kBlock) void k_order_sums(Bufs B, int run) {
 __global__ __launch_bounds__(kBlock) void k_order_apply(Bufs B, int run) {
   __shared__ int64_t lds[kBlock / 64 + 1];
   const RunDev &rd = B.runs[run];
+  const int nch = rd.c1 - rd.c0;
   constexpr int per = kChunk / kBlock;
   for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
     const Chunk ch = B.chunks[c];
     const int base = B.units[ch.unit].cl_begin + ch.begin;
     int f[per];
-    int64_t loc = 0;
     for (int k = 0; k < per; ++k) {
       const int i = threadIdx.x * per + k;
       f[k] = i < ch.count ? B.sval[base + i] : 0;
-      loc += f[k];
     }
-    int64_t tot;
-    int64_t ex = block_exclusive_scan<int64_t>(loc, lds, &tot) + B.scan_tmp[c - rd.c0];
-    for (int k = 0; k < per; ++k) {
-      if (f[k]) {
-        B.kf_order[rd.trk0 + (int32_t)ex] = B.tofg[base + threadIdx.x * per + k];
-        ++ex;
+    for (int cls = 2; cls >= 1; --cls) {
+      int64_t loc = 0;
+      for (int k = 0; k < per; ++k) loc += f[k] == cls;
+      int64_t tot;
+      int64_t ex = block_exclusive_scan<int64_t>(loc, lds, &tot) +
+                   B.scan_tmp[(cls == 2 ? 0 : nch) + c - rd.c0];
+      for (int k = 0; k < per; ++k) {
+        if (f[k] == cls) {
+          B.kf_order[rd.trk0 + (int32_t)ex] = B.tofg[base + threadIdx.x * per + k];
+          ++ex;
+        }
       }
+      __syncthreads();  // lds is reused by the next class's scan
     }
   }
 }
@@ -1619,7 +1641,7 @@ hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHo
     k_scan_tiles<<<1, 1024, 0, s>>>(B.scan_tmp, nch);
     k_flag_apply<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
     k_order_sums<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
-    k_scan_tiles<<<1, 1024, 0, s>>>(B.scan_tmp, nch);
+    k_scan_tiles<<<1, 1024, 0, s>>>(B.scan_tmp, 2 * (int64_t)nch);
     k_order_apply<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
   }
   if (nu > 0) k_empty_units<<<grid_for(nu, 64, 1024), 64, 0, s>>>(B, run);

@@ -257,7 +257,7 @@ static int ensure_work(tpcca_ctx *c, int64_t n_cl, int64_t n_units, int64_t n_bi
   ENS(accx, T + 1, sizeof(unsigned long long), 0);
   ENS(tracks, T, sizeof(tpcca_track_t), keepT);
   ENS(unit_res, U, sizeof(tpcca_unit_result_t), keepU);
-  const size_t tiles = std::max(NB / kScanTile + 2, std::max(NC + 2, T / kScanTile + 2));
+  const size_t tiles = std::max(NB / kScanTile + 2, std::max(2 * NC + 2, T / kScanTile + 2));
   ENS(scan_tmp, tiles, sizeof(int64_t), 0);
 #undef ENS
   refresh_bufs(c);
@@ -596,6 +596,7 @@ int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int 
   P.kf_claims = 1;
   P.kf_xcd = 0;
   P.link_stage = 0;
+  P.kf_split = 0;
   std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
@@ -1083,7 +1084,8 @@ int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
   if (!c || !t) return TPCCA_EINVAL;
   if (t->fit_pool < 0 || t->fit_pool > 4096 || t->fit_blocks_per_cu < 0 || t->grid_hits_per_bin < 0 ||
       t->link_blocks_per_cu < 0 || t->fit_min_waves < 0 || t->fit_claims < 0 || t->fit_claims > 1 ||
-      t->fit_xcd_slices < 0 || t->fit_xcd_slices > 1 || t->link_stage < 0 || t->link_stage > 2)
+      t->fit_xcd_slices < 0 || t->fit_xcd_slices > 1 || t->link_stage < 0 || t->link_stage > 2 ||
+      t->fit_long_first < 0)
     return TPCCA_EINVAL;
   // the grid layout of loaded units depends on hits per bin
   if (t->grid_hits_per_bin && !c->units.empty() && t->grid_hits_per_bin != c->P.hits_per_bin)
@@ -1092,6 +1094,7 @@ int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
   c->P.kf_claims = t->fit_claims;
   c->P.kf_xcd = t->fit_xcd_slices;
   c->P.link_stage = t->link_stage;
+  c->P.kf_split = t->fit_long_first;
   c->P.kf_pool = t->fit_pool ? t->fit_pool : 64;
   c->P.kf_blocks_per_cu = t->fit_blocks_per_cu;
   c->P.link_blocks_per_cu = t->link_blocks_per_cu;
@@ -1113,6 +1116,7 @@ int tpcca_get_tuning(tpcca_ctx_t *c, tpcca_tuning_t *t) {
   t->fit_claims = c->P.kf_claims;
   t->fit_xcd_slices = c->P.kf_xcd;
   t->link_stage = c->P.link_stage;
+  t->fit_long_first = c->P.kf_split;
   return TPCCA_OK;
 }
 
