@@ -1340,14 +1340,20 @@ __global__ __launch_bounds__(kBlock) void k_claim(Bufs B, ParamsDev P, int run) 
   }
 }
 
-// Thread per tracklet (64 neighbouring tracklets of the processing order
-// per wave): count the hits it won, record which, accept or reject.  Hit
-// slots and owner words are read eight at a time so that each lane keeps
-// several independent loads in flight.
+// The selection kernels give each tracklet a group of kGrp lanes (four
+// neighbouring tracklets of the processing order per wave): the group walks
+// the tracklet's hit slots kGrp at a time, so a wave's trip count follows
+// the lengths of four tracklets rather than of sixty-four.
+constexpr int kGrp = 16;
+
+// Count the hits a tracklet won, record which, accept or reject.
 __global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
   const RunDev &rd = B.runs[run];
   const int R = P.n_rows;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rd.n_trk; i += gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int gl = lane & (kGrp - 1), g0 = lane & ~(kGrp - 1);
+  const int ng = (gridDim.x * blockDim.x) / kGrp;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / kGrp; i < rd.n_trk; i += ng) {
     const int t = B.kf_order[rd.trk0 + i];
     const int tl = t - rd.trk0;
     const tpcca_tracklet_t &o = B.trk[t];
@@ -1360,27 +1366,21 @@ __global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
       const int n = o.n_hits;
       unsigned long long cur = 0;
       int won = 0;
-      for (int j0 = 0; j0 < n; j0 += 8) {
-        int h[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) h[q] = j0 + q < n ? slot_hit(hl[j0 + q], ucl) : -1;
-        unsigned int bits = 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const bool w = h[q] >= 0 && B.owner[h[q]] == key;
-          bits |= (w ? 1u : 0u) << q;
-        }
+      for (int j0 = 0; j0 < n; j0 += kGrp) {
+        const int j = j0 + gl;
+        const bool w = j < n && B.owner[slot_hit(hl[j], ucl)] == key;
+        const unsigned int bits = (unsigned int)(__ballot(w) >> g0) & ((1u << kGrp) - 1);
         won += __popc(bits);
         cur |= (unsigned long long)bits << (j0 & 63);
-        if (((j0 + 8) & 63) == 0 || j0 + 8 >= n) {  // a 64-slot word is complete
-          wm[j0 >> 6] = cur;
+        if (((j0 + kGrp) & 63) == 0 || j0 + kGrp >= n) {  // a 64-slot word is complete
+          if (gl == 0) wm[j0 >> 6] = cur;
           cur = 0;
         }
       }
       if (won >= P.min_hits && won * 100 >= P.own_pct * n)
         v = (1ull << 40) | (unsigned long long)won;
     }
-    B.accv[tl] = v;
+    if (gl == 0) B.accv[tl] = v;
   }
 }
 
@@ -1480,14 +1480,17 @@ __global__ void k_unit_results(Bufs B, int run) {
   }
 }
 
-// Compaction of accepted tracks, thread per tracklet: parameters, won hits
-// in ascending rows (inward hits were stored after the pass-1 hits, in
-// descending rows) and the per-cluster assignment (unit-local track index).
-// Won slots are gathered eight at a time for independent loads in flight.
+// Compaction of accepted tracks, a group of kGrp lanes per tracklet:
+// parameters, won hits in ascending rows (inward hits were stored after the
+// pass-1 hits, in descending rows) and the per-cluster assignment
+// (unit-local track index).
 __global__ __launch_bounds__(kBlock) void k_output(Bufs B, ParamsDev P, int run) {
   const RunDev &rd = B.runs[run];
   const int R = P.n_rows;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rd.n_trk; i += gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int gl = lane & (kGrp - 1), g0 = lane & ~(kGrp - 1);
+  const int ng = (gridDim.x * blockDim.x) / kGrp;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / kGrp; i < rd.n_trk; i += ng) {
     const int t = B.kf_order[rd.trk0 + i];
     const int tl = t - rd.trk0;
     if (B.accv[tl] == 0) continue;
@@ -1508,40 +1511,33 @@ __global__ __launch_bounds__(kBlock) void k_output(Bufs B, ParamsDev P, int run)
     const unsigned long long m2 = nh > 128 ? wmp[2] : 0ull;
     const unsigned long long m3 = nh > 192 ? wmp[3] : 0ull;
     int w = 0;
-    for (int j0 = 0; j0 < nh; j0 += 8) {
-      int gh[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int j = j0 + q;
-        // slot of the j-th hit in row order
-        const int slot = j < ne ? n1 + ne - 1 - j : j - ne;
-        const unsigned long long m = slot < 64 ? m0 : slot < 128 ? m1 : slot < 192 ? m2 : m3;
-        const bool won = j < nh && ((m >> (slot & 63)) & 1ull);
-        gh[q] = won ? slot_hit(hl[slot], ucl) : -1;
+    for (int j0 = 0; j0 < nh; j0 += kGrp) {
+      const int j = j0 + gl;
+      // slot of the j-th hit in row order
+      const int slot = j < ne ? n1 + ne - 1 - j : j - ne;
+      const unsigned long long m = slot < 64 ? m0 : slot < 128 ? m1 : slot < 192 ? m2 : m3;
+      const bool won = j < nh && ((m >> (slot & 63)) & 1ull);
+      const unsigned int bits = (unsigned int)(__ballot(won) >> g0) & ((1u << kGrp) - 1);
+      if (won) {
+        const int id = B.sid[slot_hit(hl[slot], ucl)];
+        B.hits_out[h0 + w + __popc(bits & ((1u << gl) - 1))] = id;
+        B.assign[ucl + id] = local_track;
       }
-      int id[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) id[q] = gh[q] >= 0 ? B.sid[gh[q]] : -1;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (id[q] >= 0) {
-          B.hits_out[h0 + w] = id[q];
-          B.assign[ucl + id[q]] = local_track;
-          ++w;
-        }
-      }
+      w += __popc(bits);
     }
-    tpcca_track_t tr;
-    tr.x_ref = o.x_ref;
-    for (int q = 0; q < 5; ++q) tr.p[q] = o.p[q];
-    for (int q = 0; q < 15; ++q) tr.cov[q] = o.cov[q];
-    tr.chi2 = o.chi2;
-    tr.ndf = o.ndf;
-    tr.n_hits = w;
-    tr.hit_offset = (int32_t)(h0 - hb);
-    tr.sector = B.units[u].sector;
-    tr.start_id = o.start_id;
-    B.tracks[k] = tr;
+    if (gl == 0) {
+      tpcca_track_t tr;
+      tr.x_ref = o.x_ref;
+      for (int q = 0; q < 5; ++q) tr.p[q] = o.p[q];
+      for (int q = 0; q < 15; ++q) tr.cov[q] = o.cov[q];
+      tr.chi2 = o.chi2;
+      tr.ndf = o.ndf;
+      tr.n_hits = w;
+      tr.hit_offset = (int32_t)(h0 - hb);
+      tr.sector = B.units[u].sector;
+      tr.start_id = o.start_id;
+      B.tracks[k] = tr;
+    }
   }
 }
 
@@ -1705,17 +1701,18 @@ hipError_t launch_select(const Bufs &B, const ParamsDev &P, int run, const RunHo
   hipError_t e = launch_fill_i32(B.assign + h.cl0, n, -1, s);
   if (e != hipSuccess) return e;
   const int nu = h.u1 - h.u0;
-  const int tg = grid_for((int64_t)h.trk_cap, kBlock, 8192);  // thread per tracklet
+  const int tg = grid_for((int64_t)h.trk_cap, kBlock, 8192);  // thread per tracklet (claims)
+  const int gg = grid_for((int64_t)h.trk_cap * kGrp, kBlock, 8192);  // lane group per tracklet
   const int64_t tiles = (h.trk_cap + kScanTile - 1) / kScanTile;
   if (h.trk_cap > 0) {
     if (!P.kf_claims) k_claim<<<tg, kBlock, 0, s>>>(B, P, run);
-    k_won<<<tg, kBlock, 0, s>>>(B, P, run);
+    k_won<<<gg, kBlock, 0, s>>>(B, P, run);
     k_acc_sums<<<grid_for(tiles, 1, 8192), kBlock, 0, s>>>(B, run);
   }
   k_acc_tiles<<<1, 1024, 0, s>>>(B, run);
   if (h.trk_cap > 0) k_acc_apply<<<grid_for(tiles, 1, 8192), kBlock, 0, s>>>(B, run);
   if (nu > 0) k_unit_results<<<grid_for(nu, 64, 1024), 64, 0, s>>>(B, run);
-  if (h.trk_cap > 0) k_output<<<tg, kBlock, 0, s>>>(B, P, run);
+  if (h.trk_cap > 0) k_output<<<gg, kBlock, 0, s>>>(B, P, run);
   return hipGetLastError();
 }
 
