@@ -60,13 +60,14 @@ def parse():
     ap.add_argument("--retune", action="store_true", help="re-run the schedule autotuner")
     ap.add_argument("--summarize-profile", nargs=4, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "COMMAND"),
                     help="write the profiles/ summaries from rocprofv3 outputs of --profile runs")
+    ap.add_argument("--sq-dir", default=None, help="with --summarize-profile: an SQ counter pass to add")
     return ap.parse_args()
 
 
 def main():
     args = parse()
     if args.summarize_profile:
-        summarize_profile(*args.summarize_profile)
+        summarize_profile(*args.summarize_profile, sq_dir=args.sq_dir)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this tracker runs on one GPU; multi-GPU runs are not part of this build "
@@ -259,7 +260,7 @@ def measured_traffic():
     return {k: v["bytes"] for k, v in t["kernels"].items()}
 
 
-def summarize_profile(trace_dir, fetch_dir, write_dir, command):
+def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
     """Turn the rocprofv3 outputs of `bench.py --profile` (a kernel trace and
     FETCH_SIZE / WRITE_SIZE passes) into the committed summaries: per-kernel
     durations of the time-frame dispatches and counter bytes scaled by the
@@ -323,10 +324,11 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command):
     for k, e in out["kernels"].items():
         e["bytes"] = e.get("fetch_size", 0.0) + e.get("write_size", 0.0)
     out["factor"] = fac
-    # the fit kernel is reported under one name whatever its register variant
+    # a templated kernel is also reported under its plain name (the variant
+    # the profiled schedule ran)
     for k in list(out["kernels"]):
-        if k.startswith("k_kf<"):
-            out["kernels"]["k_kf"] = out["kernels"][k]
+        if "<" in k:
+            out["kernels"].setdefault(k.split("<")[0], out["kernels"][k])
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
     md = ["# Kernel trace and HBM traffic: batched time frame (128 events, 32.5 M clusters)", "",
@@ -340,11 +342,34 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command):
           f"WRITE {fac['WRITE_SIZE']:.4f}.", "",
           "| kernel | fetch MB | write MB | total MB |", "|---|---|---|---|"]
     for k in sorted(out["kernels"], key=lambda k: -out["kernels"][k]["bytes"]):
-        if k == "k_kf" and any(q.startswith("k_kf<") for q in out["kernels"]):
-            continue  # alias of the fit kernel's register variant
+        if "<" not in k and any(q.startswith(k + "<") for q in out["kernels"]):
+            continue  # alias of a templated kernel's variant
         e = out["kernels"][k]
         md.append(f"| {k} | {e.get('fetch_size', 0) / 1e6:.1f} | {e.get('write_size', 0) / 1e6:.1f} | "
                   f"{e['bytes'] / 1e6:.1f} |")
+    if sq_dir:
+        # instruction counters per wave of the TF dispatches (summed over the chip)
+        per_k = {}
+        for r in csv.DictReader(open(one(sq_dir, "*counter_collection.csv"))):
+            if "tpcca" not in r["Kernel_Name"]:
+                continue
+            d = per_k.setdefault(short(r["Kernel_Name"]), {})
+            d.setdefault(int(r["Dispatch_Id"]), {}).setdefault(r["Counter_Name"], 0.0)
+            d[int(r["Dispatch_Id"])][r["Counter_Name"]] += float(r["Counter_Value"])
+        md += ["", "## Instruction counters per wave (SQ pass, TF dispatches)", "",
+               "| kernel | waves | VALU | SALU | LDS | VMEM rd | VMEM wr | waiting % of wave cycles |",
+               "|---|---|---|---|---|---|---|---|"]
+        rows_sq = []
+        for k, d in per_k.items():
+            ds = [d[x] for x in sorted(d)[:tf_n]]
+            avg = {c: float(np.mean([x.get(c, 0.0) for x in ds])) for c in ds[0]}
+            w = max(1.0, avg.get("SQ_WAVES", 1.0))
+            rows_sq.append((tf_tot.get(k, 0.0), k, w, avg))
+        for _, k, w, a in sorted(rows_sq, reverse=True):
+            md.append(f"| {k} | {w:.0f} | {a.get('SQ_INSTS_VALU', 0) / w:.0f} | {a.get('SQ_INSTS_SALU', 0) / w:.0f} | "
+                      f"{a.get('SQ_INSTS_LDS', 0) / w:.0f} | {a.get('SQ_INSTS_VMEM_RD', 0) / w:.0f} | "
+                      f"{a.get('SQ_INSTS_VMEM_WR', 0) / w:.0f} | "
+                      f"{100 * a.get('SQ_WAIT_ANY', 0) / max(1.0, a.get('SQ_WAVE_CYCLES', 1)):.0f} |")
     md += ["", f"Kernel sources hash: `{out['source_hash']}` (bench.py reports traffic only while it matches)."]
     path = os.path.join(ROOT, "profiles", "tracker_timeframe128_kernel_trace.md")
     with open(path, "w") as f:
