@@ -413,18 +413,61 @@ __device__ __forceinline__ float2 cand(const Bufs &B, const float2 *src, int i, 
   return kLds ? src[i - off] : B.yz[i];
 }
 
-template <bool kLds, int kKeep>
-__device__ __forceinline__ void link_hit(const Bufs &B, const ParamsDev &P, float2 h, float luy,
-                                         float luz, float ldy, float ldz, float w, int ub, int ue,
-                                         int db, int de, const float2 *cu_src, const float2 *cd_src,
-                                         int u_off, int d_off, int *keep_u, int *keep_d, int &bu,
-                                         int &bd) {
-  float best = __builtin_inff();
-  bu = -1;
-  bd = -1;
-  int nu = 0, nd = 0;
+// Best pair so far (chi2, sorted indices of the up and down hits).
+struct LinkBest {
+  float c2;
+  int u, d;
+};
+
+// One (u, d) pair against the best so far: smaller chi2, ties by cluster IDs.
+__device__ __forceinline__ void link_pair(const Bufs &B, float2 h, float w, float2 cu, float2 cd, int u, int d,
+                                          LinkBest &b) {
+  const float ey = h.x - __builtin_fmaf(cu.x - cd.x, w, cd.x);
+  const float ez = h.y - __builtin_fmaf(cu.y - cd.y, w, cd.y);
+  const float c2 = __builtin_fmaf(ey, ey, ez * ez);
+  bool take = c2 < b.c2;
+  if (!take && c2 == b.c2 && b.u >= 0) {
+    const int iu = B.sid[u], id = B.sid[d], ibu = B.sid[b.u], ibd = B.sid[b.d];
+    take = iu < ibu || (iu == ibu && id < ibd);
+  }
+  if (take) {
+    b.c2 = c2;
+    b.u = u;
+    b.d = d;
+  }
+}
+
+// Every pair of the two windows: used when a side holds more window hits
+// than the lists, or when the tile's neighbours are not staged.  Rare, and
+// kept out of line so that the common path compiles to short loops.
+template <bool kLds>
+__device__ __noinline__ LinkBest link_all_pairs(const Bufs &B, float2 h, float luy, float luz, float ldy,
+                                                float ldz, float w, int ub, int ue, int db, int de,
+                                                const float2 *cu_src, const float2 *cd_src, int u_off,
+                                                int d_off) {
+  LinkBest b{__builtin_inff(), -1, -1};
   for (int u = ub; u < ue; ++u) {
     const float2 cu = cand<kLds>(B, cu_src, u, u_off);
+    if (!(fabsf(cu.x - h.x) <= luy && fabsf(cu.y - h.y) <= luz)) continue;
+    for (int d = db; d < de; ++d) {
+      const float2 cd = cand<kLds>(B, cd_src, d, d_off);
+      if (!(fabsf(cd.x - h.x) <= ldy && fabsf(cd.y - h.y) <= ldz)) continue;
+      link_pair(B, h, w, cu, cd, u, d, b);
+    }
+  }
+  return b;
+}
+
+// The common path, neighbours staged in LDS: the window hits of each side
+// are listed (up to kKeep), then the short lists are paired.
+template <int kKeep>
+__device__ __forceinline__ LinkBest link_hit_lds(const Bufs &B, float2 h, float luy, float luz, float ldy,
+                                                 float ldz, float w, int ub, int ue, int db, int de,
+                                                 const float2 *s_up, const float2 *s_dn, int u_off, int d_off,
+                                                 int *keep_u, int *keep_d) {
+  int nu = 0, nd = 0;
+  for (int u = ub; u < ue; ++u) {
+    const float2 cu = s_up[u - u_off];
     if (fabsf(cu.x - h.x) <= luy && fabsf(cu.y - h.y) <= luz) {
       if (nu < kKeep) keep_u[nu * kTile] = u;
       ++nu;
@@ -432,42 +475,25 @@ __device__ __forceinline__ void link_hit(const Bufs &B, const ParamsDev &P, floa
   }
   if (nu > 0) {
     for (int d = db; d < de; ++d) {
-      const float2 cd = cand<kLds>(B, cd_src, d, d_off);
+      const float2 cd = s_dn[d - d_off];
       if (fabsf(cd.x - h.x) <= ldy && fabsf(cd.y - h.y) <= ldz) {
         if (nd < kKeep) keep_d[nd * kTile] = d;
         ++nd;
       }
     }
   }
-  const bool full = nu > kKeep || nd > kKeep;
-  const int mu = full ? ue - ub : nu, md = full ? de - db : nd;
-  for (int a = 0; a < mu && nd > 0; ++a) {
-    const int u = full ? ub + a : keep_u[a * kTile];
-    const float2 cu = cand<kLds>(B, cu_src, u, u_off);
-    if (full && !(fabsf(cu.x - h.x) <= luy && fabsf(cu.y - h.y) <= luz)) continue;
-    for (int b = 0; b < md; ++b) {
-      const int d = full ? db + b : keep_d[b * kTile];
-      const float2 cd = cand<kLds>(B, cd_src, d, d_off);
-      if (full && !(fabsf(cd.x - h.x) <= ldy && fabsf(cd.y - h.y) <= ldz)) continue;
-      const float ey = h.x - __builtin_fmaf(cu.x - cd.x, w, cd.x);
-      const float ez = h.y - __builtin_fmaf(cu.y - cd.y, w, cd.y);
-      const float c2 = __builtin_fmaf(ey, ey, ez * ez);
-      bool take = c2 < best;
-      if (!take && c2 == best && bu >= 0) {
-        const int iu = B.sid[u], id = B.sid[d], ibu = B.sid[bu], ibd = B.sid[bd];
-        take = iu < ibu || (iu == ibu && id < ibd);
-      }
-      if (take) {
-        best = c2;
-        bu = u;
-        bd = d;
-      }
+  if (nu > kKeep || nd > kKeep)
+    return link_all_pairs<true>(B, h, luy, luz, ldy, ldz, w, ub, ue, db, de, s_up, s_dn, u_off, d_off);
+  LinkBest b{__builtin_inff(), -1, -1};
+  for (int a = 0; a < nu && nd > 0; ++a) {
+    const int u = keep_u[a * kTile];
+    const float2 cu = s_up[u - u_off];
+    for (int q = 0; q < nd; ++q) {
+      const int d = keep_d[q * kTile];
+      link_pair(B, h, w, cu, s_dn[d - d_off], u, d, b);
     }
   }
-  if (!(best <= P.link_chi2)) {
-    bu = -1;
-    bd = -1;
-  }
+  return b;
 }
 
 template <int kV>
@@ -545,20 +571,20 @@ __global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
       const float pad = 1e-3f + 1e-6f * fabsf(h.y);
       const int bu0 = zbin(tu, h.y - luz - pad), bu1 = zbin(tu, h.y + luz + pad);
       const int bd0 = zbin(td, h.y - ldz - pad), bd1 = zbin(td, h.y + ldz + pad);
-      int bu, bd;
+      LinkBest b;
       if (lds) {
         const int ub = s_bup[bu0 - ublo], ue = s_bup[bu1 + 1 - ublo];
         const int db = s_bdn[bd0 - dblo], de = s_bdn[bd1 + 1 - dblo];
-        link_hit<true, kKeep>(B, P, h, luy, luz, ldy, ldz, w, ub, ue, db, de, s_up, s_dn, ua, da,
-                       s_keep + i, s_keep + kKeep * kTile + i, bu, bd);
+        b = link_hit_lds<kKeep>(B, h, luy, luz, ldy, ldz, w, ub, ue, db, de, s_up, s_dn, ua, da, s_keep + i,
+                                s_keep + kKeep * kTile + i);
       } else {
         const int ub = B.binbeg[tu.bin0 + bu0], ue = B.binbeg[tu.bin0 + bu1 + 1];
         const int db = B.binbeg[td.bin0 + bd0], de = B.binbeg[td.bin0 + bd1 + 1];
-        link_hit<false, kKeep>(B, P, h, luy, luz, ldy, ldz, w, ub, ue, db, de, nullptr, nullptr, 0, 0,
-                        s_keep + i, s_keep + kKeep * kTile + i, bu, bd);
+        b = link_all_pairs<false>(B, h, luy, luz, ldy, ldz, w, ub, ue, db, de, nullptr, nullptr, 0, 0);
       }
-      B.up[g] = bu;
-      B.dn[g] = bd;
+      const bool ok = b.u >= 0 && b.c2 <= P.link_chi2;
+      B.up[g] = ok ? b.u : -1;
+      B.dn[g] = ok ? b.d : -1;
     }
     __syncthreads();
   }
