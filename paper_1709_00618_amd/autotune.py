@@ -21,8 +21,9 @@ CACHE = os.path.join(HERE, "tuning_cache.json")
 SPACE = {
     "fit_pool": [64, 128],
     "fit_min_waves": [0, 4],
-    "fit_claims": [0, 1],
-    "fit_long_first": [0, 20, 40, 80],
+    "fit_long_first": [0, 80],
+    "link_stage": [0, 1, 2],
+    "link_blocks_per_cu": [16, 32],
 }
 
 
@@ -111,5 +112,5 @@ def tuned(ctx, cl, row, units, n_clusters, device=True, log=None, retune=False):
 
 
 def _default(table):
-    d = {"fit_pool": 64, "fit_min_waves": 0, "fit_claims": 1, "fit_long_first": 0}
+    d = {"fit_pool": 64, "fit_min_waves": 0, "fit_long_first": 0, "link_stage": 0, "link_blocks_per_cu": 32}
     return d if any(k == d for _, k in table) else None

@@ -458,6 +458,37 @@ __device__ __noinline__ LinkBest link_all_pairs(const Bufs &B, float2 h, float l
   return b;
 }
 
+// Lists (up to kKeep) the staged hits in [b, e) inside the window around h,
+// two candidates per step (independent LDS reads in flight); returns how
+// many there are.
+template <int kKeep>
+__device__ __forceinline__ int collect_window(const float2 *src, int off, int b, int e, float2 h, float ly,
+                                              float lz, int *keep) {
+  int n = 0;
+  int i = b;
+  for (; i + 1 < e; i += 2) {
+    const float2 c0 = src[i - off], c1 = src[i + 1 - off];
+    const bool w0 = fabsf(c0.x - h.x) <= ly && fabsf(c0.y - h.y) <= lz;
+    const bool w1 = fabsf(c1.x - h.x) <= ly && fabsf(c1.y - h.y) <= lz;
+    if (w0) {
+      if (n < kKeep) keep[n * kTile] = i;
+      ++n;
+    }
+    if (w1) {
+      if (n < kKeep) keep[n * kTile] = i + 1;
+      ++n;
+    }
+  }
+  if (i < e) {
+    const float2 c0 = src[i - off];
+    if (fabsf(c0.x - h.x) <= ly && fabsf(c0.y - h.y) <= lz) {
+      if (n < kKeep) keep[n * kTile] = i;
+      ++n;
+    }
+  }
+  return n;
+}
+
 // The common path, neighbours staged in LDS: the window hits of each side
 // are listed (up to kKeep), then the short lists are paired.
 template <int kKeep>
@@ -465,23 +496,8 @@ __device__ __forceinline__ LinkBest link_hit_lds(const Bufs &B, float2 h, float 
                                                  float ldz, float w, int ub, int ue, int db, int de,
                                                  const float2 *s_up, const float2 *s_dn, int u_off, int d_off,
                                                  int *keep_u, int *keep_d) {
-  int nu = 0, nd = 0;
-  for (int u = ub; u < ue; ++u) {
-    const float2 cu = s_up[u - u_off];
-    if (fabsf(cu.x - h.x) <= luy && fabsf(cu.y - h.y) <= luz) {
-      if (nu < kKeep) keep_u[nu * kTile] = u;
-      ++nu;
-    }
-  }
-  if (nu > 0) {
-    for (int d = db; d < de; ++d) {
-      const float2 cd = s_dn[d - d_off];
-      if (fabsf(cd.x - h.x) <= ldy && fabsf(cd.y - h.y) <= ldz) {
-        if (nd < kKeep) keep_d[nd * kTile] = d;
-        ++nd;
-      }
-    }
-  }
+  const int nu = collect_window<kKeep>(s_up, u_off, ub, ue, h, luy, luz, keep_u);
+  const int nd = nu > 0 ? collect_window<kKeep>(s_dn, d_off, db, de, h, ldy, ldz, keep_d) : 0;
   if (nu > kKeep || nd > kKeep)
     return link_all_pairs<true>(B, h, luy, luz, ldy, ldz, w, ub, ue, db, de, s_up, s_dn, u_off, d_off);
   LinkBest b{__builtin_inff(), -1, -1};
