@@ -138,10 +138,30 @@ __global__ void k_run_reset(Bufs B, int run, int R) {
 
 // ---------------------------------------------------------------- grid ---
 // Pass 1: clusters per (unit, row) and the z range of each unit.
+// The kChunk / kBlock clusters of a thread in a chunk, loaded before any of
+// them is used (independent loads in flight); the row positions come from LDS.
+constexpr int kPer = kChunk / kBlock;
+
+__device__ __forceinline__ void load_chunk(const UnitDev &U, const Chunk &ch, const float *s_rx, int R,
+                                           float4 (&c4)[kPer], int (&r)[kPer]) {
+  int raw[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = threadIdx.x + q * kBlock;
+    const int li = ch.begin + (i < ch.count ? i : 0);
+    c4[q] = U.cl[li];
+    raw[q] = U.row[li];
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) r[q] = valid_row(c4[q], raw[q], s_rx, R);
+}
+
 __global__ __launch_bounds__(kBlock) void k_count(Bufs B, int run, int R) {
   __shared__ int hist[kMaxRows + 1];
   __shared__ int smin[kBlock / 64], smax[kBlock / 64], serr;
+  __shared__ float s_rx[kMaxRows + 1];
   const RunDev &rd = B.runs[run];
+  for (int r = threadIdx.x; r < R; r += blockDim.x) s_rx[r] = B.row_x[r];
   for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
     const Chunk ch = B.chunks[c];
     const UnitDev U = B.units[ch.unit];
@@ -149,10 +169,14 @@ __global__ __launch_bounds__(kBlock) void k_count(Bufs B, int run, int R) {
     if (threadIdx.x == 0) serr = 0;
     __syncthreads();
     int zmin = 0x7FFFFFFF, zmax = (int)0x80000000, bad = 0;
-    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
-      const int li = ch.begin + i;
-      const float4 c4 = U.cl[li];
-      const int r = valid_row(c4, U.row[li], B.row_x, R);
+    float4 cq[kPer];
+    int rq[kPer];
+    load_chunk(U, ch, s_rx, R, cq, rq);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      if (threadIdx.x + q * kBlock >= ch.count) break;
+      const float4 c4 = cq[q];
+      const int r = rq[q];
       atomicAdd(&hist[r], 1);
       if (r < R) {
         const int oz = ordered_int(c4.z);
@@ -253,7 +277,9 @@ __global__ __launch_bounds__(kBlock) void k_rowscatter(Bufs B, int run, int R) {
   __shared__ int hist[kGroup * (kMaxRows + 1)];
   __shared__ int cursor[kGroup * (kMaxRows + 1)];
   __shared__ int slot_unit[kGroup];
+  __shared__ float s_rx[kMaxRows + 1];
   const RunDev &rd = B.runs[run];
+  for (int r = threadIdx.x; r < R; r += blockDim.x) s_rx[r] = B.row_x[r];
   const int nslots = kGroup * (R + 1);
   const int ngroups = (rd.c1 - rd.c0 + kGroup - 1) / kGroup;
   for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
@@ -301,12 +327,15 @@ __global__ __launch_bounds__(kBlock) void k_rowscatter(Bufs B, int run, int R) {
       const Chunk ch = B.chunks[c];
       const UnitDev U = B.units[ch.unit];
       const int so = slot_unit[c - c0] * (R + 1);
-      for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
-        const int li = ch.begin + i;
-        const float4 c4 = U.cl[li];
-        const int r = valid_row(c4, U.row[li], B.row_x, R);
-        const int pos = atomicAdd(&cursor[so + r], 1);
-        B.rtmp[pos] = make_int4(__float_as_int(c4.y), __float_as_int(c4.z), li, r);
+      float4 cq[kPer];
+      int rq[kPer];
+      load_chunk(U, ch, s_rx, R, cq, rq);
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int i = threadIdx.x + q * kBlock;
+        if (i >= ch.count) break;
+        const int pos = atomicAdd(&cursor[so + rq[q]], 1);
+        B.rtmp[pos] = make_int4(__float_as_int(cq[q].y), __float_as_int(cq[q].z), ch.begin + i, rq[q]);
       }
     }
     __syncthreads();
