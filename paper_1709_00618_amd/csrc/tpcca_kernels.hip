@@ -650,11 +650,27 @@ __global__ __launch_bounds__(kBlock) void k_clean(Bufs B, int run) {
     const int cb = U.cl_begin + ch.begin;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < ch.count; i += blockDim.x) {
+    // a thread's hits: links first, then the partners' links, all in flight together
+    int lu[kPer], ld[kPer], pu[kPer], pd[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = threadIdx.x + q * kBlock;
+      const int g = cb + (i < ch.count ? i : 0);
+      lu[q] = i < ch.count ? B.up[g] : -1;
+      ld[q] = i < ch.count ? B.dn[g] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      pu[q] = lu[q] >= 0 ? B.dn[lu[q]] : -1;
+      pd[q] = ld[q] >= 0 ? B.up[ld[q]] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = threadIdx.x + q * kBlock;
+      if (i >= ch.count) break;
       const int g = cb + i;
-      const int u = B.up[g], d = B.dn[g];
-      const int uc = (u >= 0 && B.dn[u] == g) ? u : -1;
-      const int dc = (d >= 0 && B.up[d] == g) ? d : -1;
+      const int uc = (lu[q] >= 0 && pu[q] == g) ? lu[q] : -1;
+      const int dc = (ld[q] >= 0 && pd[q] == g) ? ld[q] : -1;
       B.upc[g] = uc;
       B.dnc[g] = dc;
       if (uc >= 0 && dc < 0) stage[cb + atomicAdd(&cnt, 1)] = make_int2(g, U.cl_begin + B.sid[g]);
