@@ -219,11 +219,14 @@ int tpcca_batch_totals(tpcca_ctx_t *ctx, int32_t *n_units, int64_t *n_clusters, 
    clusters, tracklets (fitted candidates), accepted tracks and their hits,
    Kalman row steps (propagations), candidate clusters examined by the
    track-following searches, chi2 tests of the hits those searches picked,
-   Kalman updates, and the fit kernel's loop iterations summed over its
-   64-lane waves (fit_steps / (64 x fit_wave_iterations) is its lane use). */
+   Kalman updates, the fit kernel's loop iterations summed over its 64-lane
+   waves (fit_steps / (64 x fit_wave_iterations) is its lane use), and, from
+   the GPU's constant clock, the fit kernel's span and the part of it after
+   the first wave found no more tracklets to start (the drain), in ns, summed
+   over runs. */
 typedef struct {
   int64_t clusters, tracklets, tracks, track_hits, fit_steps, fit_candidates, fit_tests, fit_updates,
-      fit_wave_iterations;
+      fit_wave_iterations, fit_ns, fit_drain_ns;
 } tpcca_work_stats_t;
 int tpcca_work_stats(tpcca_ctx_t *ctx, tpcca_work_stats_t *out);
 
@@ -249,6 +252,8 @@ typedef struct {
                                 1 medium, 2 small (more blocks per CU, more global fallbacks) */
   int32_t fit_long_first;    /* tracklets whose chain has at least this many hits are fitted
                                 first (shorter fits drain the end of the kernel); 0: off */
+  int32_t fit_row_bands;     /* fit order by (start-row band, unit) with this many bands of
+                                rows (1..n_rows; overrides fit_long_first); 0: by unit */
 } tpcca_tuning_t;
 int tpcca_set_tuning(tpcca_ctx_t *ctx, const tpcca_tuning_t *t);
 int tpcca_get_tuning(tpcca_ctx_t *ctx, tpcca_tuning_t *t);

@@ -19,11 +19,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning_cache.json")
 
 SPACE = {
-    "fit_pool": [64, 128],
+    "fit_pool": [32, 64, 128],
     "fit_min_waves": [0, 4],
-    "fit_long_first": [0, 80],
-    "link_stage": [0, 1, 2],
-    "link_blocks_per_cu": [16, 32],
+    "fit_row_bands": [0, 8, 40, 159],
 }
 
 
@@ -112,5 +110,5 @@ def tuned(ctx, cl, row, units, n_clusters, device=True, log=None, retune=False):
 
 
 def _default(table):
-    d = {"fit_pool": 64, "fit_min_waves": 0, "fit_long_first": 0, "link_stage": 0, "link_blocks_per_cu": 32}
+    d = {"fit_pool": 64, "fit_min_waves": 0, "fit_row_bands": 0}
     return d if any(k == d for _, k in table) else None

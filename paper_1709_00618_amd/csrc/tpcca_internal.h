@@ -65,7 +65,7 @@ struct RunDev {
   int32_t n_trk;
   int32_t n_acc;
   int64_t n_acc_hits;
-  int32_t err;          // 1: invalid cluster seen
+  int32_t err;          // 1: invalid cluster seen; 2: inconsistent fit order (internal)
   int32_t kf_next[8];   // work counters of the fit kernel, one per slice of the order
   int32_t n_starts;     // chain start hits found by the cleaning kernel
   unsigned long long kf_steps;   // row steps of the fit (propagations)
@@ -73,6 +73,9 @@ struct RunDev {
   unsigned long long kf_tests;   // chi2 tests of searched hits
   unsigned long long kf_updates; // Kalman updates
   unsigned long long kf_iters;   // state-machine iterations summed over the fit's waves
+  // fit timeline on the 100 MHz constant clock: first wave start, first wave
+  // to find the work counter exhausted, last wave end
+  unsigned long long kf_t_start, kf_t_drain, kf_t_end;
 };
 
 // Device-side parameters (FP32 copies of tpcca_params_t).
@@ -93,6 +96,7 @@ struct ParamsDev {
   int32_t kf_xcd;      // 1: the fit's order is cut into one slice per XCD
   int32_t link_stage;  // staging capacity variant of the neighbour kernel (0..2)
   int32_t kf_split;    // chains of at least this many hits are fitted first (0: off)
+  int32_t kf_bands;    // fit order by (start-row band, unit) with this many bands (0: unit-major)
 };
 
 // Device buffers of a context (all indices global).
@@ -120,6 +124,8 @@ struct Bufs {
   uint8_t *sval;         // sorted: 1 if the hit starts a tracklet
   int32_t *tofg;         // sorted start hit -> tracklet
   int32_t *kf_order;     // processing rank -> tracklet (grid order of start hits)
+  int32_t *kf_tmp;       // the unit-major order while start-row bands reorder it
+  int32_t *band_tmp;     // 3 x units x (n_rows + 1): band counts, band-major and unit-major offsets
   int32_t *trk_start;    // tracklet -> sorted index of its start hit
   int32_t *trk_unit;     // tracklet -> unit
   int32_t *unit_tbegin;  // unit -> first tracklet

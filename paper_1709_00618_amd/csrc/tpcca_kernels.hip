@@ -133,6 +133,8 @@ __global__ void k_run_reset(Bufs B, int run, int R) {
     rd.kf_tests = 0;
     rd.kf_updates = 0;
     rd.kf_iters = 0;
+    rd.kf_t_start = rd.kf_t_drain = ~0ull;
+    rd.kf_t_end = 0;
   }
 }
 
@@ -716,7 +718,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(Bufs B, ParamsDev P, int run) 
       B.flag[st.y] = g + 1;
       B.cinfo[g] = make_int2(last, n);
       // 2: a long chain, fitted in the first part of the processing order
-      B.sval[g] = (P.kf_split > 0 && n >= P.kf_split) ? 2 : 1;
+      B.sval[g] = (P.kf_split > 0 && P.kf_bands == 0 && n >= P.kf_split) ? 2 : 1;
     }
   }
 }
@@ -829,7 +831,7 @@ __global__ __launch_bounds__(kBlock) void k_order_sums(Bufs B, int run) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_order_apply(Bufs B, int run) {
+__global__ __launch_bounds__(kBlock) void k_order_apply(Bufs B, int run, int32_t *dst) {
   __shared__ int64_t lds[kBlock / 64 + 1];
   const RunDev &rd = B.runs[run];
   const int nch = rd.c1 - rd.c0;
@@ -850,12 +852,71 @@ __global__ __launch_bounds__(kBlock) void k_order_apply(Bufs B, int run) {
                    B.scan_tmp[(cls == 2 ? 0 : nch) + c - rd.c0];
       for (int k = 0; k < per; ++k) {
         if (f[k] == cls) {
-          B.kf_order[rd.trk0 + (int32_t)ex] = B.tofg[base + threadIdx.x * per + k];
+          dst[rd.trk0 + (int32_t)ex] = B.tofg[base + threadIdx.x * per + k];
           ++ex;
         }
       }
       __syncthreads();  // lds is reused by the next class's scan
     }
+  }
+}
+
+// Optional start-row bands of the fit's processing order: (band of the start
+// row, unit, grid order) instead of (unit, grid order).  Tracklets that
+// start at outer rows cannot run long, so when they come last the fit's
+// drain is short; and the tracklets in flight together sweep neighbouring
+// rows of all units.  In the unit-major order each (unit, band) bucket is
+// contiguous, so a tracklet's new position is its bucket's band-major offset
+// plus its rank inside the bucket.
+__device__ __forceinline__ int start_band(const Bufs &B, int t, int nb, int R) {
+  return (int)B.srow[B.trk_start[t]] * nb / R;
+}
+
+__global__ void k_band_count(Bufs B, ParamsDev P, int run) {
+  const RunDev &rd = B.runs[run];
+  const int nu = rd.u1 - rd.u0, nb = P.kf_bands;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rd.n_trk; i += gridDim.x * blockDim.x) {
+    const int t = B.kf_tmp[rd.trk0 + i];
+    atomicAdd(&B.band_tmp[start_band(B, t, nb, P.n_rows) * nu + (B.trk_unit[t] - rd.u0)], 1);
+  }
+}
+
+// One block: band-major and unit-major exclusive scans of the bucket counts.
+__global__ __launch_bounds__(1024) void k_band_scan(Bufs B, ParamsDev P, int run) {
+  __shared__ int32_t lds[1024 / 64 + 1];
+  const RunDev &rd = B.runs[run];
+  const int nu = rd.u1 - rd.u0, nb = P.kf_bands, n = nu * nb;
+  const int32_t *cnt = B.band_tmp;
+  int32_t *off_bm = B.band_tmp + n, *off_um = B.band_tmp + 2 * n;
+  for (int order = 0; order < 2; ++order) {
+    int32_t carry = 0;
+    for (int s0 = 0; s0 < n; s0 += 1024) {
+      const int k = s0 + threadIdx.x;  // position in the scan order
+      int j = k;                        // bucket index (band * nu + unit)
+      if (order == 1 && k < n) j = (k % nb) * nu + k / nb;
+      const int32_t v = k < n ? cnt[j] : 0;
+      int32_t tot;
+      const int32_t ex = block_exclusive_scan<int32_t>(v, lds, &tot);
+      if (k < n) (order == 0 ? off_bm : off_um)[j] = carry + ex;
+      carry += tot;
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_band_apply(Bufs B, ParamsDev P, int run) {
+  RunDev &rd = B.runs[run];
+  const int nu = rd.u1 - rd.u0, nb = P.kf_bands, n = nu * nb;
+  const int n_trk = rd.n_trk;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_trk; i += gridDim.x * blockDim.x) {
+    const int t = B.kf_tmp[rd.trk0 + i];
+    const int j = start_band(B, t, nb, P.n_rows) * nu + (B.trk_unit[t] - rd.u0);
+    const int pos = B.band_tmp[n + j] + (i - B.band_tmp[2 * n + j]);
+    if (pos < 0 || pos >= n_trk) {  // never write outside the run's slots
+      atomicOr(&rd.err, 2);
+      continue;
+    }
+    B.kf_order[rd.trk0 + pos] = t;
   }
 }
 
@@ -1160,6 +1221,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
   float chi2 = 0.0f;
   unsigned int cands = 0;
   unsigned int steps = 0, tests = 0, updates = 0, iters = 0;  // wave totals (scalar)
+  const unsigned long long t_start = __builtin_amdgcn_s_memrealtime();
   int pnext = 0, pend = 0;  // wave-private pool of claimed tracklets
   // The processing order is cut into one slice per XCD.  Block b runs on
   // XCD b mod 8, whose waves drain that slice first (its L2 then holds the
@@ -1167,22 +1229,32 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
   // the following slices.
   const int nsl = P.kf_xcd ? kXcds : 1;
   int part = blockIdx.x % nsl, tried = 0;
+  int seen = 0;  // the work counter as of this wave's last claim
   for (;;) {
     const unsigned long long idle = __ballot(phase == kIdle);
     while (idle && pnext == pend && !exhausted) {
-      // claim the next kPool tracklets of the slice with one atomic per wave
+      // claim the next tracklets of the slice with one atomic per wave:
+      // kPool neighbouring ones while many remain; in the last stretch
+      // (less than a quarter pool per wave left, judged from this wave's
+      // previous claim) fewer, but never fewer than the idle lanes, so that
+      // at the end no wave holds a private backlog
       const int lo = (int)((int64_t)n_trk * part / nsl);
       const int hi = (int)((int64_t)n_trk * (part + 1) / nsl);
+      const int nw = (int)((gridDim.x * blockDim.x) >> 6);
+      const int want = max(__popcll(idle), min(kPool, 4 * (((hi - lo) - seen) / nw)));
       int base = 0;
-      if (lane == 0) base = atomicAdd(&rd.kf_next[part], kPool);
+      if (lane == 0) base = atomicAdd(&rd.kf_next[part], want);
       base = __shfl(base, 0, 64);
+      seen = base + want;
       if (base < hi - lo) {
         pnext = lo + base;
-        pend = min(pnext + kPool, hi);
+        pend = min(pnext + want, hi);
       } else if (++tried == nsl) {
         exhausted = true;
+        if (lane == 0) atomicMin(&rd.kf_t_drain, (unsigned long long)__builtin_amdgcn_s_memrealtime());
       } else {
         part = (part + 1) % nsl;
+        seen = 0;
       }
     }
     if (idle && pnext < pend) {
@@ -1394,6 +1466,8 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
     atomicAdd(&rd.kf_tests, (unsigned long long)tests);
     atomicAdd(&rd.kf_updates, (unsigned long long)updates);
     atomicAdd(&rd.kf_iters, (unsigned long long)iters);
+    atomicMin(&rd.kf_t_start, t_start);
+    atomicMax(&rd.kf_t_end, (unsigned long long)__builtin_amdgcn_s_memrealtime());
   }
 }
 
@@ -1725,7 +1799,16 @@ hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHo
     k_flag_apply<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
     k_order_sums<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
     k_scan_tiles<<<1, 1024, 0, s>>>(B.scan_tmp, 2 * (int64_t)nch);
-    k_order_apply<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
+    const bool bands = P.kf_bands > 0 && h.trk_cap > 0;
+    k_order_apply<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run, bands ? B.kf_tmp : B.kf_order);
+    if (bands) {
+      const int64_t nbk = (int64_t)nu * P.kf_bands;
+      e = launch_fill_i32(B.band_tmp, nbk, 0, s);
+      if (e != hipSuccess) return e;
+      k_band_count<<<grid_for(h.trk_cap, kBlock, 4096), kBlock, 0, s>>>(B, P, run);
+      k_band_scan<<<1, 1024, 0, s>>>(B, P, run);
+      k_band_apply<<<grid_for(h.trk_cap, kBlock, 4096), kBlock, 0, s>>>(B, P, run);
+    }
   }
   if (nu > 0) k_empty_units<<<grid_for(nu, 64, 1024), 64, 0, s>>>(B, run);
   return hipGetLastError();

@@ -61,7 +61,7 @@ struct tpcca_ctx {
 
   // device buffers
   DevBuf row_x_d, units_d, chunks_d, runs_d, rowtab, row_cnt, row_fill, chunk_hist, rtmp, zmm, binbeg, yz, sid, up,
-      dn, upc, dnc, flag, starts, tiles, sval, tofg, kf_order, srow, cinfo, trk_start, trk_unit, unit_tbegin, trk, trk_hits, owner, accv, wonmask, accx,
+      dn, upc, dnc, flag, starts, tiles, sval, tofg, kf_order, kf_tmp, band_tmp, srow, cinfo, trk_start, trk_unit, unit_tbegin, trk, trk_hits, owner, accv, wonmask, accx,
       tracks, hits_out, assign, unit_res, scan_tmp, in_cl, in_row;
   Bufs B{};
 
@@ -190,6 +190,8 @@ static void refresh_bufs(tpcca_ctx *c) {
   B.sval = ptr<uint8_t>(c->sval);
   B.tofg = ptr<int32_t>(c->tofg);
   B.kf_order = ptr<int32_t>(c->kf_order);
+  B.kf_tmp = ptr<int32_t>(c->kf_tmp);
+  B.band_tmp = ptr<int32_t>(c->band_tmp);
   B.trk_start = ptr<int32_t>(c->trk_start);
   B.trk_unit = ptr<int32_t>(c->trk_unit);
   B.unit_tbegin = ptr<int32_t>(c->unit_tbegin);
@@ -246,6 +248,8 @@ static int ensure_work(tpcca_ctx *c, int64_t n_cl, int64_t n_units, int64_t n_bi
   ENS(assign, N, sizeof(int32_t), keepN);
   ENS(trk_start, T, sizeof(int32_t), keepT);
   ENS(kf_order, T, sizeof(int32_t), keepT);
+  ENS(kf_tmp, T, sizeof(int32_t), 0);
+  ENS(band_tmp, 3 * U * (R + 1), sizeof(int32_t), 0);
   ENS(sval, N, sizeof(uint8_t), keepN);
   ENS(tofg, N, sizeof(int32_t), keepN);
   ENS(trk_unit, T, sizeof(int32_t), keepT);
@@ -422,7 +426,10 @@ static int check_errors(tpcca_ctx *c) {
   for (int run : c->pending_runs) {
     RunDev d;
     RCCHK(copy_sync(c, &d, ptr<RunDev>(c->runs_d) + run, sizeof(d), hipMemcpyDeviceToHost));
-    if (d.err) {
+    if (d.err & 2) {
+      c->last_error = "internal error: inconsistent fit order";
+      rc = TPCCA_EDEVICE;
+    } else if (d.err) {
       c->last_error = "invalid cluster (row out of range, non-finite value, or x off its row)";
       rc = TPCCA_EINVAL;
     }
@@ -597,6 +604,7 @@ int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int 
   P.kf_xcd = 0;
   P.link_stage = 0;
   P.kf_split = 0;
+  P.kf_bands = 0;
   std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
@@ -630,7 +638,7 @@ int tpcca_destroy(tpcca_ctx_t *c) {
   DevBuf *all[] = {&c->row_x_d, &c->units_d, &c->chunks_d, &c->runs_d, &c->rowtab, &c->row_cnt,
                    &c->row_fill, &c->chunk_hist, &c->rtmp,
                    &c->zmm, &c->binbeg, &c->yz, &c->sid, &c->up, &c->dn, &c->upc,
-                   &c->dnc, &c->flag, &c->starts, &c->tiles, &c->sval, &c->tofg, &c->kf_order, &c->srow, &c->cinfo, &c->trk_start, &c->trk_unit, &c->unit_tbegin, &c->trk,
+                   &c->dnc, &c->flag, &c->starts, &c->tiles, &c->sval, &c->tofg, &c->kf_order, &c->kf_tmp, &c->band_tmp, &c->srow, &c->cinfo, &c->trk_start, &c->trk_unit, &c->unit_tbegin, &c->trk,
                    &c->trk_hits, &c->owner, &c->accv, &c->wonmask, &c->accx, &c->tracks, &c->hits_out,
                    &c->assign, &c->unit_res, &c->scan_tmp, &c->in_cl, &c->in_row};
   for (DevBuf *b : all)
@@ -1016,6 +1024,11 @@ int tpcca_work_stats(tpcca_ctx_t *c, tpcca_work_stats_t *out) {
       out->fit_tests += (int64_t)d.kf_tests;
       out->fit_updates += (int64_t)d.kf_updates;
       out->fit_wave_iterations += (int64_t)d.kf_iters;
+      if (d.kf_t_end > d.kf_t_start && d.kf_t_start != ~0ull) {
+        out->fit_ns += (int64_t)(d.kf_t_end - d.kf_t_start) * 10;  // 100 MHz clock
+        if (d.kf_t_drain != ~0ull && d.kf_t_drain <= d.kf_t_end)
+          out->fit_drain_ns += (int64_t)(d.kf_t_end - d.kf_t_drain) * 10;
+      }
     }
     if (lo >= kSelected) {
       out->tracks += d.n_acc;
@@ -1085,7 +1098,7 @@ int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
   if (t->fit_pool < 0 || t->fit_pool > 4096 || t->fit_blocks_per_cu < 0 || t->grid_hits_per_bin < 0 ||
       t->link_blocks_per_cu < 0 || t->fit_min_waves < 0 || t->fit_claims < 0 || t->fit_claims > 1 ||
       t->fit_xcd_slices < 0 || t->fit_xcd_slices > 1 || t->link_stage < 0 || t->link_stage > 2 ||
-      t->fit_long_first < 0)
+      t->fit_long_first < 0 || t->fit_row_bands < 0 || t->fit_row_bands > c->R)
     return TPCCA_EINVAL;
   // the grid layout of loaded units depends on hits per bin
   if (t->grid_hits_per_bin && !c->units.empty() && t->grid_hits_per_bin != c->P.hits_per_bin)
@@ -1095,6 +1108,7 @@ int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
   c->P.kf_xcd = t->fit_xcd_slices;
   c->P.link_stage = t->link_stage;
   c->P.kf_split = t->fit_long_first;
+  c->P.kf_bands = t->fit_row_bands;
   c->P.kf_pool = t->fit_pool ? t->fit_pool : 64;
   c->P.kf_blocks_per_cu = t->fit_blocks_per_cu;
   c->P.link_blocks_per_cu = t->link_blocks_per_cu;
@@ -1117,6 +1131,7 @@ int tpcca_get_tuning(tpcca_ctx_t *c, tpcca_tuning_t *t) {
   t->fit_xcd_slices = c->P.kf_xcd;
   t->link_stage = c->P.link_stage;
   t->fit_long_first = c->P.kf_split;
+  t->fit_row_bands = c->P.kf_bands;
   return TPCCA_OK;
 }
 

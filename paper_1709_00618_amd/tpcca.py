@@ -55,13 +55,15 @@ class DeviceResults(ctypes.Structure):
 class WorkStats(ctypes.Structure):
     _fields_ = [("clusters", c_i64), ("tracklets", c_i64), ("tracks", c_i64), ("track_hits", c_i64),
                 ("fit_steps", c_i64), ("fit_candidates", c_i64), ("fit_tests", c_i64),
-                ("fit_updates", c_i64), ("fit_wave_iterations", c_i64)]
+                ("fit_updates", c_i64), ("fit_wave_iterations", c_i64), ("fit_ns", c_i64),
+                ("fit_drain_ns", c_i64)]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("fit_pool", c_i32), ("fit_blocks_per_cu", c_i32), ("grid_hits_per_bin", c_i32),
                 ("link_blocks_per_cu", c_i32), ("fit_min_waves", c_i32), ("fit_claims", c_i32),
-                ("fit_xcd_slices", c_i32), ("link_stage", c_i32), ("fit_long_first", c_i32)]
+                ("fit_xcd_slices", c_i32), ("link_stage", c_i32), ("fit_long_first", c_i32),
+                ("fit_row_bands", c_i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
