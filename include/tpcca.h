@@ -254,6 +254,8 @@ typedef struct {
                                 first (shorter fits drain the end of the kernel); 0: off */
   int32_t fit_row_bands;     /* fit order by (start-row band, unit) with this many bands of
                                 rows (1..n_rows; overrides fit_long_first); 0: by unit */
+  int32_t fit_tail_units;    /* with fit_row_bands: only the last this many units of a run are
+                                taken band by band, the others stay unit by unit; 0: all */
 } tpcca_tuning_t;
 int tpcca_set_tuning(tpcca_ctx_t *ctx, const tpcca_tuning_t *t);
 int tpcca_get_tuning(tpcca_ctx_t *ctx, tpcca_tuning_t *t);

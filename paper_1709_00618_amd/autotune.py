@@ -19,9 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning_cache.json")
 
 SPACE = {
-    "fit_pool": [32, 64, 128],
+    "fit_pool": [64, 128],
     "fit_min_waves": [0, 4],
-    "fit_row_bands": [0, 8, 40, 159],
 }
 
 

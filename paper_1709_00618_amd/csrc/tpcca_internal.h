@@ -97,6 +97,7 @@ struct ParamsDev {
   int32_t link_stage;  // staging capacity variant of the neighbour kernel (0..2)
   int32_t kf_split;    // chains of at least this many hits are fitted first (0: off)
   int32_t kf_bands;    // fit order by (start-row band, unit) with this many bands (0: unit-major)
+  int32_t kf_tail;     // with bands: only the last this many units are reordered (0: all)
 };
 
 // Device buffers of a context (all indices global).

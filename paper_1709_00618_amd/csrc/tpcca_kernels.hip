@@ -881,19 +881,30 @@ __global__ void k_band_count(Bufs B, ParamsDev P, int run) {
   }
 }
 
-// One block: band-major and unit-major exclusive scans of the bucket counts.
+// One block: exclusive scans of the bucket counts in the new order and in
+// the unit-major order.  The new order keeps the first units unit-major and
+// takes the last kf_tail units (all with kf_tail = 0) band by band.
 __global__ __launch_bounds__(1024) void k_band_scan(Bufs B, ParamsDev P, int run) {
   __shared__ int32_t lds[1024 / 64 + 1];
   const RunDev &rd = B.runs[run];
   const int nu = rd.u1 - rd.u0, nb = P.kf_bands, n = nu * nb;
+  const int nt = (P.kf_tail > 0 && P.kf_tail < nu) ? P.kf_tail : nu;  // units taken band by band
+  const int u0 = nu - nt;
   const int32_t *cnt = B.band_tmp;
   int32_t *off_bm = B.band_tmp + n, *off_um = B.band_tmp + 2 * n;
   for (int order = 0; order < 2; ++order) {
     int32_t carry = 0;
     for (int s0 = 0; s0 < n; s0 += 1024) {
       const int k = s0 + threadIdx.x;  // position in the scan order
-      int j = k;                        // bucket index (band * nu + unit)
-      if (order == 1 && k < n) j = (k % nb) * nu + k / nb;
+      int j = 0;                        // bucket index (band * nu + unit)
+      if (k < n) {
+        if (order == 1 || k < u0 * nb) {  // unit-major part
+          j = (k % nb) * nu + k / nb;
+        } else {                          // band-major part over the last nt units
+          const int kk = k - u0 * nb;
+          j = (kk / nt) * nu + u0 + kk % nt;
+        }
+      }
       const int32_t v = k < n ? cnt[j] : 0;
       int32_t tot;
       const int32_t ex = block_exclusive_scan<int32_t>(v, lds, &tot);

@@ -605,6 +605,7 @@ int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int 
   P.link_stage = 0;
   P.kf_split = 0;
   P.kf_bands = 0;
+  P.kf_tail = 0;
   std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
@@ -1098,7 +1099,7 @@ int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
   if (t->fit_pool < 0 || t->fit_pool > 4096 || t->fit_blocks_per_cu < 0 || t->grid_hits_per_bin < 0 ||
       t->link_blocks_per_cu < 0 || t->fit_min_waves < 0 || t->fit_claims < 0 || t->fit_claims > 1 ||
       t->fit_xcd_slices < 0 || t->fit_xcd_slices > 1 || t->link_stage < 0 || t->link_stage > 2 ||
-      t->fit_long_first < 0 || t->fit_row_bands < 0 || t->fit_row_bands > c->R)
+      t->fit_long_first < 0 || t->fit_row_bands < 0 || t->fit_row_bands > c->R || t->fit_tail_units < 0)
     return TPCCA_EINVAL;
   // the grid layout of loaded units depends on hits per bin
   if (t->grid_hits_per_bin && !c->units.empty() && t->grid_hits_per_bin != c->P.hits_per_bin)
@@ -1109,6 +1110,7 @@ int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
   c->P.link_stage = t->link_stage;
   c->P.kf_split = t->fit_long_first;
   c->P.kf_bands = t->fit_row_bands;
+  c->P.kf_tail = t->fit_tail_units;
   c->P.kf_pool = t->fit_pool ? t->fit_pool : 64;
   c->P.kf_blocks_per_cu = t->fit_blocks_per_cu;
   c->P.link_blocks_per_cu = t->link_blocks_per_cu;
@@ -1132,6 +1134,7 @@ int tpcca_get_tuning(tpcca_ctx_t *c, tpcca_tuning_t *t) {
   t->link_stage = c->P.link_stage;
   t->fit_long_first = c->P.kf_split;
   t->fit_row_bands = c->P.kf_bands;
+  t->fit_tail_units = c->P.kf_tail;
   return TPCCA_OK;
 }
 

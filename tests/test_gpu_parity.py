@@ -152,11 +152,11 @@ def test_batch_equals_sector_by_sector(tpcca, row_x):
 
 @pytest.mark.parametrize("knobs", [
     dict(fit_pool=16, fit_min_waves=0, grid_hits_per_bin=2, link_blocks_per_cu=8, fit_claims=1,
-         fit_xcd_slices=0, link_stage=1, fit_long_first=20),
+         fit_xcd_slices=0, link_stage=1, fit_long_first=20, fit_row_bands=30, fit_tail_units=50),
     dict(fit_pool=128, fit_min_waves=6, grid_hits_per_bin=1, link_blocks_per_cu=16, fit_claims=0,
          fit_xcd_slices=1, link_stage=2, fit_long_first=3, fit_row_bands=159),
     dict(fit_pool=32, fit_min_waves=4, fit_blocks_per_cu=2, grid_hits_per_bin=4, link_blocks_per_cu=32,
-         fit_claims=1, fit_xcd_slices=1, fit_row_bands=7),
+         fit_claims=1, fit_xcd_slices=1, fit_row_bands=7, fit_tail_units=40),
 ])
 def test_schedule_does_not_change_results(tpcca, row_x, knobs):
     """Every launch schedule gives the default schedule's bytes and the oracle's results."""
