@@ -4,7 +4,10 @@ Headline value: tracked TPC clusters per second of the batched form on a
 continuous-readout time frame (128 minimum-bias Pb-Pb events, Poisson
 arrivals at 50 kHz, z shifted by the drift velocity, clusters mixed per
 sector: about 32.5 M clusters), inputs resident in HBM, all stages replayed
-as one captured HIP graph per step.
+as one captured HIP graph per step, two time frames in flight (two
+contexts fed alternately, as the online farm processes several events in
+parallel per GPU; each step is one whole frame).  The same frame with one
+frame in flight is reported beside it ("sequential").
 
 Also reported on the same JSON line:
   per_event   - the plain path, one launch per kernel per central Pb-Pb
@@ -50,7 +53,7 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--events", type=int, default=128, help="events per time frame")
     ap.add_argument("--served-tfs", type=int, default=48, help="time frames per served load level (0: skip)")
@@ -145,6 +148,37 @@ def main():
     stages = {k: float(np.mean([s[k] for s in stage_runs])) for k in stage_runs[0]}
     log("stage ms (timed replays): " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
 
+    # ------------------------------ pipelined: two time frames in flight
+    # two contexts, each with its own stream and buffers, fed alternately:
+    # one frame's early stages fill the GPU while the other's fit drains
+    in_flight, pipe_dt = 1, dt
+    if not args.profile:
+        ctx2 = tpcca.Context(rx, device=0)
+        ctx2.set_tuning(**knobs)
+        pipe = [ctx, ctx2]
+        for i in range(2 * args.warmup):
+            pipe[i % 2].run_batch(dcl, drow, tf.units, device=True, graph=True)
+        for c in pipe:
+            c.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            pipe[i % 2].run_batch(dcl, drow, tf.units, device=True, graph=True)
+        for c in pipe:
+            c.sync()
+        torch.cuda.synchronize()
+        pipe_dt = (time.perf_counter() - t0) / args.steps
+        in_flight = 2
+        # both contexts tracked the same frame: same totals and work counts
+        assert ctx2.batch_totals() == (nu, ncl, ntr, nhits), "pipelined frame totals differ"
+        w2 = ctx2.work_stats()
+        assert all(w2[k] == work[k] for k in ("tracklets", "fit_steps", "fit_updates", "track_hits")), \
+            "pipelined work counts differ"
+        ctx2.close()
+        log(f"pipelined (2 frames in flight): {pipe_dt * 1e3:.2f} ms/frame, "
+            f"{ncl / pipe_dt / 1e9:.3f} G clusters/s")
+    value = ncl / pipe_dt
+
     # --------------------------------------------- per-event plain path
     pe = tpcca.Context(rx, device=0)
 
@@ -205,27 +239,31 @@ def main():
 
     out = {
         "metric": "tracked TPC clusters/s on 1 MI355X (batched time frame; served and per-event beside)",
-        "value": round(batched, 1),
+        "value": round(value, 1),
         "unit": "clusters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt * 1e3, 4),
+        "ms_per_step": round(pipe_dt * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded helices, tpcgen)",
         "config": {"workload": f"continuous-readout time frame: {args.events} min-bias Pb-Pb events at 50 kHz, "
-                               f"36 sector units, {ncl} clusters, device-resident, graph replay",
-                   "clusters": ncl, "units": nu, "tracks": ntr, "assigned_clusters": nhits},
-        "tracks_per_s": round(ntr / dt, 1),
+                               f"36 sector units, {ncl} clusters, device-resident, graph replay, "
+                               f"{in_flight} frame(s) in flight",
+                   "clusters": ncl, "units": nu, "tracks": ntr, "assigned_clusters": nhits,
+                   "in_flight": in_flight},
+        "tracks_per_s": round(ntr / pipe_dt, 1),
+        "sequential": {"value": round(batched, 1), "unit": "clusters/s", "ms_per_step": round(dt * 1e3, 4),
+                       "in_flight": 1},
         "schedule": {"knobs": knobs, "source": knob_src},
         "work": work,
         "per_event": {"workload": f"central Pb-Pb event, 8000 tracks, {ev.n_clusters} clusters, one launch per "
                                   "kernel per event, device-resident",
                       "value": round(per_event, 1), "unit": "clusters/s", "ms_per_event": round(pe_dt * 1e3, 4)},
-        "batched_over_per_event": round(batched / per_event, 3),
+        "batched_over_per_event": round(value / per_event, 3),
         "served": served,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roofline,

@@ -103,6 +103,28 @@ def test_graph_replays_track_changing_batches(tpcca, torch_cuda, row_x):
             _parity.compare_batch(units, tracks, hits, asg, b, refs)
 
 
+def test_two_frames_in_flight(tpcca, torch_cuda, row_x):
+    """Two contexts fed alternately (two frames in flight on one GPU, as the
+    pipelined bench runs them): every frame's results are the oracle's."""
+    torch = torch_cuda
+    frames = [tpcgen.minbias_batch(seed=s, n_events=3) for s in (11, 12)]
+    refs = [_parity.oracle_units(b, row_x) for b in frames]
+    dev = [(_dev(torch, b.cl), _dev(torch, b.row)) for b in frames]
+    torch.cuda.synchronize()
+    with tpcca.Context(row_x) as c0, tpcca.Context(row_x) as c1:
+        ctxs = (c0, c1)
+        for i in range(6):
+            k = i % 2
+            print(f"frame {i}: context {k}, {frames[k].n_clusters} clusters", flush=True)
+            ctxs[k].run_batch(dev[k][0], dev[k][1], frames[k].units, device=True, graph=True)
+            if i >= 4:
+                # the other context's frame is still in flight here
+                units, tracks, hits, asg = ctxs[k].get_batch_results()
+                _parity.compare_batch(units, tracks, hits, asg, frames[k], refs[k])
+        c0.sync()
+        c1.sync()
+
+
 def test_timed_graph_replays_give_the_same_results(tpcca, row_x):
     """Stage timing in graph mode (one graph per stage, events between)
     changes nothing in the results and reports every stage."""
