@@ -100,6 +100,10 @@ struct ParamsDev {
   int32_t kf_tail;     // with bands: only the last this many units are reordered (0: all)
 };
 
+// Hit slots per tracklet: n_rows rounded up to whole 16-B groups, so that
+// every tracklet's slots start 16-B aligned and move four at a time.
+__host__ __device__ inline int slot_stride(int R) { return (R + 3) & ~3; }
+
 // Device buffers of a context (all indices global).
 struct Bufs {
   const float *row_x;
@@ -131,7 +135,7 @@ struct Bufs {
   int32_t *trk_unit;     // tracklet -> unit
   int32_t *unit_tbegin;  // unit -> first tracklet
   tpcca_tracklet_t *trk; // tracklet fits
-  int32_t *trk_hits;     // tracklet x n_rows sorted indices
+  int32_t *trk_hits;     // tracklet x slot_stride(n_rows) hit slots
   unsigned long long *owner;  // by sorted index
   unsigned long long *accv;   // by tracklet: accepted << 40 | won hits
   unsigned long long *wonmask;  // by tracklet: 4 x 64 bits, slot k won its hit

@@ -1222,6 +1222,19 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
   // the outermost hit, then the pass-2 state at the innermost hit
   __shared__ float s_aux[21][kKfBlock];
   const int tid = threadIdx.x;
+  // hit slots go to memory four at a time (one 16-B store): a lane collects
+  // a group in LDS and writes it when complete or when its phase ends; the
+  // refit reads them back a group at a time
+  __shared__ int32_t s_slot[4][kKfBlock];
+  const int Rs = slot_stride(R);
+  auto slot_flush = [&](int j) {  // the group holding slot j
+    const int4 q = make_int4(s_slot[0][tid], s_slot[1][tid], s_slot[2][tid], s_slot[3][tid]);
+    *reinterpret_cast<int4 *>(B.trk_hits + (int64_t)t * Rs + (j & ~3)) = q;
+  };
+  auto slot_put = [&](int j, int32_t v) {
+    s_slot[j & 3][tid] = v;
+    if ((j & 3) == 3) slot_flush(j);
+  };
   auto save_aux = [&]() {
 #pragma unroll
     for (int q = 0; q < 5; ++q) s_aux[q][tid] = st.p[q];
@@ -1306,7 +1319,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
             st.C[9] = P.c33;
             st.C[14] = P.c44;
             st.x = x0;
-            B.trk_hits[(int64_t)t * R] = slot_enc(g0, ucl, r0);
+            s_slot[0][tid] = slot_enc(g0, ucl, r0);
             prev = g0;
             k = 1;
             chi2 = 0.0f;
@@ -1326,7 +1339,14 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
       given = B.upc[prev];
       row = r0 + k;
     } else if (phase == kRefit) {
-      const int32_t v = B.trk_hits[(int64_t)t * R + k];
+      if (k == n1 - 1 || (k & 3) == 3) {
+        const int4 q = *reinterpret_cast<const int4 *>(B.trk_hits + (int64_t)t * Rs + (k & ~3));
+        s_slot[0][tid] = q.x;
+        s_slot[1][tid] = q.y;
+        s_slot[2][tid] = q.z;
+        s_slot[3][tid] = q.w;
+      }
+      const int32_t v = s_slot[k & 3][tid];
       given = slot_hit(v, ucl);
       row = slot_row(v);
       prop = k < n1 - 1;
@@ -1366,7 +1386,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
         kf_fail(B, t, start_id, n_chain);
         phase = kIdle;
       } else {
-        B.trk_hits[(int64_t)t * R + k] = slot_enc(h, ucl, row);
+        slot_put(k, slot_enc(h, ucl, row));
         prev = h;
         if (++k == n_chain) {
           save_aux();
@@ -1398,10 +1418,15 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
         } else {
           if (upd) {
             if (fwd) {
-              B.trk_hits[(int64_t)t * R + n1++] = slot_enc(h, ucl, r);
+              slot_put(n1, slot_enc(h, ucl, r));
+              ++n1;
             } else {
               chi2 = chi2 + c2;
-              B.trk_hits[(int64_t)t * R + n1 + ne] = slot_enc(h, ucl, r);
+              const int j = n1 + ne;
+              if ((j & ~3) < n1)  // a group shared with pass-1 slots: this slot alone
+                B.trk_hits[(int64_t)t * Rs + j] = slot_enc(h, ucl, r);
+              else
+                slot_put(j, slot_enc(h, ucl, r));
               ++ne;
             }
             save_aux();
@@ -1413,7 +1438,10 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
         }
       }
       if (end && fwd) {
-        // end of pass 1: keep its state in the record, restart for pass 2
+        // end of pass 1: its last (partial) slot group goes to memory (the
+        // slots after n1 are written again by pass 2 or never read); keep
+        // the pass-1 state in the record, restart for pass 2
+        if (n1 & 3) slot_flush(n1 - 1);
         tpcca_tracklet_t &o = B.trk[t];
 #pragma unroll
         for (int q = 0; q < 5; ++q) o.p_out[q] = st.p[q] = s_aux[q][tid];
@@ -1431,8 +1459,12 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
         o.n_hits = n1 + ne;
         o.n_pass1 = n1;
         o.ndf = 2 * (n1 + ne) - 5;
+        // the last partial group of pass-2 slots (one that does not share
+        // pass-1 slots) goes to memory
+        const int jl = n1 + ne - 1;
+        if (ne > 0 && (jl & 3) != 3 && (jl & ~3) >= n1) slot_flush(jl);
         // outermost pass-1 hit and innermost hit, from their slots' rows
-        const int32_t *hl = B.trk_hits + (int64_t)t * R;
+        const int32_t *hl = B.trk_hits + (int64_t)t * Rs;
         o.row_out = slot_row(hl[n1 - 1]);
         o.row_ref = ne > 0 ? slot_row(hl[n1 + ne - 1]) : r0;
         o.x_ref = s_aux[20][tid];
@@ -1464,7 +1496,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
             nn, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(chi2), src)),
             __builtin_amdgcn_readlane(start_id, src));
         const int uc = __builtin_amdgcn_readlane(ucl, src);
-        const int32_t *hh = B.trk_hits + (int64_t)tt * R;
+        const int32_t *hh = B.trk_hits + (int64_t)tt * Rs;
         for (int j = lane; j < nn; j += 64) atomicMax(&B.owner[slot_hit(hh[j], uc)], kk);
       }
     }
@@ -1498,7 +1530,7 @@ __global__ __launch_bounds__(kBlock) void k_claim(Bufs B, ParamsDev P, int run) 
     const tpcca_tracklet_t &o = B.trk[t];
     if (o.status != 0) continue;
     const unsigned long long key = select_key(o);
-    const int32_t *hl = B.trk_hits + (int64_t)t * R;
+    const int32_t *hl = B.trk_hits + (int64_t)t * slot_stride(R);
     const int ucl = B.units[B.trk_unit[t]].cl_begin;
     const int n = o.n_hits;
     for (int j0 = 0; j0 < n; j0 += 8) {
@@ -1532,7 +1564,7 @@ __global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
     unsigned long long v = 0;
     if (o.status == 0) {
       const unsigned long long key = select_key(o);
-      const int32_t *hl = B.trk_hits + (int64_t)t * R;
+      const int32_t *hl = B.trk_hits + (int64_t)t * slot_stride(R);
       const int ucl = B.units[B.trk_unit[t]].cl_begin;
       unsigned long long *wm = B.wonmask + (int64_t)t * 4;
       const int n = o.n_hits;
@@ -1674,7 +1706,7 @@ __global__ __launch_bounds__(kBlock) void k_output(Bufs B, ParamsDev P, int run)
     const unsigned long long ex = B.accx[tl];
     const int k = rd.trk0 + acc_count(ex);
     const int64_t h0 = rd.cl0 + acc_hits(ex);
-    const int32_t *hl = B.trk_hits + (int64_t)t * R;
+    const int32_t *hl = B.trk_hits + (int64_t)t * slot_stride(R);
     const int n1 = o.n_pass1, nh = o.n_hits, ne = nh - n1;
     const int local_track = k - tb;
     const unsigned long long *wmp = B.wonmask + (int64_t)t * 4;

@@ -255,7 +255,7 @@ static int ensure_work(tpcca_ctx *c, int64_t n_cl, int64_t n_units, int64_t n_bi
   ENS(trk_unit, T, sizeof(int32_t), keepT);
   ENS(unit_tbegin, U + 1, sizeof(int32_t), keepU);
   ENS(trk, T, sizeof(tpcca_tracklet_t), keepT);
-  ENS(trk_hits, T * (size_t)R, sizeof(int32_t), keepT * (size_t)R);
+  ENS(trk_hits, T * (size_t)slot_stride(R), sizeof(int32_t), keepT * (size_t)slot_stride(R));
   ENS(accv, T + 1, sizeof(unsigned long long), 0);
   ENS(wonmask, 4 * T, sizeof(unsigned long long), 0);
   ENS(accx, T + 1, sizeof(unsigned long long), 0);
@@ -785,15 +785,16 @@ int tpcca_get_tracklets(tpcca_ctx_t *c, int32_t slot, int32_t sector, tpcca_trac
     if (U.n)
       RCCHK(copy_sync(c, sid.data(), ptr<int32_t>(c->sid) + U.cl_begin, sizeof(int32_t) * U.n,
                           hipMemcpyDeviceToHost));
-    std::vector<int32_t> slots((size_t)T * c->R);
+    const int Rs = slot_stride(c->R);
+    std::vector<int32_t> slots((size_t)T * Rs);
     if (T)
-      RCCHK(copy_sync(c, slots.data(), ptr<int32_t>(c->trk_hits) + (int64_t)t0 * c->R,
+      RCCHK(copy_sync(c, slots.data(), ptr<int32_t>(c->trk_hits) + (int64_t)t0 * Rs,
                           sizeof(int32_t) * slots.size(), hipMemcpyDeviceToHost));
     int64_t off = 0;
     for (int t = 0; t < T; ++t) {
       if (hit_begin) hit_begin[t] = off;
       const int n1 = trk[t].n_pass1, ne = trk[t].n_hits - trk[t].n_pass1;
-      const int32_t *hl = slots.data() + (size_t)t * c->R;
+      const int32_t *hl = slots.data() + (size_t)t * Rs;
       for (int j = 0; j < trk[t].n_hits; ++j) {
         // slots hold the unit-local sorted index in their low 24 bits
         const int32_t v = j < ne ? hl[n1 + ne - 1 - j] : hl[j - ne];
