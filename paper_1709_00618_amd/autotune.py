@@ -109,5 +109,5 @@ def tuned(ctx, cl, row, units, n_clusters, device=True, log=None, retune=False):
 
 
 def _default(table):
-    d = {"fit_pool": 64, "fit_min_waves": 0, "fit_row_bands": 0}
+    d = {"fit_pool": 64, "fit_min_waves": 0}
     return d if any(k == d for _, k in table) else None
