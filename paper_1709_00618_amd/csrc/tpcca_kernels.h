@@ -12,6 +12,7 @@ struct RunHost {
   int64_t bin0, bin1;
   int32_t trk0, trk_cap;
   int32_t tile0, tile1;
+  int32_t dense;  // mean pad-row occupancy of the batch's units >= 1024 (row sort variant)
 };
 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);

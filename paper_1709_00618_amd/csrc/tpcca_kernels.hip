@@ -350,24 +350,52 @@ __global__ __launch_bounds__(kBlock) void k_rowscatter(Bufs B, int run, int R) {
 __device__ __forceinline__ int hpad(int k) { return k + (k >> 5); }
 
 // Pass 4, one block per (unit, row): counting sort of the row's records by
-// z bin in LDS; writes the row's bin offsets and its sorted hits.  The
-// scattered writes stay inside the row's own segment.
-
-__global__ __launch_bounds__(kBlock) void k_rowsort(Bufs B, int run, int R) {
+// z bin in LDS; writes the row's bin offsets and its sorted hits.
+//   kStage false (sparse rows, kT = 256): the records are read twice (count,
+//     then scatter) and scattered straight into the row's own segment.
+//   kStage true (dense rows, kT = 1024, one block per CU by its LDS): a row
+//     of up to kT * 8 records is read once into registers, sorted into LDS
+//     and written out in order, so that no partially written line leaves
+//     L2; a longer row takes the scatter path.
+template <int kT, bool kStage>
+__global__ __launch_bounds__(kT) void k_rowsort(Bufs B, int run, int R) {
+  constexpr int kPer = 8, kCap = kStage ? kT * kPer : 1;
   __shared__ int hist[kMaxBinsRow + kMaxBinsRow / 32];
-  __shared__ int lds[kBlock / 64 + 1];
+  __shared__ int lds[kT / 64 + 1];
+  __shared__ float2 s_yz[kCap];
+  __shared__ int32_t s_sid[kCap];
+  __shared__ uint8_t s_row[kCap];
   const RunDev &rd = B.runs[run];
   const int nrows = (rd.u1 - rd.u0) * (R + 1);
-  constexpr int per = kMaxBinsRow / kBlock;
+  constexpr int per = kMaxBinsRow / kT;
   for (int w = blockIdx.x; w < nrows; w += gridDim.x) {
     const int64_t rr = (int64_t)rd.u0 * (R + 1) + w;
     const RowTab t = B.rowtab[rr];
     for (int k = threadIdx.x; k < t.nb; k += blockDim.x) hist[hpad(k)] = 0;
     __syncthreads();
+    const bool staged = kStage && t.count <= kCap;  // uniform over the block
+    int4 rec[kStage ? kPer : 1];
+    int bin[kStage ? kPer : 1];
+    if (staged) {
+#pragma unroll
+      for (int q = 0; q < (kStage ? kPer : 1); ++q) {
+        const int i = threadIdx.x + q * kT;
+        if (i < t.count) rec[q] = B.rtmp[t.begin + i];
+      }
+#pragma unroll
+      for (int q = 0; q < (kStage ? kPer : 1); ++q) {
+        const int i = threadIdx.x + q * kT;
+        if (i < t.count) {
+          bin[q] = zbin(t, __int_as_float(rec[q].y));
+          atomicAdd(&hist[hpad(bin[q])], 1);
+        }
+      }
+    } else {
 #pragma unroll 4
-    for (int i = threadIdx.x; i < t.count; i += blockDim.x) {
-      const int4 rec = B.rtmp[t.begin + i];
-      atomicAdd(&hist[hpad(zbin(t, __int_as_float(rec.y)))], 1);
+      for (int i = threadIdx.x; i < t.count; i += blockDim.x) {
+        const int4 r4 = B.rtmp[t.begin + i];
+        atomicAdd(&hist[hpad(zbin(t, __int_as_float(r4.y)))], 1);
+      }
     }
     __syncthreads();
     // exclusive scan of the nb bin counts (per consecutive entries per thread)
@@ -390,14 +418,33 @@ __global__ __launch_bounds__(kBlock) void k_rowsort(Bufs B, int run, int R) {
     for (int k = threadIdx.x; k < t.nb; k += blockDim.x) B.binbeg[t.bin0 + k] = t.begin + hist[hpad(k)];
     if (threadIdx.x == 0) B.binbeg[t.bin0 + t.nb] = t.begin + t.count;
     __syncthreads();  // every begin is read before the scatter moves the cursors
+    if (staged) {
+#pragma unroll
+      for (int q = 0; q < (kStage ? kPer : 1); ++q) {
+        const int i = threadIdx.x + q * kT;
+        if (i < t.count) {
+          const int pos = atomicAdd(&hist[hpad(bin[q])], 1);
+          s_yz[pos] = make_float2(__int_as_float(rec[q].x), __int_as_float(rec[q].y));
+          s_sid[pos] = rec[q].z;
+          s_row[pos] = (uint8_t)rec[q].w;
+        }
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < t.count; i += blockDim.x) {
+        B.yz[t.begin + i] = s_yz[i];
+        B.sid[t.begin + i] = s_sid[i];
+        B.srow[t.begin + i] = s_row[i];
+      }
+    } else {
 #pragma unroll 4
-    for (int i = threadIdx.x; i < t.count; i += blockDim.x) {
-      const int4 rec = B.rtmp[t.begin + i];
-      const float z = __int_as_float(rec.y);
-      const int pos = t.begin + atomicAdd(&hist[hpad(zbin(t, z))], 1);
-      B.yz[pos] = make_float2(__int_as_float(rec.x), z);
-      B.sid[pos] = rec.z;
-      B.srow[pos] = (uint8_t)rec.w;
+      for (int i = threadIdx.x; i < t.count; i += blockDim.x) {
+        const int4 r4 = B.rtmp[t.begin + i];
+        const float z = __int_as_float(r4.y);
+        const int pos = t.begin + atomicAdd(&hist[hpad(zbin(t, z))], 1);
+        B.yz[pos] = make_float2(__int_as_float(r4.x), z);
+        B.sid[pos] = r4.z;
+        B.srow[pos] = (uint8_t)r4.w;
+      }
     }
     __syncthreads();
   }
@@ -1795,7 +1842,14 @@ hipError_t launch_grid(const Bufs &B, const ParamsDev &P, int run, const RunHost
   if (nch > 0) k_count<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run, R);
   if (nu > 0) k_plan<<<grid_for(nu, 1, 4096), kBlock, 0, s>>>(B, run, R, P.hits_per_bin);
   if (nch > 0) k_rowscatter<<<grid_for((nch + kGroup - 1) / kGroup, 1, 8192), kBlock, 0, s>>>(B, run, R);
-  if (nu > 0) k_rowsort<<<grid_for((int64_t)nu * (R + 1), 1, 16384), kBlock, 0, s>>>(B, run, R);
+  if (nu > 0) {
+    // dense rows (time frames): the staged sort, one 1024-thread block per CU
+    const int64_t rows = (int64_t)nu * (R + 1);
+    if (h.dense)
+      k_rowsort<1024, true><<<grid_for(rows, 1, 16384), 1024, 0, s>>>(B, run, R);
+    else
+      k_rowsort<kBlock, false><<<grid_for(rows, 1, 16384), kBlock, 0, s>>>(B, run, R);
+  }
   return hipGetLastError();
 }
 

@@ -317,6 +317,7 @@ static RunHost make_run(tpcca_ctx *c, int u0, int u1) {
   h.trk_cap = (int32_t)(L.trk_base + trk_cap_of(L.n, c->P.min_chain) - h.trk0);
   h.tile0 = c->units[u0].tile_base;
   h.tile1 = (int32_t)(L.tile_base + tile_cap_of(L.n, c->R));
+  h.dense = (int64_t)(h.cl1 - h.cl0) / ((int64_t)(u1 - u0) * (c->R + 1)) >= 1024 ? 1 : 0;
   return h;
 }
 
@@ -928,6 +929,7 @@ int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
   const bool reuse = c->gexec[0] && c->gen_captured == c->generation && c->gcap.u1 == capr.u1 &&
                      c->gcap.c1 == capr.c1 && c->gcap.cl1 == capr.cl1 && c->gcap.bin1 == capr.bin1 &&
                      c->gcap.trk_cap == capr.trk_cap && c->gcap.tile1 == capr.tile1 &&
+                     c->gcap.dense == capr.dense &&
                      c->gtiming == c->timing;
   if (!reuse) {
     std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());

@@ -90,6 +90,27 @@ def test_minbias_batch(tpcca, torch_cuda, row_x, graph):
     _parity.compare_batch(units, tracks, hits, asg, b, refs)
 
 
+def test_dense_rows_time_frame(tpcca, torch_cuda, row_x):
+    """Three sector units of a 32-event time frame (about 1400 hits per pad
+    row, the dense-row sort that stages a row in LDS), graph and eager."""
+    torch = torch_cuda
+    tf = tpcgen.timeframe(seed=3, n_events=32)
+    parts = [tf.unit(u) for u in (0, 7, 30)]
+    off = np.cumsum([0] + [p[0].shape[0] for p in parts])
+    units = np.array([(off[i], parts[i][0].shape[0], parts[i][2], parts[i][3]) for i in range(3)], np.int64)
+    b = tpcgen.Batch(np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts]), units)
+    assert b.n_clusters / (3 * (row_x.shape[0] + 1)) >= 1024
+    print(f"dense batch: {b.n_clusters} clusters", flush=True)
+    refs = _parity.oracle_units(b, row_x)
+    dcl, drow = _dev(torch, b.cl), _dev(torch, b.row)
+    torch.cuda.synchronize()
+    with tpcca.Context(row_x) as ctx:
+        for graph in (True, False):
+            ctx.run_batch(dcl, drow, b.units, device=True, graph=graph)
+            units_r, tracks, hits, asg = ctx.get_batch_results()
+            _parity.compare_batch(units_r, tracks, hits, asg, b, refs)
+
+
 def test_graph_replays_track_changing_batches(tpcca, torch_cuda, row_x):
     """One context, graph replays of different batches, host work between."""
     torch = torch_cuda
