@@ -100,9 +100,10 @@ struct ParamsDev {
   int32_t kf_tail;     // with bands: only the last this many units are reordered (0: all)
 };
 
-// Hit slots per tracklet: n_rows rounded up to whole 16-B groups, so that
-// every tracklet's slots start 16-B aligned and move four at a time.
-__host__ __device__ inline int slot_stride(int R) { return (R + 3) & ~3; }
+// Hit slots per tracklet: n_rows rounded up to whole 32-B groups, so that
+// every tracklet's slots start 32-B aligned and move eight at a time.
+constexpr int kSlotGrp = 8;
+__host__ __device__ inline int slot_stride(int R) { return (R + kSlotGrp - 1) & ~(kSlotGrp - 1); }
 
 // Device buffers of a context (all indices global).
 struct Bufs {

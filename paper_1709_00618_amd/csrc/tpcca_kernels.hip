@@ -1269,18 +1269,22 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
   // the outermost hit, then the pass-2 state at the innermost hit
   __shared__ float s_aux[21][kKfBlock];
   const int tid = threadIdx.x;
-  // hit slots go to memory four at a time (one 16-B store): a lane collects
-  // a group in LDS and writes it when complete or when its phase ends; the
-  // refit reads them back a group at a time
-  __shared__ int32_t s_slot[4][kKfBlock];
+  // hit slots go to memory eight at a time (one aligned 32-B group): a lane
+  // collects a group in LDS and writes it when complete or when its phase
+  // ends; the refit reads them back a group at a time.  Scattered stores
+  // narrower than a memory segment cost a read-modify-write each, so fewer,
+  // wider ones matter.
+  constexpr int G = kSlotGrp, GM = kSlotGrp - 1;
+  __shared__ int32_t s_slot[G][kKfBlock];
   const int Rs = slot_stride(R);
   auto slot_flush = [&](int j) {  // the group holding slot j
-    const int4 q = make_int4(s_slot[0][tid], s_slot[1][tid], s_slot[2][tid], s_slot[3][tid]);
-    *reinterpret_cast<int4 *>(B.trk_hits + (int64_t)t * Rs + (j & ~3)) = q;
+    int4 *dst = reinterpret_cast<int4 *>(B.trk_hits + (int64_t)t * Rs + (j & ~GM));
+    dst[0] = make_int4(s_slot[0][tid], s_slot[1][tid], s_slot[2][tid], s_slot[3][tid]);
+    dst[1] = make_int4(s_slot[4][tid], s_slot[5][tid], s_slot[6][tid], s_slot[7][tid]);
   };
   auto slot_put = [&](int j, int32_t v) {
-    s_slot[j & 3][tid] = v;
-    if ((j & 3) == 3) slot_flush(j);
+    s_slot[j & GM][tid] = v;
+    if ((j & GM) == GM) slot_flush(j);
   };
   auto save_aux = [&]() {
 #pragma unroll
@@ -1386,14 +1390,19 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
       given = B.upc[prev];
       row = r0 + k;
     } else if (phase == kRefit) {
-      if (k == n1 - 1 || (k & 3) == 3) {
-        const int4 q = *reinterpret_cast<const int4 *>(B.trk_hits + (int64_t)t * Rs + (k & ~3));
-        s_slot[0][tid] = q.x;
-        s_slot[1][tid] = q.y;
-        s_slot[2][tid] = q.z;
-        s_slot[3][tid] = q.w;
+      if (k == n1 - 1 || (k & GM) == GM) {
+        const int4 *src = reinterpret_cast<const int4 *>(B.trk_hits + (int64_t)t * Rs + (k & ~GM));
+        const int4 q0 = src[0], q1 = src[1];
+        s_slot[0][tid] = q0.x;
+        s_slot[1][tid] = q0.y;
+        s_slot[2][tid] = q0.z;
+        s_slot[3][tid] = q0.w;
+        s_slot[4][tid] = q1.x;
+        s_slot[5][tid] = q1.y;
+        s_slot[6][tid] = q1.z;
+        s_slot[7][tid] = q1.w;
       }
-      const int32_t v = s_slot[k & 3][tid];
+      const int32_t v = s_slot[k & GM][tid];
       given = slot_hit(v, ucl);
       row = slot_row(v);
       prop = k < n1 - 1;
@@ -1470,7 +1479,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
             } else {
               chi2 = chi2 + c2;
               const int j = n1 + ne;
-              if ((j & ~3) < n1)  // a group shared with pass-1 slots: this slot alone
+              if ((j & ~GM) < n1)  // a group shared with pass-1 slots: this slot alone
                 B.trk_hits[(int64_t)t * Rs + j] = slot_enc(h, ucl, r);
               else
                 slot_put(j, slot_enc(h, ucl, r));
@@ -1488,7 +1497,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
         // end of pass 1: its last (partial) slot group goes to memory (the
         // slots after n1 are written again by pass 2 or never read); keep
         // the pass-1 state in the record, restart for pass 2
-        if (n1 & 3) slot_flush(n1 - 1);
+        if (n1 & GM) slot_flush(n1 - 1);
         tpcca_tracklet_t &o = B.trk[t];
 #pragma unroll
         for (int q = 0; q < 5; ++q) o.p_out[q] = st.p[q] = s_aux[q][tid];
@@ -1509,7 +1518,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
         // the last partial group of pass-2 slots (one that does not share
         // pass-1 slots) goes to memory
         const int jl = n1 + ne - 1;
-        if (ne > 0 && (jl & 3) != 3 && (jl & ~3) >= n1) slot_flush(jl);
+        if (ne > 0 && (jl & GM) != GM && (jl & ~GM) >= n1) slot_flush(jl);
         // outermost pass-1 hit and innermost hit, from their slots' rows
         const int32_t *hl = B.trk_hits + (int64_t)t * Rs;
         o.row_out = slot_row(hl[n1 - 1]);
