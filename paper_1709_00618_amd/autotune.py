@@ -5,7 +5,10 @@ granularity, never a result: every decision compares cluster IDs and each
 tracklet sees the same operation sequence whatever the schedule.  The tuner
 replays the batch graph of a sample batch for every point of a small grid of
 schedules, keeps the fastest, and caches it in ``tuning_cache.json`` keyed by
-device name and a size bucket of the batch (clusters, units).
+device name and a size bucket of the batch (clusters, units).  Given a second
+context, a point is timed with two batches in flight (the contexts fed
+alternately), the way the batched bench and the server run: then the cost
+per batch includes how well one batch's stages fill the other's fit drain.
 """
 from __future__ import annotations
 
@@ -21,6 +24,7 @@ CACHE = os.path.join(HERE, "tuning_cache.json")
 SPACE = {
     "fit_pool": [64, 128],
     "fit_min_waves": [0, 4],
+    "fit_blocks_per_cu": [0, 6],
 }
 
 
@@ -67,41 +71,65 @@ def _time(ctx, run, reps):
     return ts[len(ts) // 2]
 
 
-def tune(ctx, cl, row, units, device=True, reps=3, space=None, log=None):
-    """Sweep the schedule grid on one batch; returns (best dict, table)."""
+def _time_pipelined(ctxs, run, frames=8, reps=2):
+    """Median over reps of the time per batch with len(ctxs) batches in flight."""
+    for i in range(2 * len(ctxs)):
+        run(ctxs[i % len(ctxs)])
+    for c in ctxs:
+        c.sync()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        for i in range(frames):
+            run(ctxs[i % len(ctxs)])
+        for c in ctxs:
+            c.sync()
+        ts.append((time.perf_counter() - t0) / frames)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune(ctx, cl, row, units, device=True, reps=3, space=None, log=None, ctx2=None):
+    """Sweep the schedule grid on one batch; returns (best dict, table).
+    With ctx2, every point is timed with two batches in flight."""
     space = space or SPACE
     names = list(space)
     table = []
+    ctxs = [ctx] if ctx2 is None else [ctx, ctx2]
 
-    def run():
-        ctx.run_batch(cl, row, units, device=device, graph=True)
+    def run(c=ctx):
+        c.run_batch(cl, row, units, device=device, graph=True)
 
     for combo in itertools.product(*(space[n] for n in names)):
         knobs = dict(zip(names, combo))
-        ctx.reset()
-        ctx.set_tuning(**knobs)
-        t = _time(ctx, run, reps)
+        for c in ctxs:
+            c.reset()
+            c.set_tuning(**knobs)
+        t = _time(ctx, run, reps) if ctx2 is None else _time_pipelined(ctxs, run)
         table.append((t, knobs))
         if log:
             log(f"autotune {knobs}: {t * 1e3:.3f} ms")
     table.sort(key=lambda x: x[0])
     best = dict(table[0][1])
-    ctx.reset()
-    ctx.set_tuning(**best)
+    for c in ctxs:
+        c.reset()
+        c.set_tuning(**best)
     return best, table
 
 
-def tuned(ctx, cl, row, units, n_clusters, device=True, log=None, retune=False):
+def tuned(ctx, cl, row, units, n_clusters, device=True, log=None, retune=False, ctx2=None):
     """Apply the cached schedule for this device and size, tuning first if
-    there is none.  Returns (knobs, source)."""
+    there is none (with ctx2: timed with two batches in flight).  Returns
+    (knobs, source)."""
     n_units = len(units)
     entry = None if retune else lookup(n_clusters, n_units)
     if entry is not None:
-        ctx.reset()
-        ctx.set_tuning(**entry["knobs"])
+        for c in [ctx] if ctx2 is None else [ctx, ctx2]:
+            c.reset()
+            c.set_tuning(**entry["knobs"])
         return entry["knobs"], "cache"
-    best, table = tune(ctx, cl, row, units, device=device, log=log)
-    store({"knobs": best, "ms": round(table[0][0] * 1e3, 4),
+    best, table = tune(ctx, cl, row, units, device=device, log=log, ctx2=ctx2)
+    store({"knobs": best, "ms": round(table[0][0] * 1e3, 4), "in_flight": 1 if ctx2 is None else 2,
            "default_ms": round(next(t for t, k in table if k == _default(table)) * 1e3, 4)
            if _default(table) else None},
           n_clusters, n_units)
@@ -109,5 +137,5 @@ def tuned(ctx, cl, row, units, n_clusters, device=True, log=None, retune=False):
 
 
 def _default(table):
-    d = {"fit_pool": 64, "fit_min_waves": 0}
+    d = {"fit_pool": 64, "fit_min_waves": 0, "fit_blocks_per_cu": 0}
     return d if any(k == d for _, k in table) else None
