@@ -316,20 +316,26 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
         n = name.split("(")[0].replace("void ", "").strip()
         return n.replace("tpcca::", "")
 
-    # kernel trace: time-frame dispatches are the first (warmup + steps) of each kernel
-    rows = sorted(csv.DictReader(open(one(trace_dir, "*kernel_trace.csv"))), key=lambda r: int(r["Dispatch_Id"]))
-    per = {}
-    for r in rows:
-        per.setdefault(short(r["Kernel_Name"]), []).append(
-            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     tf_n = 4  # bench.py --profile: 1 warm-up + 3 timed replays of the time frame
+
+    def tf_end(ids_names):
+        # the time-frame replays come first; each ends with k_output
+        outs = sorted(i for i, n in ids_names if short(n) == "k_output")
+        return outs[tf_n - 1] if len(outs) >= tf_n else max(i for i, _ in ids_names)
+
+    # kernel trace: split at the last dispatch of the time-frame replays
+    rows = sorted(csv.DictReader(open(one(trace_dir, "*kernel_trace.csv"))), key=lambda r: int(r["Dispatch_Id"]))
+    end_tr = tf_end([(int(r["Dispatch_Id"]), r["Kernel_Name"]) for r in rows])
+    per, per_o = {}, {}
+    for r in rows:
+        (per if int(r["Dispatch_Id"]) <= end_tr else per_o).setdefault(short(r["Kernel_Name"]), []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     lines = ["| kernel | TF dispatches | avg us (TF) | share | other dispatches | avg us (other) |",
              "|---|---|---|---|---|---|"]
-    tf_tot = {k: sum(v[:tf_n]) for k, v in per.items() if k.startswith("k_")}
+    tf_tot = {k: sum(v) for k, v in per.items() if k.startswith("k_")}
     total = sum(tf_tot.values())
     for k in sorted(tf_tot, key=lambda k: -tf_tot[k]):
-        v = per[k]
-        a, b = v[:tf_n], v[tf_n:]
+        a, b = per[k], per_o.get(k, [])
         lines.append(f"| {k} | {len(a)} | {np.mean(a):.1f} | {100 * tf_tot[k] / total:.1f}% | {len(b)} | "
                      f"{(np.mean(b) if b else 0):.1f} |")
 
@@ -339,7 +345,8 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
             if r["Counter_Name"] != name:
                 continue
             vals.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
-        return [vals[k] for k in sorted(vals)]
+        end = tf_end([(k, v[0]) for k, v in vals.items()])
+        return [vals[k] + [k <= end] for k in sorted(vals)]
 
     out = {"source_hash": kernel_source_hash(), "command": command, "kernels": {}}
     fac = {}
@@ -347,19 +354,19 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
         seq = counters(d, cname)
         # the calibration copy: 1 GiB read and written; first dispatches before any tracker kernel
         cal = []
-        for name, v in seq:
+        for name, v, _ in seq:
             if "tpcca" in name:
                 break
             cal.append((name, v))
         big = [v for name, v in cal if v > 0.5 * (1 << 20)]  # KiB
         fac[cname] = (1 << 20) / float(np.median(big)) if big else 1.0
         byk = {}
-        for name, v in seq:
-            if "tpcca" in name:
+        for name, v, in_tf in seq:
+            if "tpcca" in name and in_tf:
                 byk.setdefault(short(name), []).append(v * 1024.0 * fac[cname])
         for k, v in byk.items():
             e = out["kernels"].setdefault(k, {})
-            e[cname.lower()] = float(np.mean(v[:tf_n]))
+            e[cname.lower()] = float(np.mean(v))
     for k, e in out["kernels"].items():
         e["bytes"] = e.get("fetch_size", 0.0) + e.get("write_size", 0.0)
     out["factor"] = fac
@@ -389,8 +396,10 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
     if sq_dir:
         # instruction counters per wave of the TF dispatches (summed over the chip)
         per_k = {}
-        for r in csv.DictReader(open(one(sq_dir, "*counter_collection.csv"))):
-            if "tpcca" not in r["Kernel_Name"]:
+        sq_rows = list(csv.DictReader(open(one(sq_dir, "*counter_collection.csv"))))
+        end_sq = tf_end([(int(r["Dispatch_Id"]), r["Kernel_Name"]) for r in sq_rows])
+        for r in sq_rows:
+            if "tpcca" not in r["Kernel_Name"] or int(r["Dispatch_Id"]) > end_sq:
                 continue
             d = per_k.setdefault(short(r["Kernel_Name"]), {})
             d.setdefault(int(r["Dispatch_Id"]), {}).setdefault(r["Counter_Name"], 0.0)
@@ -400,7 +409,7 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
                "|---|---|---|---|---|---|---|---|"]
         rows_sq = []
         for k, d in per_k.items():
-            ds = [d[x] for x in sorted(d)[:tf_n]]
+            ds = [d[x] for x in sorted(d)]
             avg = {c: float(np.mean([x.get(c, 0.0) for x in ds])) for c in ds[0]}
             w = max(1.0, avg.get("SQ_WAVES", 1.0))
             rows_sq.append((tf_tot.get(k, 0.0), k, w, avg))

@@ -33,9 +33,11 @@ def bucket(n_clusters: int, n_units: int) -> str:
 
 
 def device_name() -> str:
+    """Cache key of the device: its GPU architecture (the marketing name can
+    differ between environments on the same hardware)."""
     try:
         import torch
-        return torch.cuda.get_device_name(0)
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     except Exception:  # plumbing only
         return "unknown"
 
