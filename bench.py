@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--summarize-profile", nargs=4, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "COMMAND"),
                     help="write the profiles/ summaries from rocprofv3 outputs of --profile runs")
     ap.add_argument("--sq-dir", default=None, help="with --summarize-profile: an SQ counter pass to add")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="run the random-access microbenchmark and write its summary under profiles/")
     return ap.parse_args()
 
 
@@ -71,6 +73,9 @@ def main():
     args = parse()
     if args.summarize_profile:
         summarize_profile(*args.summarize_profile, sq_dir=args.sq_dir)
+        return
+    if args.ceilings:
+        ceilings()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this tracker runs on one GPU; multi-GPU runs are not part of this build "
@@ -423,6 +428,31 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
     with open(path, "w") as f:
         f.write("\n".join(md) + "\n")
     print(f"wrote {path} and {TRAFFIC_FILE}")
+
+
+def ceilings():
+    """Random-access ceilings of the GPU (paper_1709_00618_amd/membench, built
+    by build()): the rates that bound the fit and the selection."""
+    import subprocess
+
+    exe = os.path.join(ROOT, "paper_1709_00618_amd", "membench")
+    if not os.path.exists(exe):
+        sys.exit("bench.py --ceilings: paper_1709_00618_amd/membench is not built (run __graft_entry__.build())")
+    out = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, timeout=300)
+    text = out.stdout.decode(errors="replace")
+    print(text, end="", flush=True)
+    if out.returncode != 0:
+        sys.exit(out.returncode)
+    md = ["# Random-access ceilings of one MI355X", "",
+          "Command (repository root on the GPU box): `python3 bench.py --ceilings` (runs "
+          "`paper_1709_00618_amd/membench`, built from `paper_1709_00618_amd/csrc/membench.hip` by "
+          "`__graft_entry__.build()`).", "",
+          "256 x 32 blocks of 256 threads; random addresses over a 2 GiB table (atomics: 256 MiB); "
+          "one warm launch, the rate of 5 timed launches.", "", "```", text.rstrip(), "```", ""]
+    path = os.path.join(ROOT, "profiles", "memory_ceilings_random_access.md")
+    with open(path, "w") as f:
+        f.write("\n".join(md))
+    print(f"wrote {path}")
 
 
 def cpu_baseline(ev, rx, seconds):

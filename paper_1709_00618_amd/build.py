@@ -57,7 +57,25 @@ def build(verbose: bool = False) -> str:
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_membench(verbose)
     return LIB
+
+
+MEMBENCH = os.path.join(HERE, "membench")
+
+
+def build_membench(verbose: bool = False) -> str:
+    """The random-access ceilings microbenchmark (bench.py --ceilings)."""
+    tmp = MEMBENCH + ".tmp"
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", os.path.join(CSRC, "membench.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if out.returncode != 0:
+        raise RuntimeError("hipcc failed on membench.hip:\n" + out.stdout.decode(errors="replace"))
+    os.replace(tmp, MEMBENCH)
+    return MEMBENCH
 
 
 if __name__ == "__main__":
