@@ -25,6 +25,7 @@ SPACE = {
     "fit_pool": [64, 128],
     "fit_min_waves": [0, 4],
     "fit_blocks_per_cu": [0, 6],
+    "link_stage": [0, 1],
 }
 
 
@@ -139,5 +140,5 @@ def tuned(ctx, cl, row, units, n_clusters, device=True, log=None, retune=False, 
 
 
 def _default(table):
-    d = {"fit_pool": 64, "fit_min_waves": 0, "fit_blocks_per_cu": 0}
+    d = {"fit_pool": 64, "fit_min_waves": 0, "fit_blocks_per_cu": 0, "link_stage": 0}
     return d if any(k == d for _, k in table) else None

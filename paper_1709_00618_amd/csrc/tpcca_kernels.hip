@@ -477,8 +477,8 @@ __device__ __forceinline__ int row_of(const RowTab *t, int R, int g) {
 // fall back to global memory less often, smaller ones let more blocks share
 // a CU's LDS.
 template <int kV> struct LinkCaps;
-template <> struct LinkCaps<0> { static constexpr int nbr = 1536, bins = 1024, keep = 8; };
-template <> struct LinkCaps<1> { static constexpr int nbr = 768, bins = 512, keep = 4; };
+template <> struct LinkCaps<0> { static constexpr int nbr = 768, bins = 512, keep = 8; };
+template <> struct LinkCaps<1> { static constexpr int nbr = 1536, bins = 1024, keep = 8; };
 template <> struct LinkCaps<2> { static constexpr int nbr = 512, bins = 256, keep = 4; };
 
 // Candidates inside the window are first collected per side (up to kKeep
