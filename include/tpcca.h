@@ -259,6 +259,9 @@ typedef struct {
                                 taken band by band, the others stay unit by unit; 0: all */
 } tpcca_tuning_t;
 int tpcca_set_tuning(tpcca_ctx_t *ctx, const tpcca_tuning_t *t);
+/* The schedule a new context starts with (pool 64, claims in the fit,
+   every other knob 0). */
+void tpcca_tuning_default(tpcca_tuning_t *t);
 int tpcca_get_tuning(tpcca_ctx_t *ctx, tpcca_tuning_t *t);
 
 /* Error text of a status code, and the last HIP/runtime message of ctx. */
@@ -334,6 +337,10 @@ int tpcca_server_stats(tpcca_server_t *srv, tpcca_stats_t *st);
    "" if none; the pointer stays valid until the calling thread's next call. */
 const char *tpcca_server_last_error(tpcca_server_t *srv);
 int tpcca_server_reset_stats(tpcca_server_t *srv);
+/* Launch schedule of every lane's context (tpcca_set_tuning), applied by
+   each lane from its next batch on; results do not depend on it.  EINVAL
+   for knobs out of range. */
+int tpcca_server_set_tuning(tpcca_server_t *srv, const tpcca_tuning_t *t);
 /* Stop accepting, finish in-flight work, free everything. */
 int tpcca_server_destroy(tpcca_server_t *srv);
 

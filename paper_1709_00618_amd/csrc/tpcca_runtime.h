@@ -13,4 +13,6 @@ size_t ctx_allocated(tpcca_ctx_t *c);
 // stream and context set-up) and by graph capture, so that no capture on
 // one thread meets such a call from another.
 std::recursive_mutex &device_ops_lock();
+// The knob ranges tpcca_set_tuning accepts (n_rows bounds the row bands).
+bool tuning_valid(const tpcca_tuning_t *t, int n_rows);
 }  // namespace tpcca

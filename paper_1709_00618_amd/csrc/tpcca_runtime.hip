@@ -1097,13 +1097,16 @@ int tpcca_device_results(tpcca_ctx_t *c, tpcca_device_results_t *out) {
   return TPCCA_OK;
 }
 
+void tpcca_tuning_default(tpcca_tuning_t *t) {
+  if (!t) return;
+  *t = tpcca_tuning_t{};
+  t->fit_pool = 64;
+  t->fit_claims = 1;
+}
+
 int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
   if (!c || !t) return TPCCA_EINVAL;
-  if (t->fit_pool < 0 || t->fit_pool > 4096 || t->fit_blocks_per_cu < 0 || t->grid_hits_per_bin < 0 ||
-      t->link_blocks_per_cu < 0 || t->fit_min_waves < 0 || t->fit_claims < 0 || t->fit_claims > 1 ||
-      t->fit_xcd_slices < 0 || t->fit_xcd_slices > 1 || t->link_stage < 0 || t->link_stage > 2 ||
-      t->fit_long_first < 0 || t->fit_row_bands < 0 || t->fit_row_bands > c->R || t->fit_tail_units < 0)
-    return TPCCA_EINVAL;
+  if (!tpcca::tuning_valid(t, c->R)) return TPCCA_EINVAL;
   // the grid layout of loaded units depends on hits per bin
   if (t->grid_hits_per_bin && !c->units.empty() && t->grid_hits_per_bin != c->P.hits_per_bin)
     return TPCCA_ESTATE;
@@ -1164,5 +1167,12 @@ std::recursive_mutex &device_ops_lock() {
   return mu;
 }
 hipStream_t ctx_stream(tpcca_ctx *c) { return c->stream; }
+bool tuning_valid(const tpcca_tuning_t *t, int n_rows) {
+  return !(t->fit_pool < 0 || t->fit_pool > 4096 || t->fit_blocks_per_cu < 0 || t->grid_hits_per_bin < 0 ||
+           t->link_blocks_per_cu < 0 || t->fit_min_waves < 0 || t->fit_claims < 0 || t->fit_claims > 1 ||
+           t->fit_xcd_slices < 0 || t->fit_xcd_slices > 1 || t->link_stage < 0 || t->link_stage > 2 ||
+           t->fit_long_first < 0 || t->fit_row_bands < 0 || t->fit_row_bands > n_rows ||
+           t->fit_tail_units < 0);
+}
 size_t ctx_allocated(tpcca_ctx *c) { return c->allocated; }
 }  // namespace tpcca

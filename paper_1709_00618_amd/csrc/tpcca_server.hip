@@ -87,6 +87,8 @@ struct tpcca_server {
   int64_t bytes_in_flight = 0;
   int32_t batches = 0;
   int active = 0;
+  tpcca_tuning_t tuning{};  // launch schedule of the lanes' contexts
+  int tuning_gen = 0;       // 0: none set (context defaults)
   double busy_since = 0, busy_total = 0;
   std::vector<double> latencies;
   std::string last_error;  // text of the last failed batch
@@ -100,6 +102,7 @@ void lane_main(tpcca_server *S, int lane) {
   const size_t lane_budget = S->budget / S->n_lanes;
   if (tpcca_create(&S->geo, &S->params, S->device, nullptr, lane_budget, &ctx) != TPCCA_OK) return;
   hipStream_t st = tpcca::ctx_stream(ctx);
+  int tuning_gen = 0;
   float4 *d_cl = nullptr;
   uint8_t *d_row = nullptr;
   int64_t d_cap = 0;
@@ -134,6 +137,23 @@ void lane_main(tpcca_server *S, int lane) {
     }
     int rc = TPCCA_OK;
     std::string fail_text;
+    // a schedule set since this lane's last batch applies from this batch on
+    {
+      tpcca_tuning_t t{};
+      bool apply = false;
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->tuning_gen != tuning_gen) {
+          t = S->tuning;
+          tuning_gen = S->tuning_gen;
+          apply = true;
+        }
+      }
+      if (apply && (tpcca_reset(ctx) != TPCCA_OK || tpcca_set_tuning(ctx, &t) != TPCCA_OK)) {
+        rc = TPCCA_EINVAL;
+        fail_text = std::string("set_tuning: ") + tpcca_last_error(ctx);
+      }
+    }
     // inputs: one device span per batch, unit slices copied from the frames
     if (ncl > d_cap) {
       std::lock_guard<std::recursive_mutex> dlock(tpcca::device_ops_lock());
@@ -181,7 +201,7 @@ void lane_main(tpcca_server *S, int lane) {
       rc = tpcca_run_batch(ctx, &b);
       if (rc != TPCCA_OK) fail_text = std::string("run_batch: ") + tpcca_last_error(ctx);
     } else {
-      fail_text = "input staging";
+      if (fail_text.empty()) fail_text = "input staging";
     }
     tpcca_device_results_t dr{};
     if (rc == TPCCA_OK) {
@@ -442,6 +462,14 @@ int tpcca_server_stats(tpcca_server_t *S, tpcca_stats_t *st) {
   double m = 0;
   for (double v : S->latencies) m += v;
   st->mean_ms = S->latencies.empty() ? 0 : m / S->latencies.size() * 1e3;
+  return TPCCA_OK;
+}
+
+int tpcca_server_set_tuning(tpcca_server_t *S, const tpcca_tuning_t *t) {
+  if (!S || !t || !tpcca::tuning_valid(t, S->geo.n_rows)) return TPCCA_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->tuning = *t;
+  ++S->tuning_gen;
   return TPCCA_OK;
 }
 

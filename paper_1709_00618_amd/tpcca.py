@@ -108,7 +108,8 @@ SYMBOLS = (
     "tpcca_server_submit", "tpcca_server_poll", "tpcca_server_wait", "tpcca_server_release",
     "tpcca_server_stats", "tpcca_server_reset_stats", "tpcca_server_destroy", "tpcca_now",
     "tpcca_server_last_error",
-    "tpcca_work_stats", "tpcca_set_tuning", "tpcca_get_tuning",
+    "tpcca_work_stats", "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_server_set_tuning",
+    "tpcca_tuning_default",
 )
 
 _lib = None
@@ -162,6 +163,8 @@ def lib():
         "tpcca_now": (ctypes.c_double, []),
         "tpcca_work_stats": (c_i32, [c_vp, ctypes.POINTER(WorkStats)]),
         "tpcca_set_tuning": (c_i32, [c_vp, ctypes.POINTER(Tuning)]),
+        "tpcca_server_set_tuning": (c_i32, [c_vp, ctypes.POINTER(Tuning)]),
+        "tpcca_tuning_default": (None, [ctypes.POINTER(Tuning)]),
         "tpcca_get_tuning": (c_i32, [c_vp, ctypes.POINTER(Tuning)]),
     }
     missing = [n for n in SYMBOLS if not hasattr(L, n)]

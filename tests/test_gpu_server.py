@@ -127,3 +127,21 @@ def test_large_frame_sliced_across_lane_batches(mods, row_x):
         assert got[u][0].tobytes() == tracks[t0:t0 + nt].tobytes()
         assert np.array_equal(got[u][1], hits[h0:h0 + nh])
         assert np.array_equal(got[u][2], asg[c0:c0 + n])
+
+
+def test_tuned_lanes_give_the_same_results(mods, frames, row_x):
+    """A schedule set on the server (applied by every lane from its next
+    batch) changes no result; knobs out of range are refused."""
+    tpcca, serving = mods
+    with serving.Server(row_x, n_streams=2, budget_bytes=8 << 30) as srv:
+        base = _results(serving, srv, frames[:2], pinned=True)
+        srv.set_tuning(fit_pool=128, fit_blocks_per_cu=6, link_stage=1, fit_min_waves=4)
+        print("tuned lanes", flush=True)
+        tuned = _results(serving, srv, frames[:2], pinned=True)
+        with pytest.raises(tpcca.TpccaError):
+            srv.set_tuning(link_stage=7)
+        assert srv.last_error() == ""
+    for a, b in zip(base, tuned):
+        for (ta, ha, aa), (tb, hb, ab) in zip(a, b):
+            assert ta.tobytes() == tb.tobytes()
+            assert np.array_equal(ha, hb) and np.array_equal(aa, ab)
