@@ -111,6 +111,38 @@ def test_dense_rows_time_frame(tpcca, torch_cuda, row_x):
             _parity.compare_batch(units_r, tracks, hits, asg, b, refs)
 
 
+def test_dense_unit_with_an_overfull_row(tpcca, torch_cuda, row_x):
+    """A dense unit (mean row above 1024 hits) with one pad row holding more
+    hits than the LDS-staged row sort takes (8192): that row takes the
+    scatter path inside the same kernel; the result is the oracle's."""
+    torch = torch_cuda
+    tf = tpcgen.timeframe(seed=4, n_events=32)
+    cl, row, slot, sec, _ = tf.unit(5)
+    r_full = 80
+    base = cl[row == r_full]
+    rng = np.random.default_rng(4)
+    extra = np.repeat(base, 9000 // base.shape[0] + 1, axis=0)[:9000].copy()
+    extra[:, 1] += rng.uniform(-3.0, 3.0, extra.shape[0]).astype(np.float32)  # y
+    extra[:, 2] += rng.uniform(-3.0, 3.0, extra.shape[0]).astype(np.float32)  # z
+    cl2 = np.concatenate([cl, extra]).astype(np.float32)
+    row2 = np.concatenate([row, np.full(extra.shape[0], r_full, np.uint8)])
+    perm = rng.permutation(cl2.shape[0])
+    cl2, row2 = np.ascontiguousarray(cl2[perm]), np.ascontiguousarray(row2[perm])
+    assert (row2 == r_full).sum() > 8192 and cl2.shape[0] / (row_x.shape[0] + 1) >= 1024
+    units = np.array([(0, cl2.shape[0], slot, sec)], np.int64)
+    b = tpcgen.Batch(cl2, row2, units)
+    print(f"overfull row: {cl2.shape[0]} clusters, {(row2 == r_full).sum()} in row {r_full}", flush=True)
+    refs = _parity.oracle_units(b, row_x)
+    dcl, drow = _dev(torch, cl2), _dev(torch, row2)
+    torch.cuda.synchronize()
+    with tpcca.Context(row_x) as ctx:
+        ctx.run_batch(dcl, drow, units, device=True, graph=True)
+        units_r, tracks, hits, asg = ctx.get_batch_results()
+        _parity.compare_batch(units_r, tracks, hits, asg, b, refs)
+        up, dn = ctx.get_links(slot, sec, cl2.shape[0], which=1)
+    assert np.array_equal(up, refs[0].up) and np.array_equal(dn, refs[0].dn)
+
+
 def test_graph_replays_track_changing_batches(tpcca, torch_cuda, row_x):
     """One context, graph replays of different batches, host work between."""
     torch = torch_cuda
