@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--events", type=int, default=128, help="events per time frame")
-    ap.add_argument("--served-tfs", type=int, default=48, help="time frames per served load level (0: skip)")
+    ap.add_argument("--served-tfs", type=int, default=200, help="time frames per served load level (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3")
@@ -209,6 +209,86 @@ def main():
     log(f"per-event plain: {pe_dt * 1e3:.2f} ms/event, {per_event / 1e9:.3f} G clusters/s")
     pe.close()
 
+    # ------------------------------------------ host-resident bases
+    # inputs in pinned host memory (the library copies them in), every
+    # result (tracks, hits, assignment) copied back into pinned host buffers:
+    # the basis of the served path, for the plain per-event path and for the
+    # batched frame (one in flight)
+    host_res = None
+    if not args.profile:
+        keep = []
+
+        def pinned(n, dtype):
+            dtype = np.dtype(dtype)
+            t = torch.empty(max(1, n) * dtype.itemsize, dtype=torch.uint8, pin_memory=True)
+            keep.append(t)
+            return t.numpy().view(dtype)
+
+        def host_in(b):
+            hc = pinned(b.cl.shape[0] * 4, np.float32).reshape(-1, 4)
+            hc[:] = b.cl
+            hr = pinned(b.row.shape[0], np.uint8)
+            hr[:] = b.row
+            return hc, hr
+
+        def host_out(n_cl, n_units):
+            # accepted tracks own disjoint sets of >= 10 hits
+            return (pinned(n_units, tpcca.UNIT_RESULT_DTYPE), pinned(n_cl // 10 + n_units + 1, tpcca.TRACK_DTYPE),
+                    pinned(n_cl, np.int32), pinned(n_cl, np.int32))
+
+        def timed(step, n):
+            for _ in range(args.warmup):
+                step()
+            t0 = time.perf_counter()
+            for _ in range(n):
+                step()
+            return (time.perf_counter() - t0) / n
+
+        ev_in, ev_out = host_in(ev), host_out(ev.n_clusters, ev.units.shape[0])
+        he = tpcca.Context(rx, device=0)
+        he_dt = timed(lambda: (he.run_batch(ev_in[0], ev_in[1], ev.units, device=False, graph=False),
+                               he.get_batch_results(out=ev_out)), pe_steps)
+        he.close()
+        tf_in, tf_out = host_in(tf), host_out(tf.n_clusters, tf.units.shape[0])
+        hb_dt = timed(lambda: (ctx.run_batch(tf_in[0], tf_in[1], tf.units, device=False, graph=True),
+                               ctx.get_batch_results(out=tf_out)), max(5, args.steps // 2))
+        host_res = {"per_event": {"value": round(ev.n_clusters / he_dt, 1), "ms_per_event": round(he_dt * 1e3, 4)},
+                    "batched": {"value": round(ncl / hb_dt, 1), "ms_per_step": round(hb_dt * 1e3, 4),
+                                "in_flight": 1},
+                    "batched_over_per_event": round((ncl / hb_dt) / (ev.n_clusters / he_dt), 3),
+                    "unit": "clusters/s",
+                    "basis": "pinned host inputs and outputs: H2D + all stages + D2H of tracks, hits, assignment"}
+        log(f"host-resident: per-event {he_dt * 1e3:.2f} ms, batched frame {hb_dt * 1e3:.2f} ms "
+            f"({host_res['batched_over_per_event']}x)")
+        del keep, ev_in, ev_out, tf_in, tf_out
+
+    # ------------------------------------- time against frame size
+    # device-resident, one frame in flight: t = a + b N over frames of
+    # 8 .. 128 events (the paper's linear dependence on the input size)
+    lin = None
+    if not args.profile:
+        pts = []
+        for k in (8, 16, 32, 64):
+            tk = tpcgen.timeframe(seed=0, n_events=k)
+            kcl, krow = torch.from_numpy(tk.cl).cuda(), torch.from_numpy(tk.row).cuda()
+            torch.cuda.synchronize()
+            for _ in range(2):
+                ctx.run_batch(kcl, krow, tk.units, device=True, graph=True)
+                ctx.sync()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                ctx.run_batch(kcl, krow, tk.units, device=True, graph=True)
+                ctx.sync()
+            pts.append((tk.n_clusters, (time.perf_counter() - t0) / 5 * 1e3))
+            del kcl, krow
+        pts.append((ncl, dt * 1e3))
+        xs, ys = np.array([p[0] for p in pts], float), np.array([p[1] for p in pts], float)
+        b_, a_ = np.polyfit(xs, ys, 1)
+        r2 = 1.0 - float(np.sum((ys - (a_ + b_ * xs)) ** 2) / max(1e-30, np.sum((ys - ys.mean()) ** 2)))
+        lin = {"points_clusters_ms": [[int(x), round(y, 4)] for x, y in pts], "a_ms": round(float(a_), 4),
+               "b_ns_per_cluster": round(float(b_) * 1e6, 5), "r2": round(r2, 5)}
+        log(f"time vs size: t = {a_:.3f} ms + {b_ * 1e6:.4f} ns x N (r2 {r2:.4f})")
+
     # ------------------------------------------------------------ served
     served = None
     if args.served_tfs > 0:
@@ -270,6 +350,8 @@ def main():
                                   "kernel per event, device-resident",
                       "value": round(per_event, 1), "unit": "clusters/s", "ms_per_event": round(pe_dt * 1e3, 4)},
         "batched_over_per_event": round(value / per_event, 3),
+        "host_resident": host_res,
+        "linear_scaling": lin,
         "served": served,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roofline,
@@ -478,7 +560,22 @@ def cpu_baseline(ev, rx, seconds):
             if time.perf_counter() - t0 >= seconds:
                 break
     dt = time.perf_counter() - t0
+    # one thread, the 36 sectors in turn
+    t1 = time.perf_counter()
+    for u in units:
+        cl, row, _, _, _ = ev.unit(u)
+        oracle.run_sector(cl, row, rx, precision=32)
+    st_dt = time.perf_counter() - t1
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(done_cl / dt, 1), "unit": "clusters/s", "cores": cores, "kind": "oracle",
+            "single_thread": round(ev.n_clusters / st_dt, 1), "nproc": os.cpu_count(), "cpu_model": model,
             "sample": f"{rounds} pass(es) over the 36 sectors of one central Pb-Pb event "
                       f"({ev.n_clusters} clusters), FP32 oracle, one sector per thread, {dt:.1f} s wall"}
 

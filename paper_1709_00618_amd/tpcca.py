@@ -340,16 +340,24 @@ class Context:
                                         ctypes.byref(nh)), "tpcca_batch_totals", self.h)
         return nu.value, nc.value, nt.value, nh.value
 
-    def get_batch_results(self):
+    def get_batch_results(self, out=None):
+        """(units, tracks, hits, assignment) of the last batch; `out` may hold
+        four preallocated arrays of those dtypes (e.g. views of pinned host
+        memory, for copies at link speed) with room for the results."""
         nu, nc, nt, nh = self.batch_totals()
-        units = np.zeros(nu, UNIT_RESULT_DTYPE)
-        tracks = np.zeros(max(1, nt), TRACK_DTYPE)
-        hits = np.zeros(max(1, nh), np.int32)
-        asg = np.zeros(max(1, nc), np.int32)
+        if out is not None:
+            units, tracks, hits, asg = out
+            assert units.shape[0] >= nu and tracks.shape[0] >= max(1, nt) and hits.shape[0] >= max(1, nh) \
+                and asg.shape[0] >= max(1, nc), "result buffers too small"
+        else:
+            units = np.zeros(nu, UNIT_RESULT_DTYPE)
+            tracks = np.zeros(max(1, nt), TRACK_DTYPE)
+            hits = np.zeros(max(1, nh), np.int32)
+            asg = np.zeros(max(1, nc), np.int32)
         _check(lib().tpcca_get_batch_results(self.h, _p(units), _p(tracks), tracks.shape[0], _p(hits),
                                              hits.shape[0], _p(asg), asg.shape[0]),
                "tpcca_get_batch_results", self.h)
-        return units, tracks[:nt], hits[:nh], asg[:nc]
+        return units[:nu], tracks[:nt], hits[:nh], asg[:nc]
 
     def work_stats(self) -> dict:
         w = WorkStats()
