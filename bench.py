@@ -54,9 +54,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--events", type=int, default=128, help="events per time frame")
-    ap.add_argument("--served-tfs", type=int, default=200, help="time frames per served load level (0: skip)")
+    ap.add_argument("--served-tfs", type=int, default=1000, help="time frames per served load level (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3")
@@ -106,6 +106,26 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 copies of {src.numel() * 4} bytes")
         del src, dst
+
+    # measured copy bandwidth (read + write of a 1 GiB device copy), the
+    # streaming ceiling beside the published 8 TB/s
+    copy_gbs = None
+    if not args.profile:
+        a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        a.fill_(1)
+        bcp = torch.empty_like(a)
+        for _ in range(3):
+            bcp.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            bcp.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2.0 * (1 << 30) * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+        del a, bcp
 
     # ------------------------------------------------------------ inputs
     t = time.time()
@@ -316,7 +336,9 @@ def main():
     roofline_links = {"kernel": "k_links (CA neighbour finding)", "bound": "hbm", "achieved": round(link_gbs, 1),
                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(link_gbs / HBM_PEAK_GBS, 4),
                       "traffic": traffic.get("k_links"), "bytes_per_cluster": LINK_BYTES_PER_CLUSTER,
-                      "ms": round(link_ms, 4)}
+                      "ms": round(link_ms, 4),
+                      "copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
+                      "frac_of_copy": round(link_gbs / copy_gbs, 4) if copy_gbs else None}
 
     # ------------------------------------------------------ cpu baseline
     cpu = None
