@@ -66,6 +66,10 @@ def parse():
     ap.add_argument("--sq-dir", default=None, help="with --summarize-profile: an SQ counter pass to add")
     ap.add_argument("--ceilings", action="store_true",
                     help="run the random-access microbenchmark and write its summary under profiles/")
+    ap.add_argument("--profile-pipelined", action="store_true",
+                    help="short run for rocprofv3: 4 warm-up + 8 time frames with two in flight")
+    ap.add_argument("--summarize-pipelined", nargs=2, metavar=("TRACE_DIR", "COMMAND"),
+                    help="write the overlap summary of a --profile-pipelined kernel trace under profiles/")
     return ap.parse_args()
 
 
@@ -76,6 +80,9 @@ def main():
         return
     if args.ceilings:
         ceilings()
+        return
+    if args.summarize_pipelined:
+        summarize_pipelined(*args.summarize_pipelined)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this tracker runs on one GPU; multi-GPU runs are not part of this build "
@@ -92,6 +99,9 @@ def main():
     torch.cuda.set_device(0)
     rx = tpcgen.row_x()
 
+    if args.profile_pipelined:
+        profile_pipelined(rx)
+        return
     if args.profile:
         args.steps, args.warmup, args.served_tfs = min(args.steps, 3), 1, 0
         args.no_cpu_baseline = True
@@ -534,6 +544,85 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
     with open(path, "w") as f:
         f.write("\n".join(md) + "\n")
     print(f"wrote {path} and {TRAFFIC_FILE}")
+
+
+def profile_pipelined(rx):
+    """Two contexts fed alternately with the time frame (cached schedule):
+    4 warm-up frames, then 8 frames; for a kernel trace of the overlap."""
+    import torch
+
+    import tpcgen
+    from paper_1709_00618_amd import autotune, tpcca
+
+    tf = tpcgen.timeframe(seed=0, n_events=128)
+    dcl, drow = torch.from_numpy(tf.cl).cuda(), torch.from_numpy(tf.row).cuda()
+    torch.cuda.synchronize()
+    entry = autotune.lookup(tf.n_clusters, len(tf.units))
+    ctxs = [tpcca.Context(rx, device=0) for _ in range(2)]
+    for c in ctxs:
+        if entry:
+            c.set_tuning(**entry["knobs"])
+    for i in range(4):
+        ctxs[i % 2].run_batch(dcl, drow, tf.units, device=True, graph=True)
+    for c in ctxs:
+        c.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(8):
+        ctxs[i % 2].run_batch(dcl, drow, tf.units, device=True, graph=True)
+    for c in ctxs:
+        c.sync()
+    log(f"8 frames, two in flight: {(time.perf_counter() - t0) / 8 * 1e3:.2f} ms/frame")
+    for c in ctxs:
+        c.close()
+
+
+def summarize_pipelined(trace_dir, command):
+    """Overlap of the two frames' kernels in a --profile-pipelined trace: the
+    window after the 4 warm-up frames, how long the GPU runs at least one
+    and at least two tracker kernels, and the idle gaps."""
+    import csv
+    import glob
+
+    fs = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    assert fs, f"no kernel trace under {trace_dir}"
+    rows = [r for r in csv.DictReader(open(fs[0])) if "tpcca" in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    outs = [r for r in rows if "k_output" in r["Kernel_Name"]]
+    t_begin = int(outs[3]["End_Timestamp"])
+    win = [r for r in rows if int(r["Start_Timestamp"]) >= t_begin]
+    t_end = max(int(r["End_Timestamp"]) for r in win)
+    ev = sorted([(int(r["Start_Timestamp"]), 1) for r in win] + [(int(r["End_Timestamp"]), -1) for r in win])
+    busy = both = idle = 0
+    cur, last, gaps = 0, ev[0][0], []
+    for t, d in ev:
+        if cur >= 1:
+            busy += t - last
+        if cur >= 2:
+            both += t - last
+        if cur == 0 and t > last:
+            gaps.append(t - last)
+        cur += d
+        last = t
+    span = t_end - t_begin
+    per_q = {}
+    for r in win:
+        per_q.setdefault(r["Queue_Id"], 0)
+        per_q[r["Queue_Id"]] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    md = ["# Overlap of two time frames in flight (128 events, 32.5 M clusters each)", "",
+          "Command (repository root on the GPU box; `$R` = repository root):", "", "```", command, "```", "",
+          "`bench.py --profile-pipelined`: two contexts fed alternately, 4 warm-up frames, then 8 frames "
+          "(the window below starts at the end of the 4th warm-up frame).", "",
+          f"- window: {span / 1e6:.2f} ms for 8 frames = {span / 8e6:.2f} ms per frame",
+          f"- at least one tracker kernel running: {busy / 1e6:.2f} ms ({100 * busy / span:.1f} %)",
+          f"- at least two (both frames) running: {both / 1e6:.2f} ms ({100 * both / span:.1f} %)",
+          f"- idle gaps: {len(gaps)}, total {sum(gaps) / 1e3:.1f} us, largest {max(gaps, default=0) / 1e3:.1f} us",
+          "- kernel time per queue (each frame's kernels run longer when they share the GPU): " +
+          ", ".join(f"queue {q}: {v / 1e6:.2f} ms" for q, v in sorted(per_q.items())), ""]
+    path = os.path.join(ROOT, "profiles", "pipelined_timeframe128_overlap.md")
+    with open(path, "w") as f:
+        f.write("\n".join(md))
+    print(f"wrote {path}")
 
 
 def ceilings():
