@@ -321,17 +321,26 @@ typedef struct {
   double p50_ms, p99_ms, mean_ms; /* latency = end - arrival over completed requests */
 } tpcca_stats_t;
 
+/* A server on `device`: n_streams lanes (1..16), each a worker thread with
+   its own context and an equal share of budget_bytes of device memory (0:
+   64 GiB); at most max_queue (>= 1) frames wait for a lane.  The geometry
+   and parameters are copied.  EINVAL on bad arguments, EDEVICE if the
+   device cannot be selected. */
 int tpcca_server_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int device,
                         size_t budget_bytes, int32_t n_streams, int32_t max_queue,
                         tpcca_server_t **out);
 /* Non-blocking; EBUSY when the queue is full, ENOMEM when one unit alone
    exceeds the budget, EINVAL on bad descriptors. */
 int tpcca_server_submit(tpcca_server_t *srv, const tpcca_timeframe_t *tf, uint64_t *req_id);
+/* Current state of a request (done flag, status, times); ENOTFOUND for an
+   unknown or released id. */
 int tpcca_server_poll(tpcca_server_t *srv, uint64_t req_id, tpcca_result_t *res);
 /* Block until done or timeout_s elapses (returns EBUSY on timeout). */
 int tpcca_server_wait(tpcca_server_t *srv, uint64_t req_id, double timeout_s, tpcca_result_t *res);
 /* Forget a completed request's record. */
 int tpcca_server_release(tpcca_server_t *srv, uint64_t req_id);
+/* Counters since creation or the last reset, and latency percentiles over
+   the requests completed in that time. */
 int tpcca_server_stats(tpcca_server_t *srv, tpcca_stats_t *st);
 /* Text of the last failed batch (lane, size, failing step and HIP error),
    "" if none; the pointer stays valid until the calling thread's next call. */

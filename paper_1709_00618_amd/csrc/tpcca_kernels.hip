@@ -541,7 +541,7 @@ __device__ __noinline__ LinkBest link_all_pairs(const Bufs &B, float2 h, float l
 // many there are.
 template <int kKeep>
 __device__ __forceinline__ int collect_window(const float2 *src, int off, int b, int e, float2 h, float ly,
-                                              float lz, int *keep) {
+                                              float lz, uint16_t *keep) {
   int n = 0;
   int i = b;
   for (; i + 1 < e; i += 2) {
@@ -549,18 +549,18 @@ __device__ __forceinline__ int collect_window(const float2 *src, int off, int b,
     const bool w0 = fabsf(c0.x - h.x) <= ly && fabsf(c0.y - h.y) <= lz;
     const bool w1 = fabsf(c1.x - h.x) <= ly && fabsf(c1.y - h.y) <= lz;
     if (w0) {
-      if (n < kKeep) keep[n * kTile] = i;
+      if (n < kKeep) keep[n * kTile] = (uint16_t)(i - off);
       ++n;
     }
     if (w1) {
-      if (n < kKeep) keep[n * kTile] = i + 1;
+      if (n < kKeep) keep[n * kTile] = (uint16_t)(i + 1 - off);
       ++n;
     }
   }
   if (i < e) {
     const float2 c0 = src[i - off];
     if (fabsf(c0.x - h.x) <= ly && fabsf(c0.y - h.y) <= lz) {
-      if (n < kKeep) keep[n * kTile] = i;
+      if (n < kKeep) keep[n * kTile] = (uint16_t)(i - off);
       ++n;
     }
   }
@@ -573,17 +573,17 @@ template <int kKeep>
 __device__ __forceinline__ LinkBest link_hit_lds(const Bufs &B, float2 h, float luy, float luz, float ldy,
                                                  float ldz, float w, int ub, int ue, int db, int de,
                                                  const float2 *s_up, const float2 *s_dn, int u_off, int d_off,
-                                                 int *keep_u, int *keep_d) {
+                                                 uint16_t *keep_u, uint16_t *keep_d) {
   const int nu = collect_window<kKeep>(s_up, u_off, ub, ue, h, luy, luz, keep_u);
   const int nd = nu > 0 ? collect_window<kKeep>(s_dn, d_off, db, de, h, ldy, ldz, keep_d) : 0;
   if (nu > kKeep || nd > kKeep)
     return link_all_pairs<true>(B, h, luy, luz, ldy, ldz, w, ub, ue, db, de, s_up, s_dn, u_off, d_off);
   LinkBest b{__builtin_inff(), -1, -1};
   for (int a = 0; a < nu && nd > 0; ++a) {
-    const int u = keep_u[a * kTile];
+    const int u = u_off + keep_u[a * kTile];
     const float2 cu = s_up[u - u_off];
     for (int q = 0; q < nd; ++q) {
-      const int d = keep_d[q * kTile];
+      const int d = d_off + keep_d[q * kTile];
       link_pair(B, h, w, cu, s_dn[d - d_off], u, d, b);
     }
   }
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
   __shared__ float2 s_up[kNbrCap], s_dn[kNbrCap];
   __shared__ int32_t s_bup[kBinCap + 1], s_bdn[kBinCap + 1];
   __shared__ int s_red[2 * (kTile / 64)];
-  __shared__ int s_keep[2 * kKeep * kTile];
+  __shared__ uint16_t s_keep[2 * kKeep * kTile];  // staged-range offsets (< kNbrCap)
   const int R = P.n_rows;
   const RunDev &rd = B.runs[run];
   const int ntile = rd.tile1 - rd.tile0;
