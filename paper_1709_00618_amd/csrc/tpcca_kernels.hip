@@ -475,7 +475,8 @@ __device__ __forceinline__ int row_of(const RowTab *t, int R, int g) {
 // L2.
 // Staging capacities come in variants (tuning knob link_stage): larger ones
 // fall back to global memory less often, smaller ones let more blocks share
-// a CU's LDS.
+// a CU's LDS.  Variant 0 takes 22.6 KB of LDS and 72 VGPRs: 7 blocks of 256
+// threads per CU.
 template <int kV> struct LinkCaps;
 template <> struct LinkCaps<0> { static constexpr int nbr = 768, bins = 512, keep = 8; };
 template <> struct LinkCaps<1> { static constexpr int nbr = 1536, bins = 1024, keep = 8; };
@@ -593,8 +594,9 @@ __device__ __forceinline__ LinkBest link_hit_lds(const Bufs &B, float2 h, float 
 template <int kV>
 __global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
   constexpr int kNbrCap = LinkCaps<kV>::nbr, kBinCap = LinkCaps<kV>::bins, kKeep = LinkCaps<kV>::keep;
+  static_assert(kNbrCap < 65536, "bin and keep offsets are 16-bit");
   __shared__ float2 s_up[kNbrCap], s_dn[kNbrCap];
-  __shared__ int32_t s_bup[kBinCap + 1], s_bdn[kBinCap + 1];
+  __shared__ uint16_t s_bup[kBinCap + 1], s_bdn[kBinCap + 1];  // bin starts - ua / - da
   __shared__ int s_red[2 * (kTile / 64)];
   __shared__ uint16_t s_keep[2 * kKeep * kTile];  // staged-range offsets (< kNbrCap)
   const int R = P.n_rows;
@@ -657,8 +659,10 @@ __global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
     if (lds) {
       for (int q = i; q < ue_ - ua; q += blockDim.x) s_up[q] = B.yz[ua + q];
       for (int q = i; q < de_ - da; q += blockDim.x) s_dn[q] = B.yz[da + q];
-      for (int q = i; q <= ubhi - ublo + 1; q += blockDim.x) s_bup[q] = B.binbeg[tu.bin0 + ublo + q];
-      for (int q = i; q <= dbhi - dblo + 1; q += blockDim.x) s_bdn[q] = B.binbeg[td.bin0 + dblo + q];
+      for (int q = i; q <= ubhi - ublo + 1; q += blockDim.x)
+        s_bup[q] = (uint16_t)(B.binbeg[tu.bin0 + ublo + q] - ua);
+      for (int q = i; q <= dbhi - dblo + 1; q += blockDim.x)
+        s_bdn[q] = (uint16_t)(B.binbeg[td.bin0 + dblo + q] - da);
     }
     __syncthreads();
     if (i < cnt) {
@@ -667,8 +671,8 @@ __global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
       const int bd0 = zbin(td, h.y - ldz - pad), bd1 = zbin(td, h.y + ldz + pad);
       LinkBest b;
       if (lds) {
-        const int ub = s_bup[bu0 - ublo], ue = s_bup[bu1 + 1 - ublo];
-        const int db = s_bdn[bd0 - dblo], de = s_bdn[bd1 + 1 - dblo];
+        const int ub = ua + s_bup[bu0 - ublo], ue = ua + s_bup[bu1 + 1 - ublo];
+        const int db = da + s_bdn[bd0 - dblo], de = da + s_bdn[bd1 + 1 - dblo];
         b = link_hit_lds<kKeep>(B, h, luy, luz, ldy, ldz, w, ub, ue, db, de, s_up, s_dn, ua, da, s_keep + i,
                                 s_keep + kKeep * kTile + i);
       } else {
