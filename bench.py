@@ -668,12 +668,20 @@ def ceilings():
     print(text, end="", flush=True)
     if out.returncode != 0:
         sys.exit(out.returncode)
+    write_ceilings(text)
+
+
+def write_ceilings(text):
+    """profiles/memory_ceilings_random_access.md from the output of membench."""
     md = ["# Random-access ceilings of one MI355X", "",
           "Command (repository root on the GPU box): `python3 bench.py --ceilings` (runs "
           "`paper_1709_00618_amd/membench`, built from `paper_1709_00618_amd/csrc/membench.hip` by "
           "`__graft_entry__.build()`).", "",
-          "256 x 32 blocks of 256 threads; random addresses over a 2 GiB table (atomics: 256 MiB); "
-          "one warm launch, the rate of 5 timed launches.", "", "```", text.rstrip(), "```", ""]
+          "256 x 32 blocks of 256 threads; random addresses over the table size in brackets "
+          "(2 GiB where none is given); one warm launch, the rate of 5 timed launches. "
+          "`wg scope`: workgroup-scope atomics, each XCD on a region of its own. The last line "
+          "maps each block of a 8192-block launch to the XCD it ran on (hardware register XCC_ID).",
+          "", "```", text.rstrip(), "```", ""]
     path = os.path.join(ROOT, "profiles", "memory_ceilings_random_access.md")
     with open(path, "w") as f:
         f.write("\n".join(md))

@@ -9,6 +9,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <vector>
 
 namespace {
 
@@ -65,6 +66,29 @@ __global__ void k_amax(T *a, unsigned long long n, int iters) {
   }
 }
 
+// The XCD (XCC) the wave runs on, from the hardware register.
+__device__ __forceinline__ unsigned xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 7u; }
+
+// Each XCD updates its own region of n_per words with workgroup-scope
+// atomics (no other XCD touches the region, so the result is the same as
+// with device-scope atomics): would a claim scheme that keeps each sector's
+// claims on one XCD run its atomics faster?
+template <typename T>
+__global__ void k_amax_xcd(T *a, unsigned long long n_per, int iters) {
+  const unsigned long long tid = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
+  T *r = a + xcc_id() * n_per;
+  unsigned long long x = tid * 0x9E3779B97F4A7C15ull + 3;
+  for (int it = 0; it < iters; ++it) {
+    x = mix(x);
+    __hip_atomic_fetch_max(&r[x % n_per], (T)(x >> 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+// XCD of every block (for the block-to-XCD mapping)
+__global__ void k_xcc(unsigned *o) {
+  if (threadIdx.x == 0) o[blockIdx.x] = xcc_id();
+}
+
 bool ok(hipError_t e, const char *what) {
   if (e == hipSuccess) return true;
   std::fprintf(stderr, "membench: %s: %s\n", what, hipGetErrorString(e));
@@ -107,6 +131,10 @@ int main() {
   good = good && time_it("random 8-B load, buffer, nt", g, [&] { k_gather<2><<<blocks, threads>>>(a64, n64, o64, 64); });
   good = good && time_it("random 8-B load, buffer, sc1", g, [&] { k_gather<16><<<blocks, threads>>>(a64, n64, o64, 64); });
   good = good && time_it("random 8-B load, buffer, sc0 sc1", g, [&] { k_gather<17><<<blocks, threads>>>(a64, n64, o64, 64); });
+  // the same over tables that fit the 256 MB last-level cache (MALL) and L2
+  good = good && time_it("random 8-B load, plain (128 MiB)", g, [&] { k_gather<-1><<<blocks, threads>>>(a64, n64 / 16, o64, 64); });
+  good = good && time_it("random 8-B load, plain (32 MiB)", g, [&] { k_gather<-1><<<blocks, threads>>>(a64, n64 / 64, o64, 64); });
+  good = good && time_it("random 8-B load, plain (2 MiB)", g, [&] { k_gather<-1><<<blocks, threads>>>(a64, n64 / 1024, o64, 64); });
   auto *a32 = static_cast<unsigned int *>(buf);
   const unsigned long long nl = table / 128;
   const double sc = (double)blocks * threads * 16;
@@ -121,6 +149,37 @@ int main() {
                          [&] { k_amax<unsigned int><<<blocks, threads>>>(a32, small / 4, 8); });
   good = good && time_it("random atomicMax, 64-bit (256 MiB)", am,
                          [&] { k_amax<unsigned long long><<<blocks, threads>>>(a64, small / 8, 8); });
+  good = good && time_it("random atomicMax, 32-bit (128 MiB)", am,
+                         [&] { k_amax<unsigned int><<<blocks, threads>>>(a32, small / 8, 8); });
+  good = good && time_it("random atomicMax, 64-bit (128 MiB)", am,
+                         [&] { k_amax<unsigned long long><<<blocks, threads>>>(a64, small / 16, 8); });
+  good = good && time_it("random atomicMax, 32-bit (32 MiB)", am,
+                         [&] { k_amax<unsigned int><<<blocks, threads>>>(a32, small / 32, 8); });
+  good = good && time_it("random atomicMax, 32-bit (2 MiB)", am,
+                         [&] { k_amax<unsigned int><<<blocks, threads>>>(a32, small / 512, 8); });
+  // per-XCD regions (8 x the size) with L2 atomics
+  good = good && time_it("atomicMax 64-bit, wg scope, 2 MiB per XCD", am,
+                         [&] { k_amax_xcd<unsigned long long><<<blocks, threads>>>(a64, (2ull << 20) / 8, 8); });
+  good = good && time_it("atomicMax 64-bit, wg scope, 8 MiB per XCD", am,
+                         [&] { k_amax_xcd<unsigned long long><<<blocks, threads>>>(a64, (8ull << 20) / 8, 8); });
+  good = good && time_it("atomicMax 64-bit, wg scope, 32 MiB per XCD", am,
+                         [&] { k_amax_xcd<unsigned long long><<<blocks, threads>>>(a64, (32ull << 20) / 8, 8); });
+  good = good && time_it("atomicMax 32-bit, wg scope, 32 MiB per XCD", am,
+                         [&] { k_amax_xcd<unsigned int><<<blocks, threads>>>(a32, (32ull << 20) / 4, 8); });
+  if (good) {
+    auto *o32 = static_cast<unsigned *>(out);
+    k_xcc<<<blocks, 64>>>(o32);
+    std::vector<unsigned> ids(blocks);
+    good = ok(hipMemcpy(ids.data(), o32, blocks * sizeof(unsigned), hipMemcpyDeviceToHost), "xcc ids");
+    int cnt[8] = {0}, rr = 0;
+    for (int b = 0; b < blocks; ++b) {
+      ++cnt[ids[b] & 7];
+      rr += (int)(ids[b] == (unsigned)(b & 7));
+    }
+    std::printf("blocks per XCC:");
+    for (int q = 0; q < 8; ++q) std::printf(" %d", cnt[q]);
+    std::printf("; XCC == blockIdx %% 8 for %d of %d\n", rr, blocks);
+  }
   (void)hipFree(buf);
   (void)hipFree(out);
   return good ? 0 : 1;
