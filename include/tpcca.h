@@ -248,10 +248,9 @@ typedef struct {
                                 (default); 0: a claim kernel of its own */
   int32_t fit_xcd_slices;    /* 1: the fit's processing order is cut into one slice per XCD;
                                 0: one shared work counter (default) */
-  int32_t link_stage;        /* LDS staging capacity of the neighbour kernel: 0 default (768
-                                hits, 512 bins), 1 large (1536, 1024: fewer global fallbacks),
-                                2 small (512, 256, shorter candidate lists: more blocks per CU);
-                                EINVAL outside 0..2 */
+  int32_t link_stage;        /* LDS staging capacity of the neighbour kernel: 0 default (1024
+                                hits, 768 bins), 1 large (1536, 1024: fewer global fallbacks),
+                                2 small (768, 512: less LDS per block); EINVAL outside 0..2 */
   int32_t fit_long_first;    /* tracklets whose chain has at least this many hits are fitted
                                 first (shorter fits drain the end of the kernel); 0: off */
   int32_t fit_row_bands;     /* fit order by (start-row band, unit) with this many bands of

@@ -475,17 +475,12 @@ __device__ __forceinline__ int row_of(const RowTab *t, int R, int g) {
 // L2.
 // Staging capacities come in variants (tuning knob link_stage): larger ones
 // fall back to global memory less often, smaller ones let more blocks share
-// a CU's LDS.  Variant 0 takes 22.6 KB of LDS and 72 VGPRs: 7 blocks of 256
-// threads per CU.
+// a CU's LDS.  Variant 0 takes 19.5 KB of LDS and 70 VGPRs: 7 blocks of 256
+// threads per CU (the registers set the limit).
 template <int kV> struct LinkCaps;
-template <> struct LinkCaps<0> { static constexpr int nbr = 768, bins = 512, keep = 8; };
-template <> struct LinkCaps<1> { static constexpr int nbr = 1536, bins = 1024, keep = 8; };
-template <> struct LinkCaps<2> { static constexpr int nbr = 512, bins = 256, keep = 4; };
-
-// Candidates inside the window are first collected per side (up to kKeep
-// each, in LDS), then paired: the pair loop runs over the short lists, so
-// lanes with different candidate counts do not multiply their trip counts.
-// A side with more than kKeep window hits falls back to the full double loop.
+template <> struct LinkCaps<0> { static constexpr int nbr = 1024, bins = 768; };
+template <> struct LinkCaps<1> { static constexpr int nbr = 1536, bins = 1024; };
+template <> struct LinkCaps<2> { static constexpr int nbr = 768, bins = 512; };
 
 template <bool kLds>
 __device__ __forceinline__ float2 cand(const Bufs &B, const float2 *src, int i, int off) {
@@ -537,55 +532,59 @@ __device__ __noinline__ LinkBest link_all_pairs(const Bufs &B, float2 h, float l
   return b;
 }
 
-// Lists (up to kKeep) the staged hits in [b, e) inside the window around h,
-// two candidates per step (independent LDS reads in flight); returns how
-// many there are.
-template <int kKeep>
-__device__ __forceinline__ int collect_window(const float2 *src, int off, int b, int e, float2 h, float ly,
-                                              float lz, uint16_t *keep) {
-  int n = 0;
-  int i = b;
-  for (; i + 1 < e; i += 2) {
-    const float2 c0 = src[i - off], c1 = src[i + 1 - off];
-    const bool w0 = fabsf(c0.x - h.x) <= ly && fabsf(c0.y - h.y) <= lz;
-    const bool w1 = fabsf(c1.x - h.x) <= ly && fabsf(c1.y - h.y) <= lz;
-    if (w0) {
-      if (n < kKeep) keep[n * kTile] = (uint16_t)(i - off);
-      ++n;
-    }
-    if (w1) {
-      if (n < kKeep) keep[n * kTile] = (uint16_t)(i + 1 - off);
-      ++n;
-    }
+// Marks the staged hits in [b, e) (at most kMaxScan of them) that lie inside
+// the window around h: bit j of m[p] stands for hit b + 2j + p.  The loop
+// has no branches: lanes of a wave scan in step, two candidates per step
+// (independent LDS reads in flight), and the bit of each step is the same
+// for every lane.
+struct WinMask {
+  unsigned int m[2];
+};
+
+__device__ __forceinline__ WinMask window_mask(const float2 *src, int off, int b, int e, float2 h, float ly,
+                                               float lz) {
+  WinMask r{{0u, 0u}};
+  for (int k = 0; b + k < e; k += 2) {
+    const int i1 = min(b + k + 1, e - 1);
+    const float2 c0 = src[b + k - off], c1 = src[i1 - off];
+    // bitwise &: every test is evaluated (no short-circuit branches)
+    const bool w0 = (fabsf(c0.x - h.x) <= ly) & (fabsf(c0.y - h.y) <= lz);
+    const bool w1 = (b + k + 1 < e) & (fabsf(c1.x - h.x) <= ly) & (fabsf(c1.y - h.y) <= lz);
+    const unsigned int bit = 1u << (k >> 1);
+    r.m[0] |= w0 ? bit : 0u;
+    r.m[1] |= w1 ? bit : 0u;
   }
-  if (i < e) {
-    const float2 c0 = src[i - off];
-    if (fabsf(c0.x - h.x) <= ly && fabsf(c0.y - h.y) <= lz) {
-      if (n < kKeep) keep[n * kTile] = (uint16_t)(i - off);
-      ++n;
-    }
-  }
-  return n;
+  return r;
 }
 
+// Candidate ranges up to this long take the mask path (two 32-bit masks).
+constexpr int kMaxScan = 64;
+
 // The common path, neighbours staged in LDS: the window hits of each side
-// are listed (up to kKeep), then the short lists are paired.
-template <int kKeep>
+// are marked in a bit mask, then the marked hits are paired (the pair loop
+// runs over the few marked hits only, so lanes with different candidate
+// counts do not multiply their trip counts).  Longer ranges take the full
+// double loop.  Every pair is compared by (chi2, cluster IDs), so the order
+// in which pairs are visited does not change the result.
 __device__ __forceinline__ LinkBest link_hit_lds(const Bufs &B, float2 h, float luy, float luz, float ldy,
                                                  float ldz, float w, int ub, int ue, int db, int de,
-                                                 const float2 *s_up, const float2 *s_dn, int u_off, int d_off,
-                                                 uint16_t *keep_u, uint16_t *keep_d) {
-  const int nu = collect_window<kKeep>(s_up, u_off, ub, ue, h, luy, luz, keep_u);
-  const int nd = nu > 0 ? collect_window<kKeep>(s_dn, d_off, db, de, h, ldy, ldz, keep_d) : 0;
-  if (nu > kKeep || nd > kKeep)
+                                                 const float2 *s_up, const float2 *s_dn, int u_off, int d_off) {
+  if (ue - ub > kMaxScan || de - db > kMaxScan)
     return link_all_pairs<true>(B, h, luy, luz, ldy, ldz, w, ub, ue, db, de, s_up, s_dn, u_off, d_off);
   LinkBest b{__builtin_inff(), -1, -1};
-  for (int a = 0; a < nu && nd > 0; ++a) {
-    const int u = u_off + keep_u[a * kTile];
-    const float2 cu = s_up[u - u_off];
-    for (int q = 0; q < nd; ++q) {
-      const int d = d_off + keep_d[q * kTile];
-      link_pair(B, h, w, cu, s_dn[d - d_off], u, d, b);
+  const WinMask mu = window_mask(s_up, u_off, ub, ue, h, luy, luz);
+  if ((mu.m[0] | mu.m[1]) == 0u) return b;
+  const WinMask md = window_mask(s_dn, d_off, db, de, h, ldy, ldz);
+  for (int pu = 0; pu < 2; ++pu) {
+    for (unsigned int a = mu.m[pu]; a != 0u; a &= a - 1u) {
+      const int u = ub + 2 * __builtin_ctz(a) + pu;
+      const float2 cu = s_up[u - u_off];
+      for (int pd = 0; pd < 2; ++pd) {
+        for (unsigned int q = md.m[pd]; q != 0u; q &= q - 1u) {
+          const int d = db + 2 * __builtin_ctz(q) + pd;
+          link_pair(B, h, w, cu, s_dn[d - d_off], u, d, b);
+        }
+      }
     }
   }
   return b;
@@ -593,12 +592,11 @@ __device__ __forceinline__ LinkBest link_hit_lds(const Bufs &B, float2 h, float 
 
 template <int kV>
 __global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
-  constexpr int kNbrCap = LinkCaps<kV>::nbr, kBinCap = LinkCaps<kV>::bins, kKeep = LinkCaps<kV>::keep;
-  static_assert(kNbrCap < 65536, "bin and keep offsets are 16-bit");
+  constexpr int kNbrCap = LinkCaps<kV>::nbr, kBinCap = LinkCaps<kV>::bins;
+  static_assert(kNbrCap < 65536, "bin offsets are 16-bit");
   __shared__ float2 s_up[kNbrCap], s_dn[kNbrCap];
   __shared__ uint16_t s_bup[kBinCap + 1], s_bdn[kBinCap + 1];  // bin starts - ua / - da
   __shared__ int s_red[2 * (kTile / 64)];
-  __shared__ uint16_t s_keep[2 * kKeep * kTile];  // staged-range offsets (< kNbrCap)
   const int R = P.n_rows;
   const RunDev &rd = B.runs[run];
   const int ntile = rd.tile1 - rd.tile0;
@@ -673,8 +671,7 @@ __global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
       if (lds) {
         const int ub = ua + s_bup[bu0 - ublo], ue = ua + s_bup[bu1 + 1 - ublo];
         const int db = da + s_bdn[bd0 - dblo], de = da + s_bdn[bd1 + 1 - dblo];
-        b = link_hit_lds<kKeep>(B, h, luy, luz, ldy, ldz, w, ub, ue, db, de, s_up, s_dn, ua, da, s_keep + i,
-                                s_keep + kKeep * kTile + i);
+        b = link_hit_lds(B, h, luy, luz, ldy, ldz, w, ub, ue, db, de, s_up, s_dn, ua, da);
       } else {
         const int ub = B.binbeg[tu.bin0 + bu0], ue = B.binbeg[tu.bin0 + bu1 + 1];
         const int db = B.binbeg[td.bin0 + bd0], de = B.binbeg[td.bin0 + bd1 + 1];
