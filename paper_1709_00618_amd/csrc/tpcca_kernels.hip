@@ -535,25 +535,31 @@ __device__ __noinline__ LinkBest link_all_pairs(const Bufs &B, float2 h, float l
 // Marks the staged hits in [b, e) (at most kMaxScan of them) that lie inside
 // the window around h: bit j of m[p] stands for hit b + 2j + p.  The loop
 // has no branches: lanes of a wave scan in step, two candidates per step
-// (independent LDS reads in flight), and the bit of each step is the same
-// for every lane.
+// (one paired LDS read), and the bit of each step is the same for every
+// lane.  The second read of the last step may touch the entry after the
+// range (the staging arrays hold one spare entry); bits past the range are
+// cleared after the loop.
 struct WinMask {
   unsigned int m[2];
 };
+
+__device__ __forceinline__ unsigned int low_bits(int n) { return n >= 32 ? ~0u : (1u << n) - 1u; }
 
 __device__ __forceinline__ WinMask window_mask(const float2 *src, int off, int b, int e, float2 h, float ly,
                                                float lz) {
   WinMask r{{0u, 0u}};
   for (int k = 0; b + k < e; k += 2) {
-    const int i1 = min(b + k + 1, e - 1);
-    const float2 c0 = src[b + k - off], c1 = src[i1 - off];
-    // bitwise &: every test is evaluated (no short-circuit branches)
+    const float2 c0 = src[b + k - off], c1 = src[b + k + 1 - off];
+    // bitwise &: both tests are evaluated (no short-circuit branches)
     const bool w0 = (fabsf(c0.x - h.x) <= ly) & (fabsf(c0.y - h.y) <= lz);
-    const bool w1 = (b + k + 1 < e) & (fabsf(c1.x - h.x) <= ly) & (fabsf(c1.y - h.y) <= lz);
+    const bool w1 = (fabsf(c1.x - h.x) <= ly) & (fabsf(c1.y - h.y) <= lz);
     const unsigned int bit = 1u << (k >> 1);
     r.m[0] |= w0 ? bit : 0u;
     r.m[1] |= w1 ? bit : 0u;
   }
+  const int n = e - b;  // candidates b + 2j + p exist for j < (n + 1 - p) / 2
+  r.m[0] &= low_bits((n + 1) >> 1);
+  r.m[1] &= low_bits(n >> 1);
   return r;
 }
 
@@ -594,9 +600,13 @@ template <int kV>
 __global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
   constexpr int kNbrCap = LinkCaps<kV>::nbr, kBinCap = LinkCaps<kV>::bins;
   static_assert(kNbrCap < 65536, "bin offsets are 16-bit");
-  __shared__ float2 s_up[kNbrCap], s_dn[kNbrCap];
+  __shared__ float2 s_up[kNbrCap + 1], s_dn[kNbrCap + 1];  // + the spare entry of window_mask
   __shared__ uint16_t s_bup[kBinCap + 1], s_bdn[kBinCap + 1];  // bin starts - ua / - da
   __shared__ int s_red[2 * (kTile / 64)];
+  // defined contents for the entries after a tile's staged range (read by
+  // window_mask's last step, never used); the tile loop's first barrier
+  // orders this before any read
+  for (int q = threadIdx.x; q <= kNbrCap; q += blockDim.x) s_up[q] = s_dn[q] = make_float2(0.0f, 0.0f);
   const int R = P.n_rows;
   const RunDev &rd = B.runs[run];
   const int ntile = rd.tile1 - rd.tile0;
