@@ -158,15 +158,43 @@ __device__ __forceinline__ void load_chunk(const UnitDev &U, const Chunk &ch, co
   for (int q = 0; q < kPer; ++q) r[q] = valid_row(c4[q], raw[q], s_rx, R);
 }
 
+// Each block counts a contiguous range of chunks: per chunk the row
+// histogram (chunk_hist, read by the scatter pass), and per unit the row
+// counts and z range, accumulated in LDS over the range's chunks of that
+// unit and added to the unit's totals once per unit (atomics on the same
+// few words from every chunk would serialise).
 __global__ __launch_bounds__(kBlock) void k_count(Bufs B, int run, int R) {
   __shared__ int hist[kMaxRows + 1];
+  __shared__ int acc[kMaxRows + 1];
   __shared__ int smin[kBlock / 64], smax[kBlock / 64], serr;
   __shared__ float s_rx[kMaxRows + 1];
   const RunDev &rd = B.runs[run];
   for (int r = threadIdx.x; r < R; r += blockDim.x) s_rx[r] = B.row_x[r];
-  for (int c = rd.c0 + blockIdx.x; c < rd.c1; c += gridDim.x) {
+  for (int r = threadIdx.x; r <= R; r += blockDim.x) acc[r] = 0;
+  const int nch = rd.c1 - rd.c0;
+  const int per = (nch + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int cb = rd.c0 + (int)blockIdx.x * per, ce = min(rd.c1, cb + per);
+  int acc_unit = -1, acc_zmin = 0x7FFFFFFF, acc_zmax = (int)0x80000000;  // block-uniform
+  // adds the accumulated counts and z range of unit acc_unit to its totals
+  auto flush = [&]() {
+    for (int r = threadIdx.x; r <= R; r += blockDim.x) {
+      if (acc[r]) atomicAdd(&B.row_cnt[(int64_t)acc_unit * (R + 1) + r], acc[r]);
+      acc[r] = 0;
+    }
+    if (threadIdx.x == 0 && acc_zmin != 0x7FFFFFFF) {
+      atomicMin(&B.zmm[2 * acc_unit], acc_zmin);
+      atomicMax(&B.zmm[2 * acc_unit + 1], acc_zmax);
+    }
+    acc_zmin = 0x7FFFFFFF;
+    acc_zmax = (int)0x80000000;
+  };
+  for (int c = cb; c < ce; ++c) {
     const Chunk ch = B.chunks[c];
     const UnitDev U = B.units[ch.unit];
+    if (ch.unit != acc_unit) {
+      if (acc_unit >= 0) flush();
+      acc_unit = ch.unit;
+    }
     for (int r = threadIdx.x; r <= R; r += blockDim.x) hist[r] = 0;
     if (threadIdx.x == 0) serr = 0;
     __syncthreads();
@@ -198,23 +226,18 @@ __global__ __launch_bounds__(kBlock) void k_count(Bufs B, int run, int R) {
     }
     if (bad) serr = 1;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int w = 1; w < kBlock / 64; ++w) {
-        smin[0] = min(smin[0], smin[w]);
-        smax[0] = max(smax[0], smax[w]);
-      }
-      if (smin[0] != 0x7FFFFFFF) {
-        atomicMin(&B.zmm[2 * ch.unit], smin[0]);
-        atomicMax(&B.zmm[2 * ch.unit + 1], smax[0]);
-      }
-      if (serr) B.runs[run].err = 1;
+    for (int w = 0; w < kBlock / 64; ++w) {  // every thread: the block's z range
+      acc_zmin = min(acc_zmin, smin[w]);
+      acc_zmax = max(acc_zmax, smax[w]);
     }
+    if (threadIdx.x == 0 && serr) B.runs[run].err = 1;
     for (int r = threadIdx.x; r <= R; r += blockDim.x) {
       B.chunk_hist[(int64_t)c * (R + 1) + r] = hist[r];
-      if (hist[r]) atomicAdd(&B.row_cnt[(int64_t)ch.unit * (R + 1) + r], hist[r]);
+      acc[r] += hist[r];
     }
     __syncthreads();
   }
+  if (acc_unit >= 0) flush();
 }
 
 // Pass 2 (one block per unit): row offsets and z-bin layout of every row.
@@ -1859,7 +1882,7 @@ hipError_t launch_grid(const Bufs &B, const ParamsDev &P, int run, const RunHost
   const int R = P.n_rows;
   const int nch = h.c1 - h.c0, nu = h.u1 - h.u0;
   k_run_reset<<<grid_for((int64_t)nu * (R + 1), 256, 1024), 256, 0, s>>>(B, run, R);
-  if (nch > 0) k_count<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run, R);
+  if (nch > 0) k_count<<<grid_for(nch, 1, 2048), kBlock, 0, s>>>(B, run, R);
   if (nu > 0) k_plan<<<grid_for(nu, 1, 4096), kBlock, 0, s>>>(B, run, R, P.hits_per_bin);
   if (nch > 0) k_rowscatter<<<grid_for((nch + kGroup - 1) / kGroup, 1, 8192), kBlock, 0, s>>>(B, run, R);
   if (nu > 0) {
