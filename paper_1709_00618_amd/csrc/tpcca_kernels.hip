@@ -1640,7 +1640,8 @@ __global__ __launch_bounds__(kBlock) void k_claim(Bufs B, ParamsDev P, int run) 
 // the lengths of four tracklets rather than of sixty-four.
 constexpr int kGrp = 16;
 
-// Count the hits a tracklet won, record which, accept or reject.
+// Count the hits a tracklet won, record which, accept or reject (a tracklet
+// that has already lost too many hits is rejected without reading the rest).
 __global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
   const RunDev &rd = B.runs[run];
   const int R = P.n_rows;
@@ -1670,6 +1671,10 @@ __global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
           if (gl == 0) wm[j0 >> 6] = cur;
           cur = 0;
         }
+        // stop once even winning every remaining hit could not reach the
+        // acceptance bounds (the won mask is read for accepted tracks only)
+        const int most = won + (n - (j0 + kGrp));
+        if (j0 + kGrp < n && (most < P.min_hits || most * 100 < P.own_pct * n)) break;
       }
       if (won >= P.min_hits && won * 100 >= P.own_pct * n)
         v = (1ull << 40) | (unsigned long long)won;
