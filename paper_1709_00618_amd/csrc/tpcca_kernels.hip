@@ -1639,16 +1639,20 @@ __global__ __launch_bounds__(kBlock) void k_claim(Bufs B, ParamsDev P, int run) 
 // the tracklet's hit slots kGrp at a time, so a wave's trip count follows
 // the lengths of four tracklets rather than of sixty-four.
 constexpr int kGrp = 16;
+// the acceptance pass uses narrower groups: a tracklet that loses its first
+// hits is rejected after fewer owner reads
+constexpr int kWonGrp = 8;
 
 // Count the hits a tracklet won, record which, accept or reject (a tracklet
 // that has already lost too many hits is rejected without reading the rest).
+template <int kG>
 __global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
   const RunDev &rd = B.runs[run];
   const int R = P.n_rows;
   const int lane = threadIdx.x & 63;
-  const int gl = lane & (kGrp - 1), g0 = lane & ~(kGrp - 1);
-  const int ng = (gridDim.x * blockDim.x) / kGrp;
-  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / kGrp; i < rd.n_trk; i += ng) {
+  const int gl = lane & (kG - 1), g0 = lane & ~(kG - 1);
+  const int ng = (gridDim.x * blockDim.x) / kG;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / kG; i < rd.n_trk; i += ng) {
     const int t = B.kf_order[rd.trk0 + i];
     const int tl = t - rd.trk0;
     const tpcca_tracklet_t &o = B.trk[t];
@@ -1661,20 +1665,20 @@ __global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
       const int n = o.n_hits;
       unsigned long long cur = 0;
       int won = 0;
-      for (int j0 = 0; j0 < n; j0 += kGrp) {
+      for (int j0 = 0; j0 < n; j0 += kG) {
         const int j = j0 + gl;
         const bool w = j < n && B.owner[slot_hit(hl[j], ucl)] == key;
-        const unsigned int bits = (unsigned int)(__ballot(w) >> g0) & ((1u << kGrp) - 1);
+        const unsigned int bits = (unsigned int)(__ballot(w) >> g0) & ((1u << kG) - 1);
         won += __popc(bits);
         cur |= (unsigned long long)bits << (j0 & 63);
-        if (((j0 + kGrp) & 63) == 0 || j0 + kGrp >= n) {  // a 64-slot word is complete
+        if (((j0 + kG) & 63) == 0 || j0 + kG >= n) {  // a 64-slot word is complete
           if (gl == 0) wm[j0 >> 6] = cur;
           cur = 0;
         }
         // stop once even winning every remaining hit could not reach the
         // acceptance bounds (the won mask is read for accepted tracks only)
-        const int most = won + (n - (j0 + kGrp));
-        if (j0 + kGrp < n && (most < P.min_hits || most * 100 < P.own_pct * n)) break;
+        const int most = won + (n - (j0 + kG));
+        if (j0 + kG < n && (most < P.min_hits || most * 100 < P.own_pct * n)) break;
       }
       if (won >= P.min_hits && won * 100 >= P.own_pct * n)
         v = (1ull << 40) | (unsigned long long)won;
@@ -2021,7 +2025,7 @@ hipError_t launch_select(const Bufs &B, const ParamsDev &P, int run, const RunHo
   const int64_t tiles = (h.trk_cap + kScanTile - 1) / kScanTile;
   if (h.trk_cap > 0) {
     if (!P.kf_claims) k_claim<<<tg, kBlock, 0, s>>>(B, P, run);
-    k_won<<<gg, kBlock, 0, s>>>(B, P, run);
+    k_won<kWonGrp><<<gg, kBlock, 0, s>>>(B, P, run);
     k_acc_sums<<<grid_for(tiles, 1, 8192), kBlock, 0, s>>>(B, run);
   }
   k_acc_tiles<<<1, 1024, 0, s>>>(B, run);
