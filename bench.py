@@ -85,8 +85,8 @@ def main():
         summarize_pipelined(*args.summarize_pipelined)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this tracker runs on one GPU; multi-GPU runs are not part of this build "
-              "(sectors and time frames are independent: see the sharding note in DESIGN.md)",
+        print("bench.py: measures one GPU only (--gpus 1); sectors and time frames are independent "
+              "units, so several GPUs would each run a server of their own on separate frames",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -516,7 +516,7 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
     md = ["# Kernel trace and HBM traffic: batched time frame (128 events, 32.5 M clusters)", "",
-          "Command (repository root on the GPU box; `$R` = repository root):", "", "```", command, "```", "",
+          "Command (run from the repository root; `$R` = repository root):", "", "```", command, "```", "",
           "`bench.py --profile`: a 1 GiB device copy (counter calibration), then 1 warm-up + 3 timed graph "
           "replays of the time frame (the TF dispatches below), then the per-event path (other dispatches).", "",
           "## Durations (kernel trace)", ""] + lines + ["",
@@ -640,7 +640,7 @@ def summarize_pipelined(trace_dir, command):
         per_q.setdefault(r["Queue_Id"], 0)
         per_q[r["Queue_Id"]] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
     md = ["# Overlap of two time frames in flight (128 events, 32.5 M clusters each)", "",
-          "Command (repository root on the GPU box; `$R` = repository root):", "", "```", command, "```", "",
+          "Command (run from the repository root; `$R` = repository root):", "", "```", command, "```", "",
           "`bench.py --profile-pipelined`: two contexts fed alternately, 4 warm-up frames, then 8 frames "
           "(the window below starts at the end of the 4th warm-up frame).", "",
           f"- window: {span / 1e6:.2f} ms for 8 frames = {span / 8e6:.2f} ms per frame",
@@ -674,7 +674,7 @@ def ceilings():
 def write_ceilings(text):
     """profiles/memory_ceilings_random_access.md from the output of membench."""
     md = ["# Random-access ceilings of one MI355X", "",
-          "Command (repository root on the GPU box): `python3 bench.py --ceilings` (runs "
+          "Command (run from the repository root): `python3 bench.py --ceilings` (runs "
           "`paper_1709_00618_amd/membench`, built from `paper_1709_00618_amd/csrc/membench.hip` by "
           "`__graft_entry__.build()`).", "",
           "256 x 32 blocks of 256 threads; random addresses over the table size in brackets "
