@@ -90,6 +90,59 @@ def test_minbias_batch(tpcca, torch_cuda, row_x, graph):
     _parity.compare_batch(units, tracks, hits, asg, b, refs)
 
 
+def _crowded_rows_unit(row_x, n, seed, r=60):
+    """Rows r-1 and r+1 with n hits each at almost the same z (so every hit of
+    row r has all n in its candidate range) spread in y (so only a few lie
+    inside its window), and three hits in row r."""
+    rng = np.random.default_rng(seed)
+    parts, rows = [], []
+    for rr, k in ((r - 1, n), (r, 3), (r + 1, n)):
+        y = rng.uniform(-40.0, 40.0, k).astype(np.float32)
+        if rr == r:
+            y = np.array([0.0, 0.4, -0.3], np.float32)
+        else:
+            y[:3] = rng.uniform(-0.5, 0.5, 3)  # some inside the window
+        z = (10.0 + rng.uniform(-0.05, 0.05, k)).astype(np.float32)
+        c = np.stack([np.full(k, row_x[rr], np.float32), y, z, np.ones(k, np.float32)], axis=1)
+        parts.append(c)
+        rows.append(np.full(k, rr, np.uint8))
+    cl = np.concatenate(parts).astype(np.float32)
+    row = np.concatenate(rows)
+    perm = rng.permutation(cl.shape[0])
+    return np.ascontiguousarray(cl[perm]), np.ascontiguousarray(row[perm])
+
+
+def test_link_candidate_ranges_around_the_mask_limit(tpcca, torch_cuda, row_x):
+    """Candidate ranges of 63, 64 and 65 hits per side (the bit-mask scan
+    takes up to 64, longer ranges take the full double loop) and of 130:
+    links equal the oracle's on both paths."""
+    torch = torch_cuda
+    cls, rows, units, b0 = [], [], [], 0
+    for k, n in enumerate((63, 64, 65, 130)):
+        cl, row = _crowded_rows_unit(row_x, n, seed=20 + k)
+        cls.append(cl)
+        rows.append(row)
+        units.append((b0, cl.shape[0], k, k))
+        b0 += cl.shape[0]
+    cl = np.concatenate(cls)
+    row = np.concatenate(rows)
+    units = np.array(units, np.int64)
+    b = tpcgen.Batch(cl, row, units)
+    refs = _parity.oracle_units(b, row_x)
+    print(f"crowded rows: {cl.shape[0]} clusters in {units.shape[0]} units", flush=True)
+    with tpcca.Context(row_x) as ctx:
+        ctx.run_batch(_dev(torch, cl), _dev(torch, row), units, device=True, graph=False)
+        units_r, tracks, hits, asg = ctx.get_batch_results()
+        _parity.compare_batch(units_r, tracks, hits, asg, b, refs)
+        for u in range(units.shape[0]):
+            slot, sec, n = int(units[u, 2]), int(units[u, 3]), int(units[u, 1])
+            up, dn = ctx.get_links(slot, sec, n, which=0)  # as found by the neighbour kernel
+            assert np.array_equal(up, refs[u].up_raw) and np.array_equal(dn, refs[u].dn_raw), f"unit {u}"
+            assert (up >= 0).sum() == 3, f"unit {u}: each hit of the middle row links"
+            up, dn = ctx.get_links(slot, sec, n, which=1)
+            assert np.array_equal(up, refs[u].up) and np.array_equal(dn, refs[u].dn), f"unit {u}"
+
+
 def test_dense_rows_time_frame(tpcca, torch_cuda, row_x):
     """Three sector units of a 32-event time frame (about 1400 hits per pad
     row, the dense-row sort that stages a row in LDS), graph and eager."""
