@@ -807,14 +807,27 @@ __global__ __launch_bounds__(kBlock) void k_chain(Bufs B, ParamsDev P, int run) 
 // ---------------------------------------------------------------- scans ---
 // Exclusive scan of n tile sums in place (one block); sums[n] = total.
 __global__ __launch_bounds__(1024) void k_scan_tiles(int64_t *sums, int64_t n) {
+  // one pass covers 1024 x kPerT values, kPerT consecutive ones per thread
+  // (loaded together), so that a few block scans cover the whole array
+  constexpr int kPerT = 16;
   __shared__ int64_t lds[1024 / 64 + 1];
   int64_t carry = 0;
-  for (int64_t s = 0; s < n; s += 1024) {
-    const int64_t i = s + threadIdx.x;
-    const int64_t v = i < n ? sums[i] : 0;
+  for (int64_t s = 0; s < n; s += 1024 * kPerT) {
+    const int64_t b = s + (int64_t)threadIdx.x * kPerT;
+    int64_t v[kPerT];
+    int64_t loc = 0;
+#pragma unroll
+    for (int q = 0; q < kPerT; ++q) {
+      v[q] = b + q < n ? sums[b + q] : 0;
+      loc += v[q];
+    }
     int64_t tot;
-    const int64_t ex = block_exclusive_scan<int64_t>(v, lds, &tot);
-    if (i < n) sums[i] = carry + ex;
+    int64_t ex = carry + block_exclusive_scan<int64_t>(loc, lds, &tot);
+#pragma unroll
+    for (int q = 0; q < kPerT; ++q) {
+      if (b + q < n) sums[b + q] = ex;
+      ex += v[q];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) sums[n] = carry;
