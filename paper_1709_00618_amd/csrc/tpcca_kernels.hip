@@ -807,27 +807,42 @@ __global__ __launch_bounds__(kBlock) void k_chain(Bufs B, ParamsDev P, int run) 
 // ---------------------------------------------------------------- scans ---
 // Exclusive scan of n tile sums in place (one block); sums[n] = total.
 __global__ __launch_bounds__(1024) void k_scan_tiles(int64_t *sums, int64_t n) {
-  // one pass covers 1024 x kPerT values, kPerT consecutive ones per thread
-  // (loaded together), so that a few block scans cover the whole array
-  constexpr int kPerT = 16;
+  // one pass covers kSpan values: loaded and stored coalesced through LDS,
+  // scanned kPerT consecutive values per thread (LDS index padded by one
+  // word per 32 against bank conflicts)
+  constexpr int kPerT = 8, kSpan = 1024 * kPerT;
+  __shared__ int64_t buf[kSpan + kSpan / 32];
   __shared__ int64_t lds[1024 / 64 + 1];
+  auto pad = [](int i) { return i + (i >> 5); };
   int64_t carry = 0;
-  for (int64_t s = 0; s < n; s += 1024 * kPerT) {
-    const int64_t b = s + (int64_t)threadIdx.x * kPerT;
+  for (int64_t s = 0; s < n; s += kSpan) {
+#pragma unroll
+    for (int q = 0; q < kPerT; ++q) {
+      const int i = q * 1024 + (int)threadIdx.x;
+      buf[pad(i)] = s + i < n ? sums[s + i] : 0;
+    }
+    __syncthreads();
     int64_t v[kPerT];
     int64_t loc = 0;
 #pragma unroll
     for (int q = 0; q < kPerT; ++q) {
-      v[q] = b + q < n ? sums[b + q] : 0;
+      v[q] = buf[pad((int)threadIdx.x * kPerT + q)];
       loc += v[q];
     }
     int64_t tot;
-    int64_t ex = carry + block_exclusive_scan<int64_t>(loc, lds, &tot);
+    int64_t ex = carry + block_exclusive_scan<int64_t>(loc, lds, &tot);  // ends with a barrier
 #pragma unroll
     for (int q = 0; q < kPerT; ++q) {
-      if (b + q < n) sums[b + q] = ex;
+      buf[pad((int)threadIdx.x * kPerT + q)] = ex;
       ex += v[q];
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPerT; ++q) {
+      const int i = q * 1024 + (int)threadIdx.x;
+      if (s + i < n) sums[s + i] = buf[pad(i)];
+    }
+    __syncthreads();  // the next pass refills buf
     carry += tot;
   }
   if (threadIdx.x == 0) sums[n] = carry;
