@@ -82,7 +82,13 @@ def lib():
         L.tpcref_get_assignment.argtypes = [vp, vp]
         L.tpcref_get_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
         L.tpcref_refit.restype = i32
-        L.tpcref_refit.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, i32, i32, i32, i32, vp]
+        L.tpcref_refit.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, i32, i32, i32, i32, vp, vp]
+        L.tpcref_chi2.restype = i32
+        L.tpcref_chi2.argtypes = [ctypes.POINTER(Params), i32, vp, vp, ctypes.c_double, ctypes.c_double, vp]
+        L.tpcref_search_row.restype = i32
+        L.tpcref_search_row.argtypes = [ctypes.POINTER(Params), i32, vp, vp, vp, i32, i32, vp, vp, ctypes.c_double]
+        L.tpcref_select.restype = i32
+        L.tpcref_select.argtypes = [ctypes.POINTER(Params), i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.tpcref_propagate.restype = i32
         L.tpcref_propagate.argtypes = [ctypes.POINTER(Params), i32, vp, vp, vp, ctypes.c_double]
         L.tpcref_update.restype = i32
@@ -172,16 +178,68 @@ def run_sector(cl: np.ndarray, row: np.ndarray, row_x: np.ndarray, params: Param
                         {"propagations": st.propagations, "tests": st.tests, "updates": st.updates})
 
 
-def refit(cl, row, row_x, hits, k0, n_chain, params=None, precision=64):
-    """Replay one tracklet's fit along its hit list at the given precision."""
+def refit(cl, row, row_x, hits, k0, n_chain, params=None, precision=64, with_margin=False):
+    """Replay one tracklet's fit along its hit list at the given precision.
+    with_margin: also return the smallest margin of the replay's sin phi tests."""
     L = lib()
     params = params or default_params()
     hits = np.ascontiguousarray(hits, np.int32)
     out = np.zeros(1, TRACKLET_DTYPE)
+    mm = np.zeros(1, np.float64)
     rc = L.tpcref_refit(ctypes.byref(params), _ptr(np.ascontiguousarray(row_x, np.float32)),
                         _ptr(np.ascontiguousarray(cl, np.float32)), _ptr(np.ascontiguousarray(row, np.uint8)),
-                        _ptr(hits), hits.shape[0], int(k0), int(n_chain), precision, _ptr(out))
+                        _ptr(hits), hits.shape[0], int(k0), int(n_chain), precision, _ptr(out), _ptr(mm))
+    if with_margin:
+        return rc, out[0], float(mm[0])
     return rc, out[0]
+
+
+def chi2(state, cov, ym, zm, params=None, precision=64):
+    """The 2-D chi^2 of a measurement against a state (the searches' pickup test)."""
+    L = lib()
+    params = params or default_params()
+    s = np.ascontiguousarray(state, np.float64)
+    c = np.ascontiguousarray(cov, np.float64)
+    out = np.zeros(1, np.float64)
+    rc = L.tpcref_chi2(ctypes.byref(params), precision, _ptr(s), _ptr(c), float(ym), float(zm), _ptr(out))
+    return rc, float(out[0])
+
+
+def search_row(cl, row, row_x, r, state, cov, zr=0.0, params=None, precision=32):
+    """The hit the track-following search picks in row r (-1: none)."""
+    L = lib()
+    params = params or default_params()
+    cl = np.ascontiguousarray(cl, np.float32)
+    row = np.ascontiguousarray(row, np.uint8)
+    s = np.ascontiguousarray(state, np.float64)
+    c = np.ascontiguousarray(cov, np.float64)
+    h = L.tpcref_search_row(ctypes.byref(params), precision, _ptr(np.ascontiguousarray(row_x, np.float32)),
+                            _ptr(cl), _ptr(row), cl.shape[0], int(r), _ptr(s), _ptr(c), float(zr))
+    if h == -2:
+        raise ValueError("oracle rejected the input")
+    return h
+
+
+def select(n_clusters, n_hits, chi2_, start_id, status, hit_lists, params=None):
+    """The selection alone: (accepted index per candidate or -1, assignment)."""
+    L = lib()
+    params = params or default_params()
+    T = len(hit_lists)
+    nh = np.ascontiguousarray(n_hits, np.int32)
+    c2 = np.ascontiguousarray(chi2_, np.float32)
+    sid = np.ascontiguousarray(start_id, np.int32)
+    st = np.ascontiguousarray(status, np.int32)
+    hb = np.zeros(T + 1, np.int64)
+    hb[1:] = np.cumsum([len(h) for h in hit_lists])
+    hits = np.ascontiguousarray(np.concatenate([np.asarray(h, np.int32) for h in hit_lists]) if T else
+                                np.zeros(1, np.int32), np.int32)
+    acc = np.zeros(max(T, 1), np.int32)
+    asg = np.zeros(max(n_clusters, 1), np.int32)
+    k = L.tpcref_select(ctypes.byref(params), int(n_clusters), T, _ptr(nh), _ptr(c2), _ptr(sid), _ptr(st),
+                        _ptr(hb), _ptr(hits), _ptr(acc), _ptr(asg))
+    if k < 0:
+        raise ValueError("oracle rejected the candidates")
+    return acc[:T], asg[:n_clusters]
 
 
 def propagate(state, cov, x0, x1, params=None, precision=64):

@@ -261,6 +261,23 @@ struct Sector {
       if (std::fabs(y[h] - yc) <= ly && std::fabs(z[h] - zc) <= lz) fn(h);
     }
   }
+
+  /* The same for a track state whose z is kept relative to zr: the window
+     is |y_h - yc| <= ly and |(z_h - zr) - zc| <= lz.  The bracket is taken
+     around the absolute z in FP64 (a superset), the test in F. */
+  template <typename Fn>
+  void window_rel(int r, F yc, F zr, F zc, F ly, F lz, Fn &&fn) const {
+    const double za = (double)zr + (double)zc;
+    const auto &zv = zs[r];
+    const double pad = 1e-3 + 1e-6 * std::fabs(za) + 1e-3 * (double)lz;
+    const double lo = za - (double)lz - pad, hi = za + (double)lz + pad;
+    auto it = std::lower_bound(zv.begin(), zv.end(), lo,
+                               [](F a, double b) { return (double)a < b; });
+    for (size_t k = (size_t)(it - zv.begin()); k < zv.size() && (double)zv[k] <= hi; ++k) {
+      const int h = ids[r][k];
+      if (std::fabs(y[h] - yc) <= ly && std::fabs((z[h] - zr) - zc) <= lz) fn(h);
+    }
+  }
 };
 
 template <typename F>
@@ -273,7 +290,11 @@ struct Tracklet {
  * CA neighbour finding (Fig. 1a): for a hit in row i (1 <= i <= n_rows - 2)
  * consider every pair (u in row i+1, d in row i-1) inside windows
  * |dy| <= W dx, |dz| <= W dx around the hit.  The pair's deviation from a
- * straight line is measured at x_i: e = (y, z)_h - interpolation of d -> u.
+ * straight line is measured at x_i: e = (y, z)_h - interpolation of d -> u,
+ * evaluated from coordinate differences, e = (h - d) - w (u - d), with one
+ * rounding: in a time frame z' reaches tens of metres (Sec. 5), where the
+ * FP32 spacing of an absolute coordinate is a sizeable part of the
+ * deviations, while differences of nearby hits are exact.
  * The best pair minimises (chi2, id_u, id_d) lexicographically; it becomes
  * the hit's (up, down) links if chi2 <= link_chi2.  Edge rows get no links.
  */
@@ -299,8 +320,8 @@ void find_links(const Sector<F> &S, std::vector<int> &up, std::vector<int> &dn, 
     int bu = -1, bd = -1;
     for (int u : U)
       for (int d : D) {
-        const F ey = yh - std::fma(S.y[u] - S.y[d], w, S.y[d]);
-        const F ez = zh - std::fma(S.z[u] - S.z[d], w, S.z[d]);
+        const F ey = std::fma(-(S.y[u] - S.y[d]), w, yh - S.y[d]);
+        const F ez = std::fma(-(S.z[u] - S.z[d]), w, zh - S.z[d]);
         const F c2 = std::fma(ey, ey, ez * ez);
         bool better = c2 < best || (c2 == best && (u < bu || (u == bu && d < bd)));
         if (better) {
@@ -343,7 +364,7 @@ void clean_links(const std::vector<int> &up, const std::vector<int> &dn, std::ve
 /* Nearest hit to the predicted (y, z) inside nsig predicted sigmas (capped),
    by dy^2 + dz^2 with ties to the lower ID. */
 template <typename F>
-int search_row(const Sector<F> &S, const State<F> &st, int r, Margins &mg) {
+int search_row(const Sector<F> &S, const State<F> &st, F zr, int r, Margins &mg) {
   const auto &P = S.P;
   F wy = P.nsig * std::sqrt(st.C[0] + P.ery);
   F wz = P.nsig * std::sqrt(st.C[2] + P.erz);
@@ -351,9 +372,9 @@ int search_row(const Sector<F> &S, const State<F> &st, int r, Margins &mg) {
   if (wz > P.wmax) wz = P.wmax;
   int best = -1;
   F bd2 = std::numeric_limits<F>::infinity(), second = bd2;
-  S.window(r, st.p[0], st.p[1], wy, wz, [&](int h) {
+  S.window_rel(r, st.p[0], zr, st.p[1], wy, wz, [&](int h) {
     const F dy = S.y[h] - st.p[0];
-    const F dz = S.z[h] - st.p[1];
+    const F dz = (S.z[h] - zr) - st.p[1];
     const F d2 = std::fma(dy, dy, dz * dz);
     if (d2 < bd2 || (d2 == bd2 && h < best)) {
       second = bd2;
@@ -366,14 +387,15 @@ int search_row(const Sector<F> &S, const State<F> &st, int r, Margins &mg) {
   if (best >= 0) {
     if (second < std::numeric_limits<F>::infinity()) mg.note((double)bd2, (double)second);
     mg.note((double)std::fabs(S.y[best] - st.p[0]), (double)wy);
-    mg.note((double)std::fabs(S.z[best] - st.p[1]), (double)wz);
+    mg.note((double)std::fabs((S.z[best] - zr) - st.p[1]), (double)wz);
   }
   return best;
 }
 
 template <typename F>
-void to_out(const State<F> &s, double *p, double *C) {
+void to_out(const State<F> &s, double *p, double *C, F zr = (F)0) {
   for (int k = 0; k < 5; ++k) p[k] = (double)s.p[k];
+  p[1] = (double)(s.p[1] + zr); /* back to the absolute z of the sector frame */
   if (C)
     for (int k = 0; k < 15; ++k) C[k] = (double)s.C[k];
 }
@@ -398,6 +420,11 @@ void to_out(const State<F> &s, double *p, double *C) {
  *  output the state after the last pass-2 update (innermost hit), the pass-2
  *        chi2 and ndf = 2 n_hits - 5; tracklets with fewer than
  *        min_track_hits hits are kept but flagged (status 1).
+ *  z     the state's z is kept relative to zr, the z of the chain's first
+ *        hit: every measurement enters as z_h - zr and the output adds zr
+ *        back.  In a time frame z' spans tens of metres (Sec. 5) and an
+ *        absolute FP32 z would carry rounding errors comparable with the
+ *        fit's z resolution; differences of a track's own hits are exact.
  *  `replay`, when given, lists the hits to use instead of searching: the
  *        pass-1 extra hits and the inward hits, each with its row.
  */
@@ -419,6 +446,8 @@ void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F>
   const int h0 = chain[0], hL = chain[L];
   State<F> st;
   const F one = (F)1;
+  const F zr = S.z[h0];
+  auto zm = [&](int h) { return S.z[h] - zr; };
   {
     const F x0 = S.rx[S.row[h0]], xL = S.rx[S.row[hL]];
     const F dxs = xL - x0;
@@ -427,7 +456,7 @@ void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F>
     const F tz = (S.z[hL] - S.z[h0]) / dxs;
     const F tl = tz * std::sqrt(std::fma(-sn, sn, one));
     st.p[0] = S.y[h0];
-    st.p[1] = S.z[h0];
+    st.p[1] = zm(h0);
     st.p[2] = sn;
     st.p[3] = tl;
     st.p[4] = (F)0;
@@ -446,7 +475,7 @@ void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F>
     ++mg.props;
     if (!propagate(P, st, S.rx[S.row[h]], &mg)) return;
     ++mg.updates;
-    if (!update(P, st, S.y[h], S.z[h], c2)) return;
+    if (!update(P, st, S.y[h], zm(h), c2)) return;
   }
   State<F> saved = st;
   int row_out = S.row[hL];
@@ -456,15 +485,15 @@ void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F>
     for (int r = row_out + 1; r < P.n_rows; ++r) {
       ++mg.props;
       if (!propagate(P, st, S.rx[r], &mg)) break;
-      const int h = search_row(S, st, r, mg);
+      const int h = search_row(S, st, zr, r, mg);
       bool took = false;
       if (h >= 0) {
         F c;
         ++mg.tests;
-        if (chi2_2d(P, st, S.y[h], S.z[h], c)) {
+        if (chi2_2d(P, st, S.y[h], zm(h), c)) {
           mg.note((double)c, (double)P.pick_chi2);
           if (c <= P.pick_chi2) ++mg.updates;
-          if (c <= P.pick_chi2 && update(P, st, S.y[h], S.z[h], c2)) {
+          if (c <= P.pick_chi2 && update(P, st, S.y[h], zm(h), c2)) {
             pass1.push_back(h);
             saved = st;
             row_out = r;
@@ -481,10 +510,10 @@ void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F>
   } else {
     size_t k = 0;
     for (int r = row_out + 1; r < P.n_rows && k < rp->outward.size(); ++r) {
-      if (!propagate(P, st, S.rx[r], nullptr)) return;
+      if (!propagate(P, st, S.rx[r], &mg)) return;
       const int h = rp->outward[k];
       if (S.row[h] == r) {
-        if (!update(P, st, S.y[h], S.z[h], c2)) return;
+        if (!update(P, st, S.y[h], zm(h), c2)) return;
         pass1.push_back(h);
         saved = st;
         row_out = r;
@@ -513,7 +542,7 @@ void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F>
     if (k < n1 - 1) ++mg.props;
     if (k < n1 - 1 && !propagate(P, st, S.rx[S.row[h]], &mg)) return;
     ++mg.updates;
-    if (!update(P, st, S.y[h], S.z[h], c2)) return;
+    if (!update(P, st, S.y[h], zm(h), c2)) return;
     chi2 = chi2 + c2;
   }
   out_state = st;
@@ -523,15 +552,15 @@ void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F>
     for (int r = S.row[h0] - 1; r >= 0; --r) {
       ++mg.props;
       if (!propagate(P, st, S.rx[r], &mg)) break;
-      const int h = search_row(S, st, r, mg);
+      const int h = search_row(S, st, zr, r, mg);
       bool took = false;
       if (h >= 0) {
         F c;
         ++mg.tests;
-        if (chi2_2d(P, st, S.y[h], S.z[h], c)) {
+        if (chi2_2d(P, st, S.y[h], zm(h), c)) {
           mg.note((double)c, (double)P.pick_chi2);
           if (c <= P.pick_chi2) ++mg.updates;
-          if (c <= P.pick_chi2 && update(P, st, S.y[h], S.z[h], c2)) {
+          if (c <= P.pick_chi2 && update(P, st, S.y[h], zm(h), c2)) {
             chi2 = chi2 + c2;
             inward.push_back(h);
             out_state = st;
@@ -548,10 +577,10 @@ void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F>
   } else {
     size_t k = 0;
     for (int r = S.row[h0] - 1; r >= 0 && k < rp->inward.size(); --r) {
-      if (!propagate(P, st, S.rx[r], nullptr)) return;
+      if (!propagate(P, st, S.rx[r], &mg)) return;
       const int h = rp->inward[k];
       if (S.row[h] == r) {
-        if (!update(P, st, S.y[h], S.z[h], c2)) return;
+        if (!update(P, st, S.y[h], zm(h), c2)) return;
         chi2 = chi2 + c2;
         inward.push_back(h);
         out_state = st;
@@ -571,8 +600,8 @@ void fit_tracklet(const Sector<F> &S, const std::vector<int> &chain, Tracklet<F>
   o.x_ref = (double)out_state.x;
   o.x_out = (double)saved.x;
   o.chi2 = (double)chi2;
-  to_out(out_state, o.p, o.cov);
-  to_out(saved, o.p_out, o.cov_out);
+  to_out(out_state, o.p, o.cov, zr);
+  to_out(saved, o.p_out, o.cov_out, zr);
   o.status = o.n_hits < P.min_hits ? 1 : 0;
 }
 
@@ -608,10 +637,8 @@ uint64_t select_key(int n_hits, float chi2, int start_id) {
          (uint64_t)(0xFFFFFFu - (uint32_t)start_id);
 }
 
-template <typename F>
-void select_tracks(const Sector<F> &S, Result &R) {
-  const auto &P = S.P;
-  std::vector<uint64_t> owner(S.n, 0);
+void select_tracks(int min_hits, int own_pct, int n, Result &R) {
+  std::vector<uint64_t> owner(n, 0);
   const int T = (int)R.trk.size();
   auto key = [&](int t) {
     return select_key(R.trk[t].n_hits, (float)R.trk[t].chi2, R.trk[t].start_id);
@@ -620,14 +647,14 @@ void select_tracks(const Sector<F> &S, Result &R) {
     if (R.trk[t].status != 0) continue;
     for (int h : R.trk_hits[t]) owner[h] = std::max(owner[h], key(t));
   }
-  R.assign.assign(S.n, -1);
+  R.assign.assign(n, -1);
   for (int t = 0; t < T; ++t) {
     if (R.trk[t].status != 0) continue;
     std::vector<int> won;
     for (int h : R.trk_hits[t])
       if (owner[h] == key(t)) won.push_back(h);
     const int nw = (int)won.size();
-    if (nw >= P.min_hits && nw * 100 >= P.own_pct * R.trk[t].n_hits) {
+    if (nw >= min_hits && nw * 100 >= own_pct * R.trk[t].n_hits) {
       const int idx = (int)R.acc_index.size();
       R.acc_index.push_back(t);
       for (int h : won) R.assign[h] = idx;
@@ -656,7 +683,7 @@ Result *run(const tpcref_params_t &pp, const float *row_x, const float *cl, cons
     R->trk.push_back(T.t);
     R->trk_hits.push_back(std::move(T.hits));
   }
-  select_tracks(S, *R);
+  select_tracks(P.min_hits, P.own_pct, n, *R);
   return R.release();
 }
 
@@ -670,7 +697,7 @@ void set_state(State<F> &s, const double *p, const double *C, double x) {
 template <typename F>
 int32_t refit_impl(const tpcref_params_t &pp, const float *row_x, const float *cl,
                           const uint8_t *rw, int32_t n, const int32_t *hits, int32_t nh, int32_t k0,
-                          int32_t n_chain, tpcref_tracklet_t *out) {
+                          int32_t n_chain, tpcref_tracklet_t *out, double *min_margin) {
   Par<F> P(pp);
   Sector<F> S(P, row_x, cl, rw, n);
   std::vector<int> chain(hits + k0, hits + k0 + n_chain);
@@ -681,6 +708,7 @@ int32_t refit_impl(const tpcref_params_t &pp, const float *row_x, const float *c
   Margins mg;
   fit_tracklet(S, chain, T, mg, &rp);
   *out = T.t;
+  if (min_margin) *min_margin = mg.min_margin;
   return T.t.status == 2 ? -1 : 0;
 }
 
@@ -813,7 +841,8 @@ void tpcref_get_stats(const void *r, tpcref_stats_t *s) {
 
 int32_t tpcref_refit(const tpcref_params_t *p, const float *row_x, const float *cl,
                      const uint8_t *row, const int32_t *hits, int32_t n_hits, int32_t k0,
-                     int32_t n_chain, int32_t precision, tpcref_tracklet_t *out) {
+                     int32_t n_chain, int32_t precision, tpcref_tracklet_t *out,
+                     double *min_margin) {
   if (!p || !row_x || !cl || !row || !hits || !out || n_chain < 2 || k0 < 0 ||
       k0 + n_chain > n_hits)
     return -1;
@@ -828,10 +857,10 @@ int32_t tpcref_refit(const tpcref_params_t *p, const float *row_x, const float *
   }
   if (precision == 32)
     return refit_impl<float>(*p, row_x, c.data(), r.data(), n_hits, local.data(), n_hits, k0,
-                             n_chain, out);
+                             n_chain, out, min_margin);
   if (precision == 64)
     return refit_impl<double>(*p, row_x, c.data(), r.data(), n_hits, local.data(), n_hits, k0,
-                              n_chain, out);
+                              n_chain, out, min_margin);
   return -1;
 }
 
@@ -853,6 +882,74 @@ int32_t tpcref_propagate(const tpcref_params_t *p, int32_t precision, double *st
   to_out(s, state, cov);
   *x = s.x;
   return ok ? 0 : -1;
+}
+
+int32_t tpcref_chi2(const tpcref_params_t *p, int32_t precision, const double *state,
+                    const double *cov, double ym, double zm, double *chi2) {
+  if (precision == 32) {
+    Par<float> P(*p);
+    State<float> s;
+    set_state(s, state, cov, 0.0);
+    float c = 0;
+    bool ok = chi2_2d(P, s, (float)ym, (float)zm, c);
+    *chi2 = c;
+    return ok ? 0 : -1;
+  }
+  Par<double> P(*p);
+  State<double> s;
+  set_state(s, state, cov, 0.0);
+  double c = 0;
+  bool ok = chi2_2d(P, s, ym, zm, c);
+  *chi2 = c;
+  return ok ? 0 : -1;
+}
+
+int32_t tpcref_search_row(const tpcref_params_t *p, int32_t precision, const float *row_x,
+                          const float *cl, const uint8_t *row, int32_t n, int32_t r,
+                          const double *state, const double *cov, double zr) {
+  if (!valid_input(p, row_x, cl, row, n) || r < 0 || r >= p->n_rows) return -2;
+  if (precision == 32) {
+    Par<float> P(*p);
+    Sector<float> S(P, row_x, cl, row, n);
+    State<float> s;
+    set_state(s, state, cov, (double)row_x[r]);
+    Margins mg;
+    return search_row(S, s, (float)zr, r, mg);
+  }
+  Par<double> P(*p);
+  Sector<double> S(P, row_x, cl, row, n);
+  State<double> s;
+  set_state(s, state, cov, (double)row_x[r]);
+  Margins mg;
+  return search_row(S, s, zr, r, mg);
+}
+
+int32_t tpcref_select(const tpcref_params_t *p, int32_t n_clusters, int32_t n_tracklets,
+                      const int32_t *n_hits, const float *chi2, const int32_t *start_id,
+                      const int32_t *status, const int64_t *hit_begin, const int32_t *hits,
+                      int32_t *accepted, int32_t *assignment) {
+  if (!p || n_clusters < 0 || n_tracklets < 0) return -1;
+  Result R;
+  R.n = n_clusters;
+  for (int32_t t = 0; t < n_tracklets; ++t) {
+    tpcref_tracklet_t o;
+    std::memset(&o, 0, sizeof(o));
+    o.n_hits = n_hits[t];
+    o.chi2 = chi2[t];
+    o.start_id = start_id[t];
+    o.status = status[t];
+    if (hit_begin[t + 1] - hit_begin[t] != n_hits[t]) return -1;
+    std::vector<int> hl(hits + hit_begin[t], hits + hit_begin[t + 1]);
+    for (int h : hl)
+      if (h < 0 || h >= n_clusters) return -1;
+    R.trk.push_back(o);
+    R.trk_hits.push_back(std::move(hl));
+  }
+  select_tracks(p->min_track_hits, p->own_frac_pct, n_clusters, R);
+  for (int32_t t = 0; t < n_tracklets; ++t) accepted[t] = -1;
+  for (size_t k = 0; k < R.acc_index.size(); ++k) accepted[R.acc_index[k]] = (int32_t)k;
+  for (int32_t i = 0; i < n_clusters; ++i) assignment[i] = R.assign[i];
+  return (int32_t)R.acc_index.size();
 }
 
 int32_t tpcref_update(const tpcref_params_t *p, int32_t precision, double *state, double *cov,

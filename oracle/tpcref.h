@@ -99,16 +99,35 @@ void tpcref_get_stats(const void *res, tpcref_stats_t *s);
 /* Replay the fit of one tracklet along a given hit list (ascending rows;
    the chain occupies hits[k0 .. k0 + n_chain - 1] where hits[k0] is the chain
    start; hits before k0 came from the inward extension).  All decisions are
-   taken from the list; only arithmetic is redone at the given precision. */
+   taken from the list; only arithmetic is redone at the given precision.
+   *min_margin (may be NULL) receives the smallest relative margin of the
+   replay's |sin phi| <= max_sinphi tests (a replay that fails on a margin
+   below 1e-6 met a near-tie, not an error). */
 int32_t tpcref_refit(const tpcref_params_t *p, const float *row_x, const float *cl,
                      const uint8_t *row, const int32_t *hits, int32_t n_hits, int32_t k0,
-                     int32_t n_chain, int32_t precision, tpcref_tracklet_t *out);
+                     int32_t n_chain, int32_t precision, tpcref_tracklet_t *out,
+                     double *min_margin);
 
 /* Single steps, for the unit pins.  State p[5], cov[15] in/out, *x in/out. */
 int32_t tpcref_propagate(const tpcref_params_t *p, int32_t precision, double *state,
                          double *cov, double *x, double x1);
 int32_t tpcref_update(const tpcref_params_t *p, int32_t precision, double *state, double *cov,
                       double ym, double zm, double *chi2);
+/* The 2-D chi^2 the track-following searches test a picked hit with. */
+int32_t tpcref_chi2(const tpcref_params_t *p, int32_t precision, const double *state,
+                    const double *cov, double ym, double zm, double *chi2);
+/* The hit the track-following search picks in row r for a state at plane
+   row_x[r] whose z is relative to zr; -1 if none, -2 on bad input. */
+int32_t tpcref_search_row(const tpcref_params_t *p, int32_t precision, const float *row_x,
+                          const float *cl, const uint8_t *row, int32_t n, int32_t r,
+                          const double *state, const double *cov, double zr);
+/* The selection alone on given candidates: accepted[t] = index of the
+   accepted track or -1, assignment[i] = track index or -1.  Returns the
+   number of accepted tracks, -1 on bad input. */
+int32_t tpcref_select(const tpcref_params_t *p, int32_t n_clusters, int32_t n_tracklets,
+                      const int32_t *n_hits, const float *chi2, const int32_t *start_id,
+                      const int32_t *status, const int64_t *hit_begin, const int32_t *hits,
+                      int32_t *accepted, int32_t *assignment);
 
 #ifdef __cplusplus
 }

@@ -517,10 +517,13 @@ struct LinkBest {
 };
 
 // One (u, d) pair against the best so far: smaller chi2, ties by cluster IDs.
+// The deviation is formed from coordinate differences, (h - d) - w (u - d),
+// rounded once: differences of nearby hits are exact, so it keeps its
+// precision at the large z' of a time frame.
 __device__ __forceinline__ void link_pair(const Bufs &B, float2 h, float w, float2 cu, float2 cd, int u, int d,
                                           LinkBest &b) {
-  const float ey = h.x - __builtin_fmaf(cu.x - cd.x, w, cd.x);
-  const float ez = h.y - __builtin_fmaf(cu.y - cd.y, w, cd.y);
+  const float ey = __builtin_fmaf(-(cu.x - cd.x), w, h.x - cd.x);
+  const float ez = __builtin_fmaf(-(cu.y - cd.y), w, h.y - cd.y);
   const float c2 = __builtin_fmaf(ey, ey, ez * ez);
   bool take = c2 < b.c2;
   if (!take && c2 == b.c2 && b.u >= 0) {
@@ -1210,14 +1213,16 @@ __device__ __forceinline__ int slot_row(int32_t v) { return (int)((uint32_t)v >>
 
 // Nearest hit of the row described by t inside the window; its coordinates
 // are returned in bc.
+// The state's z is relative to zr (see k_kf); the bins are looked up around
+// the absolute prediction zr + z with a margin that covers its rounding.
 __device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, const RowTab &t,
-                                         const KState &s, unsigned int &cands, float2 &bc) {
+                                         const KState &s, float zr, unsigned int &cands, float2 &bc) {
   float wy = P.nsig * sqrtf(s.C[0] + P.ery);
   float wz = P.nsig * sqrtf(s.C[2] + P.erz);
   if (wy > P.wmax) wy = P.wmax;
   if (wz > P.wmax) wz = P.wmax;
   int b, e;
-  bin_range(t, B.binbeg, s.p[1], wz, b, e);
+  bin_range(t, B.binbeg, zr + s.p[1], wz, b, e);
   int best = -1;
   float bd2 = __builtin_inff();
   cands += (unsigned int)(e - b);
@@ -1230,9 +1235,9 @@ __device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, cons
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int i = i0 + q;
-      if (!(i < e && fabsf(c[q].x - s.p[0]) <= wy && fabsf(c[q].y - s.p[1]) <= wz)) continue;
+      if (!(i < e && fabsf(c[q].x - s.p[0]) <= wy && fabsf((c[q].y - zr) - s.p[1]) <= wz)) continue;
       const float dy = c[q].x - s.p[0];
-      const float dz = c[q].y - s.p[1];
+      const float dz = (c[q].y - zr) - s.p[1];
       const float d2 = __builtin_fmaf(dy, dy, dz * dz);
       // equal distances (rare) are decided by the lower cluster ID
       if (d2 < bd2 || (d2 == bd2 && B.sid[i] < B.sid[best])) {
@@ -1251,6 +1256,12 @@ __device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, cons
 // with chi2 <= pick_chi2 (stop after max_miss empty rows); pass 2 restarts at
 // the outermost hit with the pass-1 covariance x refit_inflate, refits inward
 // through all pass-1 hits and continues below the chain start.
+//
+// The state's z is kept relative to zr, the z of the chain's first hit:
+// measurements enter as z_hit - zr (exact for a track's own hits) and the
+// outputs add zr back.  Time frames place z' tens of metres from the
+// sector's origin (Sec. 5), where an absolute FP32 z would carry rounding
+// errors comparable with the fit's resolution.
 //
 // The kernel is persistent and written as a per-lane state machine: every
 // loop iteration performs one row step (propagate, search or take the given
@@ -1322,6 +1333,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
   int t = 0, start_id = 0, n_chain = 0, r0 = 0, k = 0, r = 0, miss = 0, n1 = 0, ne = 0;
   int prev = 0;
   int u = 0, ucl = 0;  // the tracklet's unit and its first global cluster index
+  float zr = 0.0f;     // z of the chain's first hit: the origin of the state's z
   // the row positions, staged once per block
   __shared__ float s_rx[kMaxRows + 1];
   for (int i = threadIdx.x; i < R; i += blockDim.x) s_rx[i] = B.row_x[i];
@@ -1419,8 +1431,9 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
             const float sn = ty / sqrtf(__builtin_fmaf(ty, ty, 1.0f));
             const float tz = (hL.y - h0.y) / dxs;
             const float tl2 = tz * sqrtf(__builtin_fmaf(-sn, sn, 1.0f));
+            zr = h0.y;
             st.p[0] = h0.x;
-            st.p[1] = h0.y;
+            st.p[1] = h0.y - zr;
             st.p[2] = sn;
             st.p[3] = tl2;
             st.p[4] = 0.0f;
@@ -1487,16 +1500,17 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
     if (prop) ok = kf_propagate(P, st, s_rx[row]);
     int h = given;
     const bool search = act && ok && given < 0;
-    if (search) h = kf_search(B, P, trow, st, cands, c);
+    if (search) h = kf_search(B, P, trow, st, zr, cands, c);
+    const float zm = c.y - zr;
     bool acc = act && ok && h >= 0;
     tests += __popcll(__ballot(acc && search));
     if (acc && search) {
       float cc2;
-      acc = kf_chi2(P, st, c.x, c.y, cc2) && cc2 <= P.pick_chi2;
+      acc = kf_chi2(P, st, c.x, zm, cc2) && cc2 <= P.pick_chi2;
     }
     float c2 = 0.0f;
     updates += __popcll(__ballot(acc));
-    const bool upd = acc && kf_update(P, st, c.x, c.y, c2);
+    const bool upd = acc && kf_update(P, st, c.x, zm, c2);
     bool fin = false;  // a tracklet fit ended with enough hits: claim them
     // ---- bookkeeping
     if (phase == kChain) {
@@ -1563,6 +1577,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
         tpcca_tracklet_t &o = B.trk[t];
 #pragma unroll
         for (int q = 0; q < 5; ++q) o.p_out[q] = st.p[q] = s_aux[q][tid];
+        o.p_out[1] = st.p[1] + zr;
 #pragma unroll
         for (int q = 0; q < 15; ++q) o.cov_out[q] = st.C[q] = s_aux[5 + q][tid];
         o.x_out = st.x = s_aux[20][tid];
@@ -1589,6 +1604,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
         o.chi2 = chi2;
 #pragma unroll
         for (int q = 0; q < 5; ++q) o.p[q] = s_aux[q][tid];
+        o.p[1] = s_aux[1][tid] + zr;
 #pragma unroll
         for (int q = 0; q < 15; ++q) o.cov[q] = s_aux[5 + q][tid];
         o.status = (n1 + ne) < P.min_hits ? 1 : 0;
