@@ -656,13 +656,13 @@ def summarize_pipelined(trace_dir, command):
 
 
 def ceilings():
-    """Random-access ceilings of the GPU (paper_1709_00618_amd/membench, built
-    by build()): the rates that bound the fit and the selection."""
+    """Random-access ceilings of the GPU (paper_1709_00618_amd/membench, a
+    measurement tool built here with hipcc, not part of the library): the
+    rates that bound the fit and the selection."""
     import subprocess
 
-    exe = os.path.join(ROOT, "paper_1709_00618_amd", "membench")
-    if not os.path.exists(exe):
-        sys.exit("bench.py --ceilings: paper_1709_00618_amd/membench is not built (run __graft_entry__.build())")
+    from paper_1709_00618_amd import build as gpu_build
+    exe = gpu_build.build_membench()
     out = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, timeout=300)
     text = out.stdout.decode(errors="replace")
     print(text, end="", flush=True)

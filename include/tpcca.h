@@ -223,10 +223,12 @@ int tpcca_batch_totals(tpcca_ctx_t *ctx, int32_t *n_units, int64_t *n_clusters, 
    waves (fit_steps / (64 x fit_wave_iterations) is its lane use), and, from
    the GPU's constant clock, the fit kernel's span and the part of it after
    the first wave found no more tracklets to start (the drain), in ns, summed
-   over runs. */
+   over runs; and the batches since the context was created that ran without
+   their graph because its capture failed (TPCCA_BATCH_GRAPH falls back to
+   plain launches; results are the same). */
 typedef struct {
   int64_t clusters, tracklets, tracks, track_hits, fit_steps, fit_candidates, fit_tests, fit_updates,
-      fit_wave_iterations, fit_ns, fit_drain_ns;
+      fit_wave_iterations, fit_ns, fit_drain_ns, graph_fallbacks;
 } tpcca_work_stats_t;
 int tpcca_work_stats(tpcca_ctx_t *ctx, tpcca_work_stats_t *out);
 
@@ -325,7 +327,8 @@ typedef struct {
    its own context and an equal share of budget_bytes of device memory (0:
    64 GiB); at most max_queue (>= 1) frames wait for a lane.  The geometry
    and parameters are copied.  EINVAL on bad arguments, EDEVICE if the
-   device cannot be selected. */
+   device cannot be selected; if a lane cannot create its context, the lanes
+   are stopped and that lane's status (EDEVICE, ENOMEM) is returned. */
 int tpcca_server_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int device,
                         size_t budget_bytes, int32_t n_streams, int32_t max_queue,
                         tpcca_server_t **out);

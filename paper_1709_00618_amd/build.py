@@ -57,7 +57,6 @@ def build(verbose: bool = False) -> str:
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
-    build_membench(verbose)
     return LIB
 
 
@@ -65,7 +64,8 @@ MEMBENCH = os.path.join(HERE, "membench")
 
 
 def build_membench(verbose: bool = False) -> str:
-    """The random-access ceilings microbenchmark (bench.py --ceilings)."""
+    """The random-access ceilings microbenchmark: a measurement tool, not part
+    of the library; built only by bench.py --ceilings."""
     tmp = MEMBENCH + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
            "-packed-fp32-ops", os.path.join(CSRC, "membench.hip"), "-o", tmp]

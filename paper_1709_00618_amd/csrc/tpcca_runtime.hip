@@ -1016,6 +1016,7 @@ int tpcca_work_stats(tpcca_ctx_t *c, tpcca_work_stats_t *out) {
   if (rc != TPCCA_OK) return rc;
   std::memset(out, 0, sizeof(*out));
   out->clusters = c->n_total;
+  out->graph_fallbacks = c->graph_fallbacks;
   for (size_t r = 0; r < c->runs.size(); ++r) {
     RunDev d;
     RCCHK(copy_sync(c, &d, ptr<RunDev>(c->runs_d) + r, sizeof(d), hipMemcpyDeviceToHost));

@@ -92,6 +92,8 @@ struct tpcca_server {
   double busy_since = 0, busy_total = 0;
   std::vector<double> latencies;
   std::string last_error;  // text of the last failed batch
+  int lanes_up = 0, lanes_failed = 0;  // lanes whose context was (not) created
+  int lane_create_status = TPCCA_OK;    // status of the first lane that failed
 };
 
 namespace {
@@ -100,7 +102,18 @@ void lane_main(tpcca_server *S, int lane) {
   hipSetDevice(S->device);
   tpcca_ctx_t *ctx = nullptr;
   const size_t lane_budget = S->budget / S->n_lanes;
-  if (tpcca_create(&S->geo, &S->params, S->device, nullptr, lane_budget, &ctx) != TPCCA_OK) return;
+  const int crc = tpcca_create(&S->geo, &S->params, S->device, nullptr, lane_budget, &ctx);
+  {
+    // server_create waits for every lane's verdict
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (crc == TPCCA_OK) {
+      S->lanes_up++;
+    } else {
+      if (S->lanes_failed++ == 0) S->lane_create_status = crc;
+    }
+  }
+  S->cv_done.notify_all();
+  if (crc != TPCCA_OK) return;
   hipStream_t st = tpcca::ctx_stream(ctx);
   int tuning_gen = 0;
   float4 *d_cl = nullptr;
@@ -157,11 +170,18 @@ void lane_main(tpcca_server *S, int lane) {
     // inputs: one device span per batch, unit slices copied from the frames
     if (ncl > d_cap) {
       std::lock_guard<std::recursive_mutex> dlock(tpcca::device_ops_lock());
-      if (d_cl) hipFree(d_cl);
-      if (d_row) hipFree(d_row);
+      if (d_cl) (void)hipFree(d_cl);
+      if (d_row) (void)hipFree(d_row);
+      d_cl = nullptr;
+      d_row = nullptr;
       d_cap = std::max<int64_t>(ncl, d_cap + d_cap / 2);
       if (hipMalloc(&d_cl, d_cap * sizeof(float4)) != hipSuccess ||
           hipMalloc(&d_row, d_cap) != hipSuccess) {
+        (void)hipGetLastError();
+        if (d_cl) (void)hipFree(d_cl);
+        if (d_row) (void)hipFree(d_row);
+        d_cl = nullptr;
+        d_row = nullptr;
         rc = TPCCA_ENOMEM;
         d_cap = 0;
       }
@@ -352,6 +372,22 @@ int tpcca_server_create(const tpcca_geometry_t *geo, const tpcca_params_t *param
   S->params = *params;
   S->lane_clusters = (int64_t)(S->budget / n_streams) / kBytesPerCluster;
   for (int l = 0; l < n_streams; ++l) S->lanes.emplace_back(lane_main, S, l);
+  int failed = 0, status = TPCCA_OK;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->lanes_up + S->lanes_failed == S->n_lanes; });
+    failed = S->lanes_failed;
+    status = S->lane_create_status;
+  }
+  if (failed) {
+    // a lane without a context would leave its share of requests waiting
+    // forever: stop the lanes that did start and report the first failure
+    S->stop.store(true);
+    S->cv_work.notify_all();
+    for (auto &t : S->lanes) t.join();
+    delete S;
+    return status;
+  }
   *out = S;
   return TPCCA_OK;
 }

@@ -56,7 +56,7 @@ class WorkStats(ctypes.Structure):
     _fields_ = [("clusters", c_i64), ("tracklets", c_i64), ("tracks", c_i64), ("track_hits", c_i64),
                 ("fit_steps", c_i64), ("fit_candidates", c_i64), ("fit_tests", c_i64),
                 ("fit_updates", c_i64), ("fit_wave_iterations", c_i64), ("fit_ns", c_i64),
-                ("fit_drain_ns", c_i64)]
+                ("fit_drain_ns", c_i64), ("graph_fallbacks", c_i64)]
 
 
 class Tuning(ctypes.Structure):

@@ -207,6 +207,8 @@ def test_graph_replays_track_changing_batches(tpcca, torch_cuda, row_x):
             ctx.run_batch(b.cl, b.row, b.units, device=False, graph=True)
             units, tracks, hits, asg = ctx.get_batch_results()
             _parity.compare_batch(units, tracks, hits, asg, b, refs)
+        # every batch ran as its graph, none fell back to plain launches
+        assert ctx.work_stats()["graph_fallbacks"] == 0
 
 
 def test_two_frames_in_flight(tpcca, torch_cuda, row_x):
@@ -229,6 +231,7 @@ def test_two_frames_in_flight(tpcca, torch_cuda, row_x):
                 _parity.compare_batch(units, tracks, hits, asg, frames[k], refs[k])
         c0.sync()
         c1.sync()
+        assert c0.work_stats()["graph_fallbacks"] == 0 and c1.work_stats()["graph_fallbacks"] == 0
 
 
 def test_timed_graph_replays_give_the_same_results(tpcca, row_x):

@@ -145,3 +145,42 @@ def test_tuned_lanes_give_the_same_results(mods, frames, row_x):
         for (ta, ha, aa), (tb, hb, ab) in zip(a, b):
             assert ta.tobytes() == tb.tobytes()
             assert np.array_equal(ha, hb) and np.array_equal(aa, ab)
+
+
+def test_full_queue_returns_ebusy(mods, frames, row_x):
+    """With room for one waiting frame, frames submitted back to back while
+    the lane works are refused with EBUSY (counted as rejected); every
+    admitted frame still completes with the batch path's results."""
+    tpcca, serving = mods
+    t = frames[2]
+    with serving.Server(row_x, n_streams=1, budget_bytes=8 << 30, max_queue=1) as srv:
+        fr = serving.Frame(t.cl, t.row, t.units, pinned=True)
+        admitted, busy = [], 0
+        for _ in range(12):
+            o = serving.Outputs(fr.n_clusters, fr.n_units)
+            try:
+                admitted.append((srv.submit(fr, o), o))
+            except tpcca.TpccaError as e:
+                assert e.status == tpcca.EBUSY
+                busy += 1
+        print(f"admitted {len(admitted)}, refused {busy}", flush=True)
+        assert busy >= 1 and len(admitted) >= 1
+        assert srv.stats().rejected == busy
+        res = []
+        for rid, o in admitted:
+            r = srv.wait(rid, 300)
+            assert r.status == 0 and r.done == 1
+            res.append(serving.unit_results(fr, o))
+            srv.release(rid)
+    with tpcca.Context(row_x) as ctx:
+        ctx.run_batch(t.cl, t.row, t.units, graph=True)
+        units, tracks, hits, asg = ctx.get_batch_results()
+    for got in res:
+        for u in range(t.units.shape[0]):
+            ur = units[u]
+            t0, nt = int(ur["track_begin"]), int(ur["n_tracks"])
+            h0, nh = int(ur["hit_begin"]), int(ur["n_track_hits"])
+            c0, n = int(ur["cluster_begin"]), int(t.units[u, 1])
+            assert got[u][0].tobytes() == tracks[t0:t0 + nt].tobytes()
+            assert np.array_equal(got[u][1], hits[h0:h0 + nh])
+            assert np.array_equal(got[u][2], asg[c0:c0 + n])
