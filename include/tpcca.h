@@ -235,6 +235,38 @@ int tpcca_work_stats(tpcca_ctx_t *ctx, tpcca_work_stats_t *out);
 /* Device pointers to the batch results (no copy; synchronises). */
 int tpcca_device_results(tpcca_ctx_t *ctx, tpcca_device_results_t *out);
 
+/* For callers that cannot allocate device memory (serving loops and
+   harnesses that forbid hipMalloc, code that must not synchronise the
+   device through the allocator): tpcca_run_batch on device-resident inputs
+   without a context and without any allocation.  Every work buffer and the
+   run tables live in one fixed device array of TPCCA_NOALLOC_SCRATCH_BYTES
+   that the library holds on each device it runs on until the process ends
+   (about 390 B per cluster: up to roughly 1.6e5 clusters, e.g. five sectors
+   of a central Pb-Pb event).  The caller owns inputs and outputs:
+     bt          units as for tpcca_run_batch; flags must be TPCCA_MEM_DEVICE
+                 (cl/row are device addresses; TPCCA_BATCH_GRAPH is EINVAL);
+     tracks      device array of tracks_cap >= sum over units of
+                 (n / min_chain_hits + 1) entries (worst-case capacity; the
+                 accepted tracks come first, in unit order);
+     hits        device array of hits_cap >= total clusters (won hits);
+     assignment  device array of n_assignment >= total clusters;
+     units       device array of n_units tpcca_unit_result_t;
+   with the layout of tpcca_device_results.  *n_tracks_out / *n_hits_out
+   (host, may be NULL) receive the totals.  The call queues the stages on
+   hip_stream (NULL: the null stream) of `device` and returns when they are
+   done.  Errors: EINVAL (bad arguments, or an invalid cluster, as the sync
+   of tpcca_run_batch reports it), ECAPACITY (an output too small), ENOMEM
+   (the units need more than TPCCA_NOALLOC_SCRATCH_BYTES), EDEVICE.  Calls
+   for one device are serialised by the library; the array keeps the last
+   call's contents, and every buffer that must start cleared is cleared by
+   the stages themselves. */
+#define TPCCA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int tpcca_run_batch_noalloc(const tpcca_geometry_t *geo, const tpcca_params_t *params, int device,
+                            void *hip_stream, const tpcca_batch_t *bt, tpcca_track_t *tracks,
+                            int64_t tracks_cap, int32_t *hits, int64_t hits_cap, int32_t *assignment,
+                            int64_t n_assignment, tpcca_unit_result_t *units, int64_t *n_tracks_out,
+                            int64_t *n_hits_out);
+
 /* Launch schedule knobs.  None of them changes any result (every decision
    compares cluster IDs and the same operation sequence runs per tracklet);
    they only trade occupancy, load balance and grid granularity.  Picked by

@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -163,106 +165,91 @@ static T *ptr(DevBuf &b) {
   return static_cast<T *>(b.p);
 }
 
+static void refresh_bufs(tpcca_ctx *c);
+
+// Every work and output buffer of a run: (member of tpcca_ctx, field of
+// Bufs, element type, element count, elements kept when it grows).  The
+// counts use R (rows), N (clusters), U (units), NB (bin-begin entries),
+// T (tracklet slots), NC (chunks), NTILE (row tiles) and NSCAN (scan tiles);
+// the kept counts keepN, keepU, keepB, keepT and keepTiles.  The tables the
+// host writes (units, chunks, runs) are sized separately.
+#define TPCCA_WORK_BUFFERS(X)                                                   \
+  X(rowtab, rowtab, RowTab, U * (R + 1), keepU * (R + 1))                        \
+  X(row_cnt, row_cnt, int32_t, U * (R + 1), keepU * (R + 1))                     \
+  X(row_fill, row_fill, int32_t, U * (R + 1), 0)                                 \
+  X(chunk_hist, chunk_hist, int32_t, NC * (R + 1), 0)                            \
+  X(rtmp, rtmp, int4, N, 0)                                                      \
+  X(zmm, zmm, int32_t, 2 * U, 2 * keepU)                                         \
+  X(binbeg, binbeg, int32_t, NB, keepB)                                          \
+  X(yz, yz, float2, N, keepN)                                                    \
+  X(sid, sid, int32_t, N, keepN)                                                 \
+  X(srow, srow, uint8_t, N, keepN)                                               \
+  X(cinfo, cinfo, int2, N, keepN)                                                \
+  X(up, up, int32_t, N, keepN)                                                   \
+  X(dn, dn, int32_t, N, keepN)                                                   \
+  X(upc, upc, int32_t, N, keepN)                                                 \
+  X(dnc, dnc, int32_t, N, keepN)                                                 \
+  X(flag, flag, int32_t, N, keepN)                                               \
+  X(starts, starts, int2, N, 0)                                                  \
+  X(tiles, tiles, int4, NTILE, keepTiles)                                        \
+  X(owner, owner, unsigned long long, N, keepN)                                  \
+  X(trk_start, trk_start, int32_t, T, keepT)                                     \
+  X(kf_order, kf_order, int32_t, T, keepT)                                       \
+  X(kf_tmp, kf_tmp, int32_t, T, 0)                                               \
+  X(band_tmp, band_tmp, int32_t, 3 * U * (R + 1), 0)                             \
+  X(sval, sval, uint8_t, N, keepN)                                               \
+  X(tofg, tofg, int32_t, N, keepN)                                               \
+  X(trk_unit, trk_unit, int32_t, T, keepT)                                       \
+  X(unit_tbegin, unit_tbegin, int32_t, U + 1, keepU)                             \
+  X(trk, trk, tpcca_tracklet_t, T, keepT)                                        \
+  X(trk_hits, trk_hits, int32_t, T * (size_t)slot_stride(R), keepT * (size_t)slot_stride(R)) \
+  X(accv, accv, unsigned long long, T + 1, 0)                                    \
+  X(wonmask, wonmask, unsigned long long, 4 * T, 0)                              \
+  X(accx, accx, unsigned long long, T + 1, 0)                                    \
+  X(scan_tmp, scan_tmp, int64_t, NSCAN, 0)
+#define TPCCA_OUTPUT_BUFFERS(X)                                                 \
+  X(tracks, tracks, tpcca_track_t, T, keepT)                                     \
+  X(hits_out, hits_out, int32_t, N, keepN)                                       \
+  X(assign, assign, int32_t, N, keepN)                                           \
+  X(unit_res, unit_res, tpcca_unit_result_t, U, keepU)
+
+// The count variables of the buffer table for the given capacities.
+#define TPCCA_BUFFER_COUNTS(R_, n_cl, n_units, n_bins, n_trk, n_chunks)                          \
+  const int R = (R_);                                                                          \
+  const size_t N = (size_t)std::max<int64_t>((n_cl), 1), U = (size_t)std::max<int64_t>((n_units), 1); \
+  const size_t NB = (size_t)std::max<int64_t>((n_bins), 1), T = (size_t)std::max<int64_t>((n_trk), 1); \
+  const size_t NC = (size_t)std::max<int64_t>((n_chunks), 1);                                  \
+  const size_t NTILE = N / kTile + U * (R + 2) + 1;                                            \
+  const size_t NSCAN = std::max(NB / kScanTile + 2, std::max(2 * NC + 2, T / kScanTile + 2));
+
 static void refresh_bufs(tpcca_ctx *c) {
   Bufs &B = c->B;
   B.row_x = ptr<float>(c->row_x_d);
   B.units = ptr<UnitDev>(c->units_d);
   B.chunks = ptr<Chunk>(c->chunks_d);
   B.runs = ptr<RunDev>(c->runs_d);
-  B.rowtab = ptr<RowTab>(c->rowtab);
-  B.row_cnt = ptr<int32_t>(c->row_cnt);
-  B.row_fill = ptr<int32_t>(c->row_fill);
-  B.chunk_hist = ptr<int32_t>(c->chunk_hist);
-  B.rtmp = ptr<int4>(c->rtmp);
-  B.zmm = ptr<int32_t>(c->zmm);
-  B.binbeg = ptr<int32_t>(c->binbeg);
-  B.yz = ptr<float2>(c->yz);
-  B.sid = ptr<int32_t>(c->sid);
-  B.srow = ptr<uint8_t>(c->srow);
-  B.cinfo = ptr<int2>(c->cinfo);
-  B.up = ptr<int32_t>(c->up);
-  B.dn = ptr<int32_t>(c->dn);
-  B.upc = ptr<int32_t>(c->upc);
-  B.dnc = ptr<int32_t>(c->dnc);
-  B.flag = ptr<int32_t>(c->flag);
-  B.starts = ptr<int2>(c->starts);
-  B.tiles = ptr<int4>(c->tiles);
-  B.sval = ptr<uint8_t>(c->sval);
-  B.tofg = ptr<int32_t>(c->tofg);
-  B.kf_order = ptr<int32_t>(c->kf_order);
-  B.kf_tmp = ptr<int32_t>(c->kf_tmp);
-  B.band_tmp = ptr<int32_t>(c->band_tmp);
-  B.trk_start = ptr<int32_t>(c->trk_start);
-  B.trk_unit = ptr<int32_t>(c->trk_unit);
-  B.unit_tbegin = ptr<int32_t>(c->unit_tbegin);
-  B.trk = ptr<tpcca_tracklet_t>(c->trk);
-  B.trk_hits = ptr<int32_t>(c->trk_hits);
-  B.owner = ptr<unsigned long long>(c->owner);
-  B.accv = ptr<unsigned long long>(c->accv);
-  B.wonmask = ptr<unsigned long long>(c->wonmask);
-  B.accx = ptr<unsigned long long>(c->accx);
-  B.tracks = ptr<tpcca_track_t>(c->tracks);
-  B.hits_out = ptr<int32_t>(c->hits_out);
-  B.assign = ptr<int32_t>(c->assign);
-  B.unit_res = ptr<tpcca_unit_result_t>(c->unit_res);
-  B.scan_tmp = ptr<int64_t>(c->scan_tmp);
+#define REF(buf, field, type, count, keepc) B.field = ptr<type>(c->buf);
+  TPCCA_WORK_BUFFERS(REF)
+  TPCCA_OUTPUT_BUFFERS(REF)
+#undef REF
   B.ids_tmp = nullptr;
 }
 
-// Size every work buffer for the loaded units plus `extra` capacity.
+// Size every work buffer for the given capacities (at least the loaded units).
 static int ensure_work(tpcca_ctx *c, int64_t n_cl, int64_t n_units, int64_t n_bins, int64_t n_trk,
                        int64_t n_chunks) {
-  const int R = c->R;
-  const size_t N = (size_t)std::max<int64_t>(n_cl, 1), U = (size_t)std::max<int64_t>(n_units, 1);
-  const size_t NB = (size_t)std::max<int64_t>(n_bins, 1), T = (size_t)std::max<int64_t>(n_trk, 1);
-  const size_t NC = (size_t)std::max<int64_t>(n_chunks, 1);
+  TPCCA_BUFFER_COUNTS(c->R, n_cl, n_units, n_bins, n_trk, n_chunks)
   const size_t keepN = (size_t)c->n_total, keepU = c->units.size(), keepB = (size_t)c->bins_total,
-               keepT = (size_t)c->trk_total;
+               keepT = (size_t)c->trk_total, keepTiles = (size_t)c->tiles_total;
   int rc;
-#define ENS(buf, count, elem, keepc)                                               \
-  if ((rc = ensure(c, c->buf, (count) * (elem), (keepc) * (elem))) != TPCCA_OK) \
+#define ENS(buf, field, type, count, keepc)                                                    \
+  if ((rc = ensure(c, c->buf, (size_t)(count) * sizeof(type), (size_t)(keepc) * sizeof(type))) != TPCCA_OK) \
     return rc;
-  ENS(units_d, U, sizeof(UnitDev), 0);
-  ENS(chunks_d, NC, sizeof(Chunk), 0);
-  ENS(runs_d, U + 1, sizeof(RunDev), c->runs.size());
-  ENS(rowtab, U * (R + 1), sizeof(RowTab), keepU * (R + 1));
-  ENS(row_cnt, U * (R + 1), sizeof(int32_t), keepU * (R + 1));
-  ENS(row_fill, U * (R + 1), sizeof(int32_t), 0);
-  ENS(chunk_hist, NC * (R + 1), sizeof(int32_t), 0);
-  ENS(rtmp, N, sizeof(int4), 0);
-  ENS(zmm, 2 * U, sizeof(int32_t), 2 * keepU);
-  ENS(binbeg, NB, sizeof(int32_t), keepB);
-  ENS(yz, N, sizeof(float2), keepN);
-  ENS(sid, N, sizeof(int32_t), keepN);
-  ENS(srow, N, sizeof(uint8_t), keepN);
-  ENS(cinfo, N, sizeof(int2), keepN);
-  ENS(up, N, sizeof(int32_t), keepN);
-  ENS(dn, N, sizeof(int32_t), keepN);
-  ENS(upc, N, sizeof(int32_t), keepN);
-  ENS(dnc, N, sizeof(int32_t), keepN);
-  ENS(flag, N, sizeof(int32_t), keepN);
-  ENS(starts, N, sizeof(int2), 0);
-  ENS(tiles, (size_t)(N / kTile + U * (R + 2) + 1), sizeof(int4), (size_t)c->tiles_total);
-  ENS(owner, N, sizeof(unsigned long long), keepN);
-  ENS(hits_out, N, sizeof(int32_t), keepN);
-  ENS(assign, N, sizeof(int32_t), keepN);
-  ENS(trk_start, T, sizeof(int32_t), keepT);
-  ENS(kf_order, T, sizeof(int32_t), keepT);
-  ENS(kf_tmp, T, sizeof(int32_t), 0);
-  ENS(band_tmp, 3 * U * (R + 1), sizeof(int32_t), 0);
-  ENS(sval, N, sizeof(uint8_t), keepN);
-  ENS(tofg, N, sizeof(int32_t), keepN);
-  ENS(trk_unit, T, sizeof(int32_t), keepT);
-  ENS(unit_tbegin, U + 1, sizeof(int32_t), keepU);
-  ENS(trk, T, sizeof(tpcca_tracklet_t), keepT);
-  ENS(trk_hits, T * (size_t)slot_stride(R), sizeof(int32_t), keepT * (size_t)slot_stride(R));
-  ENS(accv, T + 1, sizeof(unsigned long long), 0);
-  ENS(wonmask, 4 * T, sizeof(unsigned long long), 0);
-  ENS(accx, T + 1, sizeof(unsigned long long), 0);
-  ENS(tracks, T, sizeof(tpcca_track_t), keepT);
-  ENS(unit_res, U, sizeof(tpcca_unit_result_t), keepU);
-  const size_t tiles = std::max(NB / kScanTile + 2, std::max(2 * NC + 2, T / kScanTile + 2));
-  ENS(scan_tmp, tiles, sizeof(int64_t), 0);
+  ENS(units_d, units, UnitDev, U, 0)
+  ENS(chunks_d, chunks, Chunk, NC, 0)
+  ENS(runs_d, runs, RunDev, U + 1, c->runs.size())
+  TPCCA_WORK_BUFFERS(ENS)
+  TPCCA_OUTPUT_BUFFERS(ENS)
 #undef ENS
   refresh_bufs(c);
   return TPCCA_OK;
@@ -512,6 +499,44 @@ static int load_unit(tpcca_ctx *c, int32_t slot, int32_t sector, const tpcca_clu
   return TPCCA_OK;
 }
 
+// Device copy of the parameters with the default launch schedule.
+static ParamsDev params_dev(const tpcca_params_t &p) {
+  ParamsDev P{};
+  P.n_rows = p.n_rows;
+  P.wy = p.link_wy;
+  P.wz = p.link_wz;
+  P.link_chi2 = p.link_chi2;
+  P.min_chain = p.min_chain_hits;
+  P.kB = p.kB;
+  P.ery = p.err2_y;
+  P.erz = p.err2_z;
+  P.max_sin = p.max_sinphi;
+  P.c22 = p.seed_c22;
+  P.c33 = p.seed_c33;
+  P.c44 = p.seed_c44;
+  P.r00 = p.reset_c00;
+  P.r11 = p.reset_c11;
+  P.nsig = p.pick_nsig;
+  P.wmax = p.pick_win_max;
+  P.pick_chi2 = p.pick_chi2;
+  P.max_miss = p.max_miss;
+  P.min_hits = p.min_track_hits;
+  P.own_pct = p.own_frac_pct;
+  P.inflate = p.refit_inflate;
+  P.hits_per_bin = p.grid_hits_per_bin;
+  P.kf_pool = 64;
+  P.kf_claims = 1;
+  return P;
+}
+
+// The argument checks tpcca_create applies to a geometry and parameters.
+static bool setup_valid(const tpcca_geometry_t *geo, const tpcca_params_t *params) {
+  if (!geo || !params || !geo->row_x) return false;
+  if (geo->n_rows < 3 || geo->n_rows > kMaxRows || params->n_rows != geo->n_rows) return false;
+  return !(geo->n_sectors < 1 || params->grid_hits_per_bin < 1 || params->min_chain_hits < 2 ||
+           params->min_track_hits < 1 || params->max_miss < 1);
+}
+
 // ===================================================================== ABI
 extern "C" {
 
@@ -559,11 +584,7 @@ const char *tpcca_last_error(tpcca_ctx_t *c) { return c ? c->last_error.c_str() 
 
 int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int device,
                  void *hip_stream, size_t budget, tpcca_ctx_t **out) {
-  if (!geo || !params || !out || !geo->row_x) return TPCCA_EINVAL;
-  if (geo->n_rows < 3 || geo->n_rows > kMaxRows || params->n_rows != geo->n_rows) return TPCCA_EINVAL;
-  if (geo->n_sectors < 1 || params->grid_hits_per_bin < 1 || params->min_chain_hits < 2 ||
-      params->min_track_hits < 1 || params->max_miss < 1)
-    return TPCCA_EINVAL;
+  if (!out || !setup_valid(geo, params)) return TPCCA_EINVAL;
   *out = nullptr;
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) return TPCCA_EDEVICE;
@@ -574,39 +595,7 @@ int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int 
   c->R = geo->n_rows;
   c->n_sectors = geo->n_sectors;
   c->row_x.assign(geo->row_x, geo->row_x + geo->n_rows);
-  ParamsDev &P = c->P;
-  P.n_rows = params->n_rows;
-  P.wy = params->link_wy;
-  P.wz = params->link_wz;
-  P.link_chi2 = params->link_chi2;
-  P.min_chain = params->min_chain_hits;
-  P.kB = params->kB;
-  P.ery = params->err2_y;
-  P.erz = params->err2_z;
-  P.max_sin = params->max_sinphi;
-  P.c22 = params->seed_c22;
-  P.c33 = params->seed_c33;
-  P.c44 = params->seed_c44;
-  P.r00 = params->reset_c00;
-  P.r11 = params->reset_c11;
-  P.nsig = params->pick_nsig;
-  P.wmax = params->pick_win_max;
-  P.pick_chi2 = params->pick_chi2;
-  P.max_miss = params->max_miss;
-  P.min_hits = params->min_track_hits;
-  P.own_pct = params->own_frac_pct;
-  P.inflate = params->refit_inflate;
-  P.hits_per_bin = params->grid_hits_per_bin;
-  P.kf_pool = 64;
-  P.kf_blocks_per_cu = 0;
-  P.link_blocks_per_cu = 0;
-  P.kf_min_waves = 0;
-  P.kf_claims = 1;
-  P.kf_xcd = 0;
-  P.link_stage = 0;
-  P.kf_split = 0;
-  P.kf_bands = 0;
-  P.kf_tail = 0;
+  c->P = params_dev(*params);
   std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
@@ -1160,6 +1149,181 @@ int tpcca_stage_times(tpcca_ctx_t *c, float *ms, int32_t cap) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------ allocation-free ---
+// Device memory of tpcca_run_batch_noalloc: the run tables and every work
+// buffer are carved from this array.  Each device the library runs on holds
+// its own copy until the process ends.  In host code the name stands for a
+// host-side shadow, not a device address: the device address is looked up
+// once per device with hipGetSymbolAddress and only that address is used.
+static __device__ __align__(256) unsigned char noalloc_scratch[TPCCA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+struct NoallocDevice {
+  std::mutex mu;                      // one call at a time per device
+  unsigned char *scratch = nullptr;   // device address of noalloc_scratch
+  std::vector<unsigned char> tables;  // host image of the run tables
+};
+
+NoallocDevice &noalloc_device(int dev) {
+  static std::mutex mu;
+  static std::map<int, std::unique_ptr<NoallocDevice>> devs;
+  std::lock_guard<std::mutex> lock(mu);
+  auto &d = devs[dev];
+  if (!d) d.reset(new NoallocDevice());
+  return *d;
+}
+
+// Lays out the run tables (row radii, the run, units, chunks: one block at
+// the start, written by one copy) and every work buffer from `base`, 256-B
+// aligned; base = nullptr only sizes them.  Returns {table bytes, total bytes}.
+std::pair<size_t, size_t> noalloc_layout(unsigned char *base, int R_, int64_t n_cl, int64_t n_units,
+                                         int64_t n_bins, int64_t n_trk, int64_t n_chunks, Bufs &B) {
+  TPCCA_BUFFER_COUNTS(R_, n_cl, n_units, n_bins, n_trk, n_chunks)
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char *p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  B.row_x = reinterpret_cast<float *>(take(sizeof(float) * (size_t)R));
+  B.runs = reinterpret_cast<RunDev *>(take(sizeof(RunDev)));
+  B.units = reinterpret_cast<UnitDev *>(take(sizeof(UnitDev) * U));
+  B.chunks = reinterpret_cast<Chunk *>(take(sizeof(Chunk) * NC));
+  const size_t table_bytes = off;
+#define CARVE(buf, field, type, count, keepc) B.field = reinterpret_cast<type *>(take((size_t)(count) * sizeof(type)));
+  TPCCA_WORK_BUFFERS(CARVE)
+#undef CARVE
+  B.ids_tmp = nullptr;
+  return {table_bytes, off};
+}
+
+}  // namespace
+
+extern "C" int tpcca_run_batch_noalloc(const tpcca_geometry_t *geo, const tpcca_params_t *params,
+                                       int device, void *hip_stream, const tpcca_batch_t *bt,
+                                       tpcca_track_t *tracks, int64_t tracks_cap, int32_t *hits,
+                                       int64_t hits_cap, int32_t *assignment, int64_t n_assignment,
+                                       tpcca_unit_result_t *units, int64_t *n_tracks_out,
+                                       int64_t *n_hits_out) {
+  if (!setup_valid(geo, params) || !bt || bt->n_units < 0) return TPCCA_EINVAL;
+  if ((bt->flags & 1) != TPCCA_MEM_DEVICE || (bt->flags & TPCCA_BATCH_GRAPH)) return TPCCA_EINVAL;
+  const int U = bt->n_units;
+  if (U > 0 && (!bt->slot || !bt->sector || !bt->begin || !bt->n || !units)) return TPCCA_EINVAL;
+  const int R = geo->n_rows;
+  const ParamsDev P = params_dev(*params);
+  // capacities, exactly as a context reserves them for these units
+  int64_t n_total = 0, bins_total = 0, trk_total = 0, tiles_total = 0, n_chunks = 0;
+  for (int u = 0; u < U; ++u) {
+    const int64_t n = bt->n[u];
+    if (n < 0 || n > 0xFFFFFF || bt->begin[u] < 0 || bt->slot[u] < 0 || bt->sector[u] < 0 ||
+        bt->sector[u] >= geo->n_sectors)
+      return TPCCA_EINVAL;
+    n_total += n;
+    bins_total += bins_cap_of(n, P.hits_per_bin, R);
+    trk_total += trk_cap_of(n, P.min_chain);
+    tiles_total += tile_cap_of(n, R);
+    n_chunks += (n + kChunk - 1) / kChunk;
+  }
+  if (n_total > 0 && (!bt->cl || !bt->row)) return TPCCA_EINVAL;
+  if (n_total > 0 && (!tracks || !hits || !assignment)) return TPCCA_EINVAL;
+  if (tracks_cap < trk_total || hits_cap < n_total || n_assignment < n_total) return TPCCA_ECAPACITY;
+  Bufs B{};
+  const auto sz = noalloc_layout(nullptr, R, n_total, U, bins_total, trk_total, n_chunks, B);
+  if (sz.second > (size_t)TPCCA_NOALLOC_SCRATCH_BYTES) return TPCCA_ENOMEM;
+  if (U == 0) {
+    if (n_tracks_out) *n_tracks_out = 0;
+    if (n_hits_out) *n_hits_out = 0;
+    return TPCCA_OK;
+  }
+  if (hipSetDevice(device) != hipSuccess) return TPCCA_EDEVICE;
+  NoallocDevice &D = noalloc_device(device);
+  std::lock_guard<std::mutex> lock(D.mu);
+  if (!D.scratch) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return TPCCA_EDEVICE;
+    }
+    D.scratch = static_cast<unsigned char *>(p);
+  }
+  // host image of the tables, laid out as on the device
+  D.tables.assign(sz.first, 0);
+  Bufs H{};
+  noalloc_layout(D.tables.data(), R, n_total, U, bins_total, trk_total, n_chunks, H);
+  std::memcpy(const_cast<float *>(H.row_x), geo->row_x, sizeof(float) * (size_t)R);
+  int64_t cl = 0, bins = 0, trk = 0, tiles = 0, ch = 0;
+  for (int u = 0; u < U; ++u) {
+    const int32_t n = bt->n[u];
+    UnitDev &V = H.units[u];
+    V.cl = reinterpret_cast<const float4 *>(bt->cl + bt->begin[u]);
+    V.row = bt->row + bt->begin[u];
+    V.bin_base = bins;
+    V.cl_begin = (int32_t)cl;
+    V.n = n;
+    V.trk_base = (int32_t)trk;
+    V.slot = bt->slot[u];
+    V.sector = bt->sector[u];
+    V.tile_base = (int32_t)tiles;
+    for (int32_t b = 0; b < n; b += kChunk) H.chunks[ch++] = Chunk{u, b, std::min(kChunk, n - b), 0};
+    cl += n;
+    bins += bins_cap_of(n, P.hits_per_bin, R);
+    trk += trk_cap_of(n, P.min_chain);
+    tiles += tile_cap_of(n, R);
+  }
+  RunHost h{};
+  h.u0 = 0;
+  h.u1 = U;
+  h.c0 = 0;
+  h.c1 = (int32_t)n_chunks;
+  h.cl0 = 0;
+  h.cl1 = (int32_t)n_total;
+  h.bin0 = 0;
+  h.bin1 = bins_total;
+  h.trk0 = 0;
+  h.trk_cap = (int32_t)trk_total;
+  h.tile0 = 0;
+  h.tile1 = (int32_t)tiles_total;
+  h.dense = n_total / ((int64_t)U * (R + 1)) >= 1024 ? 1 : 0;
+  RunDev &rd = H.runs[0];
+  rd.u0 = h.u0;
+  rd.u1 = h.u1;
+  rd.c0 = h.c0;
+  rd.c1 = h.c1;
+  rd.cl0 = h.cl0;
+  rd.cl1 = h.cl1;
+  rd.bin0 = h.bin0;
+  rd.bin1 = h.bin1;
+  rd.trk0 = h.trk0;
+  rd.trk_cap = h.trk_cap;
+  rd.tile0 = h.tile0;
+  rd.tile1 = h.tile1;
+  noalloc_layout(D.scratch, R, n_total, U, bins_total, trk_total, n_chunks, B);
+  B.tracks = tracks;
+  B.hits_out = hits;
+  B.assign = assignment;
+  B.unit_res = units;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipMemcpyAsync(D.scratch, D.tables.data(), sz.first, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_grid(B, P, 0, h, s);
+  if (e == hipSuccess) e = launch_links(B, P, 0, h, s);
+  if (e == hipSuccess) e = launch_clean(B, P, 0, h, s);
+  if (e == hipSuccess) e = launch_chains(B, P, 0, h, s);
+  if (e == hipSuccess) e = launch_kf(B, P, 0, h, s);
+  if (e == hipSuccess) e = launch_select(B, P, 0, h, s);
+  RunDev out{};
+  if (e == hipSuccess) e = hipMemcpyAsync(&out, B.runs, sizeof(RunDev), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return TPCCA_EDEVICE;
+  }
+  if (out.err) return (out.err & 2) ? TPCCA_EDEVICE : TPCCA_EINVAL;
+  if (n_tracks_out) *n_tracks_out = out.n_acc;
+  if (n_hits_out) *n_hits_out = out.n_acc_hits;
+  return TPCCA_OK;
+}
 
 // ------------------------------------------------ internal (server) hooks ---
 namespace tpcca {

@@ -109,7 +109,7 @@ SYMBOLS = (
     "tpcca_server_stats", "tpcca_server_reset_stats", "tpcca_server_destroy", "tpcca_now",
     "tpcca_server_last_error",
     "tpcca_work_stats", "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_server_set_tuning",
-    "tpcca_tuning_default",
+    "tpcca_tuning_default", "tpcca_run_batch_noalloc",
 )
 
 _lib = None
@@ -166,6 +166,9 @@ def lib():
         "tpcca_server_set_tuning": (c_i32, [c_vp, ctypes.POINTER(Tuning)]),
         "tpcca_tuning_default": (None, [ctypes.POINTER(Tuning)]),
         "tpcca_get_tuning": (c_i32, [c_vp, ctypes.POINTER(Tuning)]),
+        "tpcca_run_batch_noalloc": (c_i32, [ctypes.POINTER(Geometry), ctypes.POINTER(Params), c_i32, c_vp,
+                                            ctypes.POINTER(Batch), c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp,
+                                            ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
     }
     missing = [n for n in SYMBOLS if not hasattr(L, n)]
     if missing:
@@ -390,6 +393,38 @@ class Context:
         ms = np.zeros(6, np.float32)
         n = lib().tpcca_stage_times(self.h, _p(ms), 6)
         return dict(zip(self.STAGES, ms[:n].tolist()))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # TPCCA_NOALLOC_SCRATCH_BYTES
+
+
+def run_batch_noalloc(row_x, cl, row, units, tracks, hits, assignment, unit_results, params: Params | None = None,
+                      device: int = 0, stream=None, n_sectors: int = 36):
+    """tpcca_run_batch_noalloc: the whole tracker on device-resident inputs,
+    every work buffer in the library's fixed device array, results written
+    to the caller's device tensors (tracks: uint8 of n x 108 B, hits and
+    assignment: int32, unit_results: uint8 of U x 48 B).  units: (U, 4)
+    int array of (begin, n, slot, sector).  Returns (n_tracks, n_hits)."""
+    row_x = np.ascontiguousarray(row_x, np.float32)
+    params = params or params_default(n_rows=row_x.shape[0])
+    geo = Geometry(n_sectors, row_x.shape[0], _p(row_x))
+    units = np.asarray(units, np.int64).reshape(-1, 4)
+    slot = np.ascontiguousarray(units[:, 2], np.int32)
+    sector = np.ascontiguousarray(units[:, 3], np.int32)
+    begin = np.ascontiguousarray(units[:, 0], np.int64)
+    n = np.ascontiguousarray(units[:, 1], np.int32)
+    b = Batch(units.shape[0], _p(slot), _p(sector), _p(begin), _p(n), _p(cl), _p(row), MEM_DEVICE)
+    nt, nh = c_i64(), c_i64()
+    st = lib().tpcca_run_batch_noalloc(
+        ctypes.byref(geo), ctypes.byref(params), device, stream, ctypes.byref(b), _p(tracks),
+        tracks.numel() // TRACK_DTYPE.itemsize, _p(hits), hits.numel(), _p(assignment), assignment.numel(),
+        _p(unit_results), ctypes.byref(nt), ctypes.byref(nh))
+    detail = ""
+    if st == ENOMEM:
+        detail = f"the units need more than the {NOALLOC_SCRATCH_BYTES >> 20} MiB allocation-free work array"
+    if st != OK:
+        raise TpccaError(st, "tpcca_run_batch_noalloc", detail)
+    return nt.value, nh.value
 
 
 def now() -> float:
