@@ -332,7 +332,9 @@ def timeframe(seed=0, n_events=128, tf_index=0, slot=0, keep_truth=False, shuffl
             per_sector[s].append(c)
             per_sector_row[s].append(ev.row[b:e])
             if keep_truth and ev.truth is not None:
-                per_sector_truth[s].append(ev.truth[b:e])
+                t = ev.truth[b:e].copy()
+                t["pad"] = i  # event index inside the frame
+                per_sector_truth[s].append(t)
     parts = []
     for s in range(N_SECTORS):
         c = np.concatenate(per_sector[s]) if per_sector[s] else np.zeros((0, 4), np.float32)
