@@ -314,6 +314,136 @@ int tpcca_stage_times(tpcca_ctx_t *ctx, float *ms, int32_t cap);
 /* Enable/disable per-stage event recording (off by default). */
 int tpcca_set_timing(tpcca_ctx_t *ctx, int32_t enable);
 
+/* ------------------------------------------------------ second phase --- */
+/* The steps after the sector tracker, on the accepted tracks of every unit
+   of a context ("segments"):
+   - Sec. 2, second phase: the segments found in the individual sectors are
+     merged into final tracks, which are refitted.  Reading: segment A (in
+     sector s) and B (in the neighbouring sector s +- 1 of the same side and
+     slot) are a candidate pair if B's first won row follows A's last by 1 to
+     merge_max_gap rows and their facing ends lie within merge_dz_ends in z;
+     B's inner state is rotated into A's frame, A's outer end (its fitted
+     state propagated along its won hits) propagated to that plane, and the
+     five-parameter difference must lie within the y, z windows and the
+     chi^2 cut.  Mutual best partners (smallest chi^2, then (sector, index))
+     merge; a final track is a chain of merged segments, refitted inward from
+     the outermost segment's outer end (covariance x refit_inflate) through
+     every won hit, the state rotated between sector frames.
+   - Sec. 5, continuous read-out: the time of a vertex is known only after
+     tracking, so tracking runs in the drift coordinate z' and each refitted
+     track is extrapolated (dca_steps propagation steps) to the plane x = 0
+     of its frame, which holds the beam axis, for z0 and a time estimate
+     t0 = -z0 / v (A side), z0 / v (C side).  Sorted t0 of tracks with at
+     least vtx_min_hits hits and |q/pT| <= rej_looper_qpt form vertices
+     (estimates closer than vtx_gap_us chain; at least vtx_min_tracks; time
+     = lower median); every track joins the nearest vertex within
+     vtx_attach_us and gets z = z' + v t0 (A), z' - v t0 (C).
+   - Sec. 3, compression: per segment, the first won cluster quantised
+     (rint(y / cmp_qy), rint(z / cmp_qz)) and sin phi, tan lambda, q/pT as
+     FP32; per further hit the row step and the residuals of the quantised
+     cluster to the quantised prediction of an FP32 Kalman fit over the
+     quantised values; decompression runs the same fit and is exact.
+   - Sec. 3, rejection: flags per cluster of a final track: 1 |q/pT| >
+     rej_qpt (pT < 50 MeV), 2 later leg of a looping track (|q/pT| >
+     rej_looper_qpt and no vertex), 4 local |sin phi| > rej_sinphi.
+   The phase's propagations and rotations fail beyond |sin phi| > max_sinphi.
+   Defaults from tpcca_phase2_params_default(); field order is part of the
+   ABI. */
+typedef struct {
+  float sector_cos, sector_sin; /* cos, sin of the 20-degree sector width */
+  float max_sinphi;             /* 0.99 */
+  float merge_dz_ends;          /* 40 cm */
+  int32_t merge_max_gap;        /* 10 rows */
+  float merge_wy, merge_wz;     /* 4 cm */
+  float merge_chi2;             /* 50 */
+  float refit_inflate;          /* 100 */
+  int32_t dca_steps;            /* 16 */
+  float vdrift;                 /* 2.58 cm/us */
+  float vtx_gap_us;             /* 0.1 */
+  int32_t vtx_min_tracks;       /* 3 */
+  int32_t vtx_min_hits;         /* 20 */
+  float vtx_attach_us;          /* 0.25 */
+  float cmp_qy, cmp_qz;         /* 0.01 cm */
+  float cmp_c22, cmp_c33, cmp_c44; /* 1e-4, 1e-4, 1 */
+  float rej_qpt;                /* 20 c/GeV (50 MeV) */
+  float rej_looper_qpt;         /* 5.4 c/GeV: the circle turns back inside 247 cm */
+  float rej_sinphi;             /* 0.8 */
+} tpcca_phase2_params_t;
+
+/* A final track: state at its innermost hit in the frame of its innermost
+   segment's sector. */
+typedef struct {
+  int32_t slot, sector;
+  int32_t status;     /* 0 refitted, 2 numerical failure of the refit */
+  int32_t n_seg, n_hits, ndf, row_ref;
+  int32_t vertex;     /* index into the slot's vertices, or -1 */
+  int32_t z0_ok;      /* 1 if the extrapolation to the axis succeeded */
+  int32_t first_seg;  /* innermost segment: sector << 24 | index among its unit's tracks */
+  int64_t hit_begin;  /* first entry in the hit list returned with the finals */
+  float x_ref, chi2;
+  float p[5];         /* y, z', sin phi, tan lambda, q/pT */
+  float cov[15];
+  float z0, t0;       /* z' at the axis, time estimate (us) */
+  float z_conv;       /* p[1] converted with the vertex time (p[1] without vertex) */
+  int32_t pad_;
+} tpcca_final_t;      /* 152 B */
+
+typedef struct {
+  int32_t slot, n_tracks;
+  int32_t first;      /* first member's position among the slot's sorted t0 estimates */
+  float t0;           /* us */
+} tpcca_vertex_t;
+
+/* Device views of the phase's results (valid until the next load/reset). */
+typedef struct {
+  int32_t n_seg, n_final, n_vertices;
+  int32_t pad_;
+  int64_t n_final_hits;
+  const tpcca_final_t *finals;  /* all slots, in the order of their innermost segment */
+  const int32_t *final_hits;    /* sector << 24 | cluster ID */
+  const tpcca_vertex_t *vertices; /* slot field = compact slot index */
+  const uint8_t *flags;         /* per cluster, batch order (as the assignment) */
+  const int32_t *rec;           /* 6 per segment */
+  const int32_t *res;           /* 3 per hit, at the hit's position in the track hit array */
+  const int32_t *seg_n_hits;    /* per segment */
+  const int64_t *seg_hit_begin; /* per segment: first hit in the track hit array */
+} tpcca_phase2_view_t;
+
+void tpcca_phase2_params_default(tpcca_phase2_params_t *q);
+/* Parameters of the phase for ctx (copied). EINVAL on out-of-range values. */
+int tpcca_set_phase2_params(tpcca_ctx_t *ctx, const tpcca_phase2_params_t *q);
+/* Run the phase on every unit of ctx (all must have been selected; ESTATE
+   otherwise).  Reads the units' inputs again: device inputs must still be
+   valid.  Queues its kernels and waits once for the number of final tracks
+   (to size the sort of the time estimates).  Errors: ESTATE, ENOMEM,
+   EDEVICE. */
+int tpcca_phase2(tpcca_ctx_t *ctx);
+/* Final tracks of one slot (order of their innermost segment) with their
+   hits (sector << 24 | cluster ID, inner to outer); ECAPACITY with the sizes. */
+int tpcca_get_finals(tpcca_ctx_t *ctx, int32_t slot, tpcca_final_t *out, int32_t cap, int32_t *n_out,
+                     int32_t *hits, int64_t hits_cap, int64_t *n_hits_out);
+/* Per track of unit (slot, sector), n = its number of tracks: the merge
+   partners (sector << 24 | index among that unit's tracks, -1 if none) and
+   the index of its final track among the slot's finals. */
+int tpcca_get_segment_links(tpcca_ctx_t *ctx, int32_t slot, int32_t sector, int32_t *next,
+                            int32_t *prev, int32_t *final_of, int32_t n);
+int tpcca_get_vertices(tpcca_ctx_t *ctx, int32_t slot, tpcca_vertex_t *out, int32_t cap, int32_t *n_out);
+/* Rejection flags of the unit's clusters (n = cluster count). */
+int tpcca_get_flags(tpcca_ctx_t *ctx, int32_t slot, int32_t sector, uint8_t *flags, int32_t n);
+/* Compressed form of the unit's tracks (ascending start_id): 6 int32 per
+   track (row, y and z step counts of the first won cluster, FP32 bits of
+   sin phi, tan lambda, q/pT) and 3 int32 per won hit (row step, residual of
+   y, of z; zeros for the first). */
+int tpcca_get_compressed(tpcca_ctx_t *ctx, int32_t slot, int32_t sector, int32_t *rec, int32_t seg_cap,
+                         int32_t *res, int64_t hits_cap, int32_t *n_seg, int64_t *n_hits);
+int tpcca_phase2_view(tpcca_ctx_t *ctx, tpcca_phase2_view_t *out);
+/* Decompression (device pointers, queued on ctx's stream): n_seg records
+   (6 int32), their hits' residuals (3 int32 per hit, hit_begin / n_hits per
+   record) -> the quantised coordinates yq, zq and the rows of every hit, at
+   the same positions.  Uses ctx's geometry and phase parameters. */
+int tpcca_decompress(tpcca_ctx_t *ctx, int32_t n_seg, const int32_t *n_hits, const int64_t *hit_begin,
+                     const int32_t *rec, const int32_t *res, int32_t *yq, int32_t *zq, uint8_t *rows);
+
 /* ------------------------------------------------------------ server --- */
 /* Continuous batching of time frames (Sec. 5: time frames are tracked as a
    whole; GPU memory is the limit, a frame larger than memory is sliced, here

@@ -15,6 +15,7 @@
 #include "tpcca.h"
 #include "tpcca_internal.h"
 #include "tpcca_kernels.h"
+#include "tpcca_phase2.h"
 #include "tpcca_runtime.h"
 
 using namespace tpcca;
@@ -82,6 +83,19 @@ struct tpcca_ctx {
   bool gtiming = false;         // the captured graph holds stage events
 
   std::string last_error;
+
+  // second phase (Sec. 2 merging and refit, Sec. 5 vertices, Sec. 3
+  // compression and rejection)
+  tpcca_phase2_params_t p2params{};
+  DevBuf p2units, p2seg_begin, p2seg_unit, p2seg_nh, p2seg_hb, p2seg_rows, p2seg_zin, p2seg_zout, p2seg_out,
+      p2zmm, p2bin_cnt, p2bin_beg, p2bin_seg, p2best_b, p2best_a, p2next, p2prev, p2final_of, p2final_start,
+      p2final_nhits, p2final_hbeg, p2finals, p2final_hits, p2vkey0, p2vkey1, p2vval0, p2vval1, p2gstart,
+      p2group_pos, p2vertices, p2slot_first, p2slot_vbeg, p2slot_vend, p2flags, p2rec, p2res, p2scan, p2cnt,
+      p2sort_tmp;
+  P2Bufs P2{};
+  bool p2_done = false;
+  P2Counts p2c{};
+  std::vector<int32_t> p2_slot_value;  // compact slot index -> slot
 };
 
 // --------------------------------------------------------------- errors ---
@@ -596,6 +610,7 @@ int tpcca_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int 
   c->n_sectors = geo->n_sectors;
   c->row_x.assign(geo->row_x, geo->row_x + geo->n_rows);
   c->P = params_dev(*params);
+  tpcca_phase2_params_default(&c->p2params);
   std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
@@ -631,7 +646,14 @@ int tpcca_destroy(tpcca_ctx_t *c) {
                    &c->zmm, &c->binbeg, &c->yz, &c->sid, &c->up, &c->dn, &c->upc,
                    &c->dnc, &c->flag, &c->starts, &c->tiles, &c->sval, &c->tofg, &c->kf_order, &c->kf_tmp, &c->band_tmp, &c->srow, &c->cinfo, &c->trk_start, &c->trk_unit, &c->unit_tbegin, &c->trk,
                    &c->trk_hits, &c->owner, &c->accv, &c->wonmask, &c->accx, &c->tracks, &c->hits_out,
-                   &c->assign, &c->unit_res, &c->scan_tmp, &c->in_cl, &c->in_row};
+                   &c->assign, &c->unit_res, &c->scan_tmp, &c->in_cl, &c->in_row,
+                   &c->p2units, &c->p2seg_begin, &c->p2seg_unit, &c->p2seg_nh, &c->p2seg_hb, &c->p2seg_rows,
+                   &c->p2seg_zin, &c->p2seg_zout, &c->p2seg_out, &c->p2zmm, &c->p2bin_cnt, &c->p2bin_beg,
+                   &c->p2bin_seg, &c->p2best_b, &c->p2best_a, &c->p2next, &c->p2prev, &c->p2final_of,
+                   &c->p2final_start, &c->p2final_nhits, &c->p2final_hbeg, &c->p2finals, &c->p2final_hits,
+                   &c->p2vkey0, &c->p2vkey1, &c->p2vval0, &c->p2vval1, &c->p2gstart, &c->p2group_pos,
+                   &c->p2vertices, &c->p2slot_first, &c->p2slot_vbeg, &c->p2slot_vend, &c->p2flags, &c->p2rec,
+                   &c->p2res, &c->p2scan, &c->p2cnt, &c->p2sort_tmp};
   for (DevBuf *b : all)
     if (b->p) hipFree(b->p);
   for (int k = 0; k < 7; ++k)
@@ -655,6 +677,7 @@ int tpcca_reset(tpcca_ctx_t *c) {
   c->n_total = c->bins_total = c->trk_total = c->tiles_total = c->in_used = 0;
   c->tables_dirty = true;
   c->have_times = false;
+  c->p2_done = false;
   return TPCCA_OK;
 }
 
@@ -1341,3 +1364,374 @@ bool tuning_valid(const tpcca_tuning_t *t, int n_rows) {
 }
 size_t ctx_allocated(tpcca_ctx *c) { return c->allocated; }
 }  // namespace tpcca
+
+// ========================================================= second phase ===
+// Merging of the sector segments and refit (Sec. 2), vertex times (Sec. 5),
+// track-model compression and rejection flags (Sec. 3) on the accepted
+// tracks of every unit of a context.
+namespace {
+
+P2Params p2_dev(const tpcca_phase2_params_t &q) {
+  P2Params d{};
+  d.cs = q.sector_cos;
+  d.sn = q.sector_sin;
+  d.max_sin = q.max_sinphi;
+  d.dz_ends = q.merge_dz_ends;
+  d.max_gap = q.merge_max_gap;
+  d.wy = q.merge_wy;
+  d.wz = q.merge_wz;
+  d.chi2 = q.merge_chi2;
+  d.inflate = q.refit_inflate;
+  d.dca_steps = q.dca_steps;
+  d.vdrift = q.vdrift;
+  d.gap_us = q.vtx_gap_us;
+  d.vtx_min_tracks = q.vtx_min_tracks;
+  d.vtx_min_hits = q.vtx_min_hits;
+  d.attach_us = q.vtx_attach_us;
+  d.qy = q.cmp_qy;
+  d.qz = q.cmp_qz;
+  d.c22 = q.cmp_c22;
+  d.c33 = q.cmp_c33;
+  d.c44 = q.cmp_c44;
+  d.rej_qpt = q.rej_qpt;
+  d.rej_looper = q.rej_looper_qpt;
+  d.rej_sin = q.rej_sinphi;
+  return d;
+}
+
+// the tracker's parameters with the phase's own |sin phi| limit
+ParamsDev p2_prop_params(const tpcca_ctx *c) {
+  ParamsDev P = c->P;
+  P.max_sin = c->p2params.max_sinphi;
+  return P;
+}
+
+bool p2_valid(const tpcca_phase2_params_t &q) {
+  auto fin = [](float v) { return std::isfinite(v); };
+  return fin(q.sector_cos) && fin(q.sector_sin) && q.max_sinphi > 0.0f && q.max_sinphi < 1.0f &&
+         q.merge_dz_ends >= 0.0f && q.merge_max_gap >= 1 && q.merge_wy >= 0.0f && q.merge_wz >= 0.0f &&
+         q.merge_chi2 >= 0.0f && q.refit_inflate > 0.0f && q.dca_steps >= 1 && q.dca_steps <= 1024 &&
+         q.vdrift > 0.0f && q.vtx_gap_us >= 0.0f && q.vtx_min_tracks >= 1 && q.vtx_attach_us >= 0.0f &&
+         q.cmp_qy > 0.0f && q.cmp_qz > 0.0f && q.cmp_c22 > 0.0f && q.cmp_c33 > 0.0f && q.cmp_c44 > 0.0f &&
+         fin(q.rej_qpt) && fin(q.rej_looper_qpt) && fin(q.rej_sinphi);
+}
+
+int p2_ensure(tpcca_ctx *c, int64_t U, int64_t T, int64_t N, int64_t S) {
+  U = std::max<int64_t>(U, 1);
+  T = std::max<int64_t>(T, 1);
+  N = std::max<int64_t>(N, 1);
+  S = std::max<int64_t>(S, 1);
+  const int64_t tiles = T / kP2Tile + 2 + N / kP2Tile;
+  struct E {
+    DevBuf *b;
+    size_t bytes;
+  } list[] = {
+      {&c->p2units, sizeof(P2Unit) * U}, {&c->p2seg_begin, sizeof(int32_t) * (U + 1)},
+      {&c->p2seg_unit, sizeof(int32_t) * T}, {&c->p2seg_nh, sizeof(int32_t) * T},
+      {&c->p2seg_hb, sizeof(int64_t) * T}, {&c->p2seg_rows, sizeof(int2) * T},
+      {&c->p2seg_zin, sizeof(float) * T}, {&c->p2seg_zout, sizeof(float) * T},
+      {&c->p2seg_out, sizeof(P2Out) * T}, {&c->p2zmm, sizeof(int2) * U},
+      {&c->p2bin_cnt, sizeof(int32_t) * U * kP2Bins}, {&c->p2bin_beg, sizeof(int32_t) * U * (kP2Bins + 1)},
+      {&c->p2bin_seg, sizeof(int32_t) * T}, {&c->p2best_b, sizeof(unsigned long long) * T},
+      {&c->p2best_a, sizeof(unsigned long long) * T}, {&c->p2next, sizeof(int32_t) * T},
+      {&c->p2prev, sizeof(int32_t) * T}, {&c->p2final_of, sizeof(int32_t) * T},
+      {&c->p2final_start, sizeof(int32_t) * T}, {&c->p2final_nhits, sizeof(int32_t) * T},
+      {&c->p2final_hbeg, sizeof(int64_t) * T}, {&c->p2finals, sizeof(tpcca_final_t) * T},
+      {&c->p2final_hits, sizeof(int32_t) * N}, {&c->p2vkey0, sizeof(unsigned long long) * T},
+      {&c->p2vkey1, sizeof(unsigned long long) * T}, {&c->p2vval0, sizeof(int32_t) * T},
+      {&c->p2vval1, sizeof(int32_t) * T}, {&c->p2gstart, sizeof(int32_t) * T},
+      {&c->p2group_pos, sizeof(int32_t) * T}, {&c->p2vertices, sizeof(tpcca_vertex_t) * T},
+      {&c->p2slot_first, sizeof(int32_t) * S}, {&c->p2slot_vbeg, sizeof(int32_t) * S},
+      {&c->p2slot_vend, sizeof(int32_t) * S}, {&c->p2flags, (size_t)N},
+      {&c->p2rec, sizeof(int32_t) * 6 * T}, {&c->p2res, sizeof(int32_t) * 3 * N},
+      {&c->p2scan, sizeof(int64_t) * (tiles + 2)}, {&c->p2cnt, sizeof(P2Counts)},
+  };
+  for (auto &e : list) RCCHK(ensure(c, *e.b, e.bytes, 0));
+  P2Bufs &Q = c->P2;
+  Q.units = ptr<P2Unit>(c->p2units);
+  Q.n_units = (int32_t)c->units.size();
+  Q.seg_begin = ptr<int32_t>(c->p2seg_begin);
+  Q.seg_unit = ptr<int32_t>(c->p2seg_unit);
+  Q.seg_nh = ptr<int32_t>(c->p2seg_nh);
+  Q.seg_hb = ptr<int64_t>(c->p2seg_hb);
+  Q.seg_rows = ptr<int2>(c->p2seg_rows);
+  Q.seg_zin = ptr<float>(c->p2seg_zin);
+  Q.seg_zout = ptr<float>(c->p2seg_zout);
+  Q.seg_out = ptr<P2Out>(c->p2seg_out);
+  Q.zmm = ptr<int2>(c->p2zmm);
+  Q.bin_cnt = ptr<int32_t>(c->p2bin_cnt);
+  Q.bin_beg = ptr<int32_t>(c->p2bin_beg);
+  Q.bin_seg = ptr<int32_t>(c->p2bin_seg);
+  Q.best_b = ptr<unsigned long long>(c->p2best_b);
+  Q.best_a = ptr<unsigned long long>(c->p2best_a);
+  Q.next = ptr<int32_t>(c->p2next);
+  Q.prev = ptr<int32_t>(c->p2prev);
+  Q.final_of = ptr<int32_t>(c->p2final_of);
+  Q.final_start = ptr<int32_t>(c->p2final_start);
+  Q.final_nhits = ptr<int32_t>(c->p2final_nhits);
+  Q.final_hbeg = ptr<int64_t>(c->p2final_hbeg);
+  Q.finals = ptr<tpcca_final_t>(c->p2finals);
+  Q.final_hits = ptr<int32_t>(c->p2final_hits);
+  Q.vkey[0] = ptr<unsigned long long>(c->p2vkey0);
+  Q.vkey[1] = ptr<unsigned long long>(c->p2vkey1);
+  Q.vval[0] = ptr<int32_t>(c->p2vval0);
+  Q.vval[1] = ptr<int32_t>(c->p2vval1);
+  Q.gstart = ptr<int32_t>(c->p2gstart);
+  Q.group_pos = ptr<int32_t>(c->p2group_pos);
+  Q.vertices = ptr<tpcca_vertex_t>(c->p2vertices);
+  Q.slot_first = ptr<int32_t>(c->p2slot_first);
+  Q.slot_vbeg = ptr<int32_t>(c->p2slot_vbeg);
+  Q.slot_vend = ptr<int32_t>(c->p2slot_vend);
+  Q.flags = ptr<uint8_t>(c->p2flags);
+  Q.rec = ptr<int32_t>(c->p2rec);
+  Q.res = ptr<int32_t>(c->p2res);
+  Q.scan_tmp = ptr<int64_t>(c->p2scan);
+  Q.cnt = ptr<P2Counts>(c->p2cnt);
+  return TPCCA_OK;
+}
+
+int p2_side_of(int s) { return s < 18 ? 0 : 1; }
+
+int p2_ready(tpcca_ctx *c) {
+  if (!c) return TPCCA_EINVAL;
+  if (!c->p2_done) return TPCCA_ESTATE;
+  hipSetDevice(c->device);
+  return check_errors(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+void tpcca_phase2_params_default(tpcca_phase2_params_t *q) {
+  if (!q) return;
+  const double w = 20.0 * 3.14159265358979323846 / 180.0;
+  q->sector_cos = (float)std::cos(w);
+  q->sector_sin = (float)std::sin(w);
+  q->max_sinphi = 0.99f;
+  q->merge_dz_ends = 40.0f;
+  q->merge_max_gap = 10;
+  q->merge_wy = 4.0f;
+  q->merge_wz = 4.0f;
+  q->merge_chi2 = 50.0f;
+  q->refit_inflate = 100.0f;
+  q->dca_steps = 16;
+  q->vdrift = 2.58f;
+  q->vtx_gap_us = 0.1f;
+  q->vtx_min_tracks = 3;
+  q->vtx_min_hits = 20;
+  q->vtx_attach_us = 0.25f;
+  q->cmp_qy = 0.01f;
+  q->cmp_qz = 0.01f;
+  q->cmp_c22 = 1e-4f;
+  q->cmp_c33 = 1e-4f;
+  q->cmp_c44 = 1.0f;
+  q->rej_qpt = 20.0f;
+  q->rej_looper_qpt = 5.4f;
+  q->rej_sinphi = 0.8f;
+}
+
+int tpcca_set_phase2_params(tpcca_ctx_t *c, const tpcca_phase2_params_t *q) {
+  if (!c || !q || !p2_valid(*q)) return TPCCA_EINVAL;
+  c->p2params = *q;
+  return TPCCA_OK;
+}
+
+int tpcca_phase2(tpcca_ctx_t *c) {
+  if (!c) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  const int U = (int)c->units.size();
+  if (U == 0) return TPCCA_ESTATE;
+  for (int u = 0; u < U; ++u)
+    if (c->uh[u].state < kSelected) return TPCCA_ESTATE;
+  c->p2_done = false;
+  // units: compact slot index and the neighbouring sectors of the same side
+  std::map<int, int> slot_idx;
+  c->p2_slot_value.clear();
+  for (int u = 0; u < U; ++u) {
+    if (!slot_idx.count(c->uh[u].slot)) {
+      slot_idx[c->uh[u].slot] = (int)c->p2_slot_value.size();
+      c->p2_slot_value.push_back(c->uh[u].slot);
+    }
+  }
+  std::vector<P2Unit> pu(U);
+  for (int u = 0; u < U; ++u) {
+    const int s = c->uh[u].sector, side = p2_side_of(s);
+    const int sp = side * 18 + ((s % 18) + 17) % 18, sn = side * 18 + ((s % 18) + 1) % 18;
+    pu[u].slot = slot_idx[c->uh[u].slot];
+    pu[u].sector = s;
+    pu[u].prev = (s < 36 && sp < c->n_sectors && sp != s) ? find_unit(c, c->uh[u].slot, sp) : -1;
+    pu[u].next = (s < 36 && sn < c->n_sectors && sn != s) ? find_unit(c, c->uh[u].slot, sn) : -1;
+  }
+  const int64_t T = std::max<int64_t>(c->trk_total, 1);
+  const int S = (int)c->p2_slot_value.size();
+  RCCHK(p2_ensure(c, U, T, c->n_total, S));
+  RCCHK(copy_sync(c, c->p2units.p, pu.data(), sizeof(P2Unit) * U, hipMemcpyHostToDevice));
+  const P2Params q = p2_dev(c->p2params);
+  const ParamsDev P = p2_prop_params(c);
+  hipError_t e = p2_launch_merge(c->B, c->P2, P, q, U, T, c->stream);
+  if (e != hipSuccess) return dev_err(c, e, "second phase (merge)");
+  RCCHK(copy_sync(c, &c->p2c, c->p2cnt.p, sizeof(P2Counts), hipMemcpyDeviceToHost));
+  const size_t tmp = p2_sort_tmp_bytes(c->p2c.n_cand);
+  RCCHK(ensure(c, c->p2sort_tmp, std::max<size_t>(tmp, 256), 0));
+  e = p2_launch_vertices(c->B, c->P2, P, q, c->p2c.n_final, c->p2c.n_cand, S, c->p2sort_tmp.p,
+                         c->p2sort_tmp.bytes, c->stream);
+  if (e != hipSuccess) return dev_err(c, e, "second phase (vertices)");
+  e = p2_launch_finish(c->B, c->P2, P, q, c->p2c.n_seg, c->p2c.n_final, c->n_total, c->stream);
+  if (e != hipSuccess) return dev_err(c, e, "second phase (flags, compression)");
+  c->p2_done = true;
+  return TPCCA_OK;
+}
+
+int tpcca_get_finals(tpcca_ctx_t *c, int32_t slot, tpcca_final_t *out, int32_t cap, int32_t *n_out,
+                     int32_t *hits, int64_t hits_cap, int64_t *n_hits_out) {
+  RCCHK(p2_ready(c));
+  if (!n_out) return TPCCA_EINVAL;
+  const int nf = c->p2c.n_final;
+  std::vector<tpcca_final_t> all(nf);
+  if (nf) RCCHK(copy_sync(c, all.data(), c->p2finals.p, sizeof(tpcca_final_t) * nf, hipMemcpyDeviceToHost));
+  std::vector<int> mine;
+  int64_t nh = 0;
+  for (int f = 0; f < nf; ++f) {
+    if (c->p2_slot_value[all[f].slot] != slot) continue;
+    mine.push_back(f);
+    nh += all[f].n_hits;
+  }
+  *n_out = (int32_t)mine.size();
+  if (n_hits_out) *n_hits_out = nh;
+  if (cap < (int32_t)mine.size() || (hits && hits_cap < nh)) return TPCCA_ECAPACITY;
+  int64_t off = 0;
+  for (size_t k = 0; k < mine.size(); ++k) {
+    tpcca_final_t o = all[mine[k]];
+    if (hits && o.n_hits)
+      HIPCHK(c, hipMemcpyAsync(hits + off, ptr<int32_t>(c->p2final_hits) + o.hit_begin, sizeof(int32_t) * o.n_hits,
+                               hipMemcpyDeviceToHost, c->stream));
+    o.slot = slot;
+    o.hit_begin = off;
+    off += o.n_hits;
+    if (out) out[k] = o;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TPCCA_OK;
+}
+
+int tpcca_get_segment_links(tpcca_ctx_t *c, int32_t slot, int32_t sector, int32_t *next, int32_t *prev,
+                            int32_t *final_of, int32_t n) {
+  RCCHK(p2_ready(c));
+  const int u = find_unit(c, slot, sector);
+  if (u < 0) return TPCCA_ESTATE;
+  const int U = (int)c->units.size();
+  std::vector<int32_t> sb(U + 1), su;
+  RCCHK(copy_sync(c, sb.data(), c->p2seg_begin.p, sizeof(int32_t) * (U + 1), hipMemcpyDeviceToHost));
+  const int g0 = sb[u], ng = sb[u + 1] - sb[u];
+  if (n != ng) return TPCCA_EINVAL;
+  if (ng == 0) return TPCCA_OK;
+  std::vector<int32_t> nx(ng), pv(ng), fo(ng);
+  RCCHK(copy_sync(c, nx.data(), ptr<int32_t>(c->p2next) + g0, sizeof(int32_t) * ng, hipMemcpyDeviceToHost));
+  RCCHK(copy_sync(c, pv.data(), ptr<int32_t>(c->p2prev) + g0, sizeof(int32_t) * ng, hipMemcpyDeviceToHost));
+  RCCHK(copy_sync(c, fo.data(), ptr<int32_t>(c->p2final_of) + g0, sizeof(int32_t) * ng, hipMemcpyDeviceToHost));
+  // final index among the slot's finals: finals of earlier positions in the slot
+  const int nf = c->p2c.n_final;
+  std::vector<tpcca_final_t> all(nf);
+  if (nf) RCCHK(copy_sync(c, all.data(), c->p2finals.p, sizeof(tpcca_final_t) * nf, hipMemcpyDeviceToHost));
+  std::vector<int32_t> local(nf, -1);
+  int k = 0;
+  for (int f = 0; f < nf; ++f)
+    if (c->p2_slot_value[all[f].slot] == slot) local[f] = k++;
+  auto key = [&](int g) {
+    if (g < 0) return -1;
+    const int v = (int)(std::upper_bound(sb.begin(), sb.end(), g) - sb.begin()) - 1;
+    return (int32_t)(((uint32_t)c->uh[v].sector << 24) | (uint32_t)(g - sb[v]));
+  };
+  for (int i = 0; i < ng; ++i) {
+    if (next) next[i] = key(nx[i]);
+    if (prev) prev[i] = key(pv[i]);
+    if (final_of) final_of[i] = fo[i] >= 0 ? local[fo[i]] : -1;
+  }
+  return TPCCA_OK;
+}
+
+int tpcca_get_vertices(tpcca_ctx_t *c, int32_t slot, tpcca_vertex_t *out, int32_t cap, int32_t *n_out) {
+  RCCHK(p2_ready(c));
+  if (!n_out) return TPCCA_EINVAL;
+  int32_t nv = 0;
+  RCCHK(copy_sync(c, &nv, &c->P2.cnt->n_vtx, sizeof(int32_t), hipMemcpyDeviceToHost));
+  std::vector<tpcca_vertex_t> all(nv);
+  if (nv) RCCHK(copy_sync(c, all.data(), c->p2vertices.p, sizeof(tpcca_vertex_t) * nv, hipMemcpyDeviceToHost));
+  int32_t k = 0;
+  for (auto &v : all) {
+    if (c->p2_slot_value[v.slot] != slot) continue;
+    if (out && k < cap) {
+      out[k] = v;
+      out[k].slot = slot;
+    }
+    ++k;
+  }
+  *n_out = k;
+  return cap < k ? TPCCA_ECAPACITY : TPCCA_OK;
+}
+
+int tpcca_get_flags(tpcca_ctx_t *c, int32_t slot, int32_t sector, uint8_t *flags, int32_t n) {
+  RCCHK(p2_ready(c));
+  const int u = find_unit(c, slot, sector);
+  if (u < 0) return TPCCA_ESTATE;
+  if (!flags || n != c->uh[u].n) return TPCCA_EINVAL;
+  if (n) RCCHK(copy_sync(c, flags, ptr<uint8_t>(c->p2flags) + c->units[u].cl_begin, (size_t)n, hipMemcpyDeviceToHost));
+  return TPCCA_OK;
+}
+
+int tpcca_get_compressed(tpcca_ctx_t *c, int32_t slot, int32_t sector, int32_t *rec, int32_t seg_cap,
+                         int32_t *res, int64_t hits_cap, int32_t *n_seg, int64_t *n_hits) {
+  RCCHK(p2_ready(c));
+  const int u = find_unit(c, slot, sector);
+  if (u < 0) return TPCCA_ESTATE;
+  if (!n_seg) return TPCCA_EINVAL;
+  int32_t sb[2];
+  RCCHK(copy_sync(c, sb, ptr<int32_t>(c->p2seg_begin) + u, sizeof(sb), hipMemcpyDeviceToHost));
+  tpcca_unit_result_t r;
+  RCCHK(copy_sync(c, &r, ptr<tpcca_unit_result_t>(c->unit_res) + u, sizeof(r), hipMemcpyDeviceToHost));
+  *n_seg = sb[1] - sb[0];
+  if (n_hits) *n_hits = r.n_track_hits;
+  if ((rec && seg_cap < *n_seg) || (res && hits_cap < r.n_track_hits)) return TPCCA_ECAPACITY;
+  if (rec && *n_seg)
+    RCCHK(copy_sync(c, rec, ptr<int32_t>(c->p2rec) + 6 * (int64_t)sb[0], sizeof(int32_t) * 6 * (size_t)*n_seg,
+                    hipMemcpyDeviceToHost));
+  if (res && r.n_track_hits)
+    RCCHK(copy_sync(c, res, ptr<int32_t>(c->p2res) + 3 * r.hit_begin, sizeof(int32_t) * 3 * (size_t)r.n_track_hits,
+                    hipMemcpyDeviceToHost));
+  return TPCCA_OK;
+}
+
+int tpcca_phase2_view(tpcca_ctx_t *c, tpcca_phase2_view_t *out) {
+  RCCHK(p2_ready(c));
+  if (!out) return TPCCA_EINVAL;
+  RCCHK(copy_sync(c, &c->p2c, c->p2cnt.p, sizeof(P2Counts), hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof(*out));
+  out->n_seg = c->p2c.n_seg;
+  out->n_final = c->p2c.n_final;
+  out->n_vertices = c->p2c.n_cand > 0 ? c->p2c.n_vtx : 0;
+  out->n_final_hits = c->p2c.n_final_hits;
+  out->finals = ptr<tpcca_final_t>(c->p2finals);
+  out->final_hits = ptr<int32_t>(c->p2final_hits);
+  out->vertices = ptr<tpcca_vertex_t>(c->p2vertices);
+  out->flags = ptr<uint8_t>(c->p2flags);
+  out->rec = ptr<int32_t>(c->p2rec);
+  out->res = ptr<int32_t>(c->p2res);
+  out->seg_n_hits = ptr<int32_t>(c->p2seg_nh);
+  out->seg_hit_begin = ptr<int64_t>(c->p2seg_hb);
+  return TPCCA_OK;
+}
+
+int tpcca_decompress(tpcca_ctx_t *c, int32_t n_seg, const int32_t *n_hits, const int64_t *hit_begin,
+                     const int32_t *rec, const int32_t *res, int32_t *yq, int32_t *zq, uint8_t *rows) {
+  if (!c || n_seg < 0) return TPCCA_EINVAL;
+  if (n_seg > 0 && (!n_hits || !hit_begin || !rec || !res || !yq || !zq || !rows)) return TPCCA_EINVAL;
+  hipSetDevice(c->device);
+  const P2Params q = p2_dev(c->p2params);
+  hipError_t e = p2_launch_decompress(p2_prop_params(c), q, ptr<float>(c->row_x_d), n_seg, n_hits, hit_begin, rec,
+                                      res, yq, zq, rows, c->stream);
+  if (e != hipSuccess) return dev_err(c, e, "decompress");
+  return TPCCA_OK;
+}
+
+}  // extern "C"

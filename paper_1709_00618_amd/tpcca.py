@@ -87,6 +87,34 @@ class Stats(ctypes.Structure):
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double)]
 
 
+class Phase2Params(ctypes.Structure):
+    _fields_ = [
+        ("sector_cos", c_f32), ("sector_sin", c_f32), ("max_sinphi", c_f32), ("merge_dz_ends", c_f32),
+        ("merge_max_gap", c_i32), ("merge_wy", c_f32), ("merge_wz", c_f32), ("merge_chi2", c_f32),
+        ("refit_inflate", c_f32), ("dca_steps", c_i32), ("vdrift", c_f32), ("vtx_gap_us", c_f32),
+        ("vtx_min_tracks", c_i32), ("vtx_min_hits", c_i32), ("vtx_attach_us", c_f32), ("cmp_qy", c_f32),
+        ("cmp_qz", c_f32), ("cmp_c22", c_f32), ("cmp_c33", c_f32), ("cmp_c44", c_f32), ("rej_qpt", c_f32),
+        ("rej_looper_qpt", c_f32), ("rej_sinphi", c_f32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Phase2View(ctypes.Structure):
+    _fields_ = [("n_seg", c_i32), ("n_final", c_i32), ("n_vertices", c_i32), ("pad_", c_i32),
+                ("n_final_hits", c_i64), ("finals", c_vp), ("final_hits", c_vp), ("vertices", c_vp),
+                ("flags", c_vp), ("rec", c_vp), ("res", c_vp), ("seg_n_hits", c_vp), ("seg_hit_begin", c_vp)]
+
+
+FINAL_DTYPE = np.dtype([("slot", "i4"), ("sector", "i4"), ("status", "i4"), ("n_seg", "i4"), ("n_hits", "i4"),
+                        ("ndf", "i4"), ("row_ref", "i4"), ("vertex", "i4"), ("z0_ok", "i4"), ("first_seg", "i4"),
+                        ("hit_begin", "i8"), ("x_ref", "f4"), ("chi2", "f4"), ("p", "f4", 5), ("cov", "f4", 15),
+                        ("z0", "f4"), ("t0", "f4"), ("z_conv", "f4"), ("pad_", "i4")])
+VERTEX_DTYPE = np.dtype([("slot", "i4"), ("n_tracks", "i4"), ("first", "i4"), ("t0", "f4")])
+assert FINAL_DTYPE.itemsize == 152 and VERTEX_DTYPE.itemsize == 16
+FLAG_LOWPT, FLAG_LEG, FLAG_INCL = 1, 2, 4
+
 TRACK_DTYPE = np.dtype([("x_ref", "f4"), ("p", "f4", 5), ("cov", "f4", 15), ("chi2", "f4"), ("ndf", "i4"),
                         ("n_hits", "i4"), ("hit_offset", "i4"), ("sector", "i4"), ("start_id", "i4")])
 TRACKLET_DTYPE = np.dtype([("start_id", "i4"), ("n_chain", "i4"), ("status", "i4"), ("n_hits", "i4"),
@@ -110,6 +138,9 @@ SYMBOLS = (
     "tpcca_server_last_error",
     "tpcca_work_stats", "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_server_set_tuning",
     "tpcca_tuning_default", "tpcca_run_batch_noalloc",
+    "tpcca_phase2_params_default", "tpcca_set_phase2_params", "tpcca_phase2", "tpcca_get_finals",
+    "tpcca_get_segment_links", "tpcca_get_vertices", "tpcca_get_flags", "tpcca_get_compressed",
+    "tpcca_phase2_view", "tpcca_decompress",
 )
 
 _lib = None
@@ -169,6 +200,18 @@ def lib():
         "tpcca_run_batch_noalloc": (c_i32, [ctypes.POINTER(Geometry), ctypes.POINTER(Params), c_i32, c_vp,
                                             ctypes.POINTER(Batch), c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp,
                                             ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
+        "tpcca_phase2_params_default": (None, [ctypes.POINTER(Phase2Params)]),
+        "tpcca_set_phase2_params": (c_i32, [c_vp, ctypes.POINTER(Phase2Params)]),
+        "tpcca_phase2": (c_i32, [c_vp]),
+        "tpcca_get_finals": (c_i32, [c_vp, c_i32, c_vp, c_i32, ctypes.POINTER(c_i32), c_vp, c_i64,
+                                     ctypes.POINTER(c_i64)]),
+        "tpcca_get_segment_links": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_vp, c_vp, c_i32]),
+        "tpcca_get_vertices": (c_i32, [c_vp, c_i32, c_vp, c_i32, ctypes.POINTER(c_i32)]),
+        "tpcca_get_flags": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_i32]),
+        "tpcca_get_compressed": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_i32, c_vp, c_i64, ctypes.POINTER(c_i32),
+                                         ctypes.POINTER(c_i64)]),
+        "tpcca_phase2_view": (c_i32, [c_vp, ctypes.POINTER(Phase2View)]),
+        "tpcca_decompress": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     }
     missing = [n for n in SYMBOLS if not hasattr(L, n)]
     if missing:
@@ -387,12 +430,81 @@ class Context:
     def set_timing(self, on=True):
         lib().tpcca_set_timing(self.h, 1 if on else 0)
 
+    # second phase (merging and refit, vertices, compression, rejection flags)
+    def set_phase2_params(self, **kw):
+        q = phase2_params_default(**kw)
+        _check(lib().tpcca_set_phase2_params(self.h, ctypes.byref(q)), "tpcca_set_phase2_params", self.h)
+
+    def phase2(self):
+        _check(lib().tpcca_phase2(self.h), "tpcca_phase2", self.h)
+
+    def get_finals(self, slot):
+        n, nh = c_i32(), c_i64()
+        st = lib().tpcca_get_finals(self.h, slot, None, 0, ctypes.byref(n), None, 0, ctypes.byref(nh))
+        if st not in (OK, ECAPACITY):
+            _check(st, "tpcca_get_finals", self.h)
+        out = np.zeros(max(1, n.value), FINAL_DTYPE)
+        hits = np.zeros(max(1, nh.value), np.int32)
+        _check(lib().tpcca_get_finals(self.h, slot, _p(out), out.shape[0], ctypes.byref(n), _p(hits), hits.shape[0],
+                                      ctypes.byref(nh)), "tpcca_get_finals", self.h)
+        return out[:n.value], hits[:nh.value]
+
+    def get_segment_links(self, slot, sector, n):
+        nx, pv, fo = (np.zeros(max(1, n), np.int32) for _ in range(3))
+        _check(lib().tpcca_get_segment_links(self.h, slot, sector, _p(nx), _p(pv), _p(fo), n),
+               "tpcca_get_segment_links", self.h)
+        return nx[:n], pv[:n], fo[:n]
+
+    def get_vertices(self, slot):
+        n = c_i32()
+        st = lib().tpcca_get_vertices(self.h, slot, None, 0, ctypes.byref(n))
+        if st not in (OK, ECAPACITY):
+            _check(st, "tpcca_get_vertices", self.h)
+        out = np.zeros(max(1, n.value), VERTEX_DTYPE)
+        _check(lib().tpcca_get_vertices(self.h, slot, _p(out), out.shape[0], ctypes.byref(n)), "tpcca_get_vertices",
+               self.h)
+        return out[:n.value]
+
+    def get_flags(self, slot, sector, n):
+        f = np.zeros(max(1, n), np.uint8)
+        _check(lib().tpcca_get_flags(self.h, slot, sector, _p(f), n), "tpcca_get_flags", self.h)
+        return f[:n]
+
+    def get_compressed(self, slot, sector):
+        ns, nh = c_i32(), c_i64()
+        st = lib().tpcca_get_compressed(self.h, slot, sector, None, 0, None, 0, ctypes.byref(ns), ctypes.byref(nh))
+        if st not in (OK, ECAPACITY):
+            _check(st, "tpcca_get_compressed", self.h)
+        rec = np.zeros((max(1, ns.value), 6), np.int32)
+        res = np.zeros((max(1, nh.value), 3), np.int32)
+        _check(lib().tpcca_get_compressed(self.h, slot, sector, _p(rec), rec.shape[0], _p(res), res.shape[0],
+                                          ctypes.byref(ns), ctypes.byref(nh)), "tpcca_get_compressed", self.h)
+        return rec[:ns.value], res[:nh.value]
+
+    def phase2_view(self) -> Phase2View:
+        v = Phase2View()
+        _check(lib().tpcca_phase2_view(self.h, ctypes.byref(v)), "tpcca_phase2_view", self.h)
+        return v
+
+    def decompress(self, n_seg, n_hits, hit_begin, rec, res, yq, zq, rows):
+        """Device pointers (ints) or tensors; queued on the context's stream."""
+        _check(lib().tpcca_decompress(self.h, n_seg, _p(n_hits), _p(hit_begin), _p(rec), _p(res), _p(yq), _p(zq),
+                                      _p(rows)), "tpcca_decompress", self.h)
+
     STAGES = ("grid", "links", "clean", "chains", "fit", "select")
 
     def stage_times(self):
         ms = np.zeros(6, np.float32)
         n = lib().tpcca_stage_times(self.h, _p(ms), 6)
         return dict(zip(self.STAGES, ms[:n].tolist()))
+
+
+def phase2_params_default(**over) -> Phase2Params:
+    q = Phase2Params()
+    lib().tpcca_phase2_params_default(ctypes.byref(q))
+    for k, v in over.items():
+        setattr(q, k, v)
+    return q
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # TPCCA_NOALLOC_SCRATCH_BYTES

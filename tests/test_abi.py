@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     text = open(os.path.join(ROOT, "include", "tpcca.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tpcca_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(tpcca_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -39,6 +39,14 @@ def test_defaults_match_the_oracle_reading():
     for name, _ in oracle.Params._fields_:
         assert np.float32(getattr(g, name)) == np.float32(getattr(o, name)), name
     assert g.grid_hits_per_bin >= 1
+
+
+def test_phase2_defaults_match_the_oracle_reading():
+    g = tpcca.phase2_params_default()
+    o = oracle.default_p2params()
+    for name, _ in oracle.P2Params._fields_:
+        assert np.float32(getattr(g, name)) == np.float32(getattr(o, name)), name
+    assert [n for n, _ in tpcca.Phase2Params._fields_] == [n for n, _ in oracle.P2Params._fields_]
 
 
 def test_error_strings():
