@@ -215,6 +215,14 @@ def main():
             f"{ncl / pipe_dt / 1e9:.3f} G clusters/s")
     value = ncl / pipe_dt
 
+    # -------------------------------- second phase on the resident frame
+    # merging of the sector segments and refit (Sec. 2), vertex times
+    # (Sec. 5), rejection flags and track-model compression (Sec. 3), run on
+    # the tracks the frame's batch left in HBM (no host transfer)
+    phase2 = None
+    if not args.profile:
+        phase2 = bench_phase2(ctx, dcl, drow, tf, args, log)
+
     # --------------------------------------------- per-event plain path
     pe = tpcca.Context(rx, device=0)
 
@@ -319,6 +327,11 @@ def main():
                "b_ns_per_cluster": round(float(b_) * 1e6, 5), "r2": round(r2, 5)}
         log(f"time vs size: t = {a_:.3f} ms + {b_ * 1e6:.4f} ns x N (r2 {r2:.4f})")
 
+    # ---------------------------------- 64 minimum-bias events, one launch
+    mb64 = None
+    if not args.profile:
+        mb64 = bench_minbias64(rx, tpcca, torch, args, log, knobs)
+
     # ------------------------------------------------------------ served
     served = None
     if args.served_tfs > 0:
@@ -387,6 +400,10 @@ def main():
                       "value": round(per_event, 1), "unit": "clusters/s", "ms_per_event": round(pe_dt * 1e3, 4)},
         "batched_over_per_event": round(value / per_event, 3),
         "host_resident": host_res,
+        "served_over_per_event": (round(served["capacity"]["clusters_per_s"] / host_res["per_event"]["value"], 3)
+                                  if served and host_res else None),
+        "phase2": phase2,
+        "batched_minbias64": mb64,
         "linear_scaling": lin,
         "served": served,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
@@ -686,6 +703,161 @@ def write_ceilings(text):
     with open(path, "w") as f:
         f.write("\n".join(md))
     print(f"wrote {path}")
+
+
+def _entropy_bits(v):
+    """Zeroth-order empirical entropy (bits per symbol) of an integer array."""
+    v = np.asarray(v, np.int64).ravel()
+    if v.size == 0:
+        return 0.0
+    _, c = np.unique(v, return_counts=True)
+    p = c / c.sum()
+    return float(-(p * np.log2(p)).sum())
+
+
+def bench_phase2(ctx, dcl, drow, tf, args, log):
+    """The second phase on the frame the context tracked last: its time per
+    call (the kernels and one wait for the number of final tracks), what it
+    produced, and the entropy of the track-model residuals against that of
+    the stored coordinates."""
+    ctx.run_batch(dcl, drow, tf.units, device=True, graph=True)
+    ctx.sync()
+    for _ in range(2):
+        ctx.phase2()
+        ctx.sync()
+    reps = max(5, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.phase2()
+        ctx.sync()
+    p2_dt = (time.perf_counter() - t0) / reps
+    finals, _ = ctx.get_finals(0)
+    verts = ctx.get_vertices(0)
+    units, _, hits, _ = ctx.get_batch_results()
+    nseg = int(units["n_tracks"].sum())
+    flags = np.concatenate([ctx.get_flags(0, int(u[3]), int(u[1])) for u in tf.units])
+    # entropy: stored (quantised) coordinates of every cluster against the
+    # track model (rows steps and residuals of the clusters on tracks, the
+    # first cluster of a segment stored as it is plus its three FP32 values)
+    q = np.float32(0.01)
+    yq_all = np.rint(tf.cl[:, 1] / q).astype(np.int64)
+    zq_all = np.rint(tf.cl[:, 2] / q).astype(np.int64)
+    h_abs = _entropy_bits(yq_all) + _entropy_bits(zq_all) + _entropy_bits(tf.row)
+    res_all, rec_all = [], []
+    for u in tf.units:
+        rec, res = ctx.get_compressed(0, int(u[3]))
+        rec_all.append(rec)
+        res_all.append(res)
+    rec = np.concatenate(rec_all)
+    res = np.concatenate(res_all)
+    first = np.zeros(res.shape[0], bool)
+    # the first hit of each segment holds zeros: locate them from the segments' hit counts
+    seg_nh = np.concatenate([ctx.get_tracks(0, int(u[3]))[0]["n_hits"] for u in tf.units])
+    first[np.r_[0, np.cumsum(seg_nh)[:-1]]] = True
+    rest = res[~first]
+    h_model_hit = _entropy_bits(rest[:, 0]) + _entropy_bits(rest[:, 1]) + _entropy_bits(rest[:, 2])
+    n_on = int(res.shape[0])
+    n_off = int(tf.n_clusters) - n_on
+    bits_abs = h_abs * tf.n_clusters
+    bits_model = h_model_hit * (n_on - nseg) + nseg * (h_abs + 96.0) + n_off * h_abs
+    out = {
+        "workload": "the resident 128-event time frame's accepted tracks (sector segments)",
+        "ms": round(p2_dt * 1e3, 4),
+        "segments": nseg, "final_tracks": int(finals.shape[0]),
+        "merged_segments": int(nseg - finals.shape[0]),
+        "refit_failures": int((finals["status"] != 0).sum()),
+        "vertices": int(verts.shape[0]), "events_in_frame": int(len(tf.meta["t0_us"])),
+        "tracks_with_vertex": int((finals["vertex"] >= 0).sum()),
+        "flagged_clusters": {"low_pt": int(((flags & 1) != 0).sum()), "looper_leg": int(((flags & 2) != 0).sum()),
+                             "inclined": int(((flags & 4) != 0).sum()), "any": int((flags != 0).sum()),
+                             "of": int(tf.n_clusters)},
+        "compression": {"bits_per_cluster_stored_coordinates": round(h_abs, 3),
+                        "bits_per_track_hit_model": round(h_model_hit, 3),
+                        "bits_per_cluster_with_model": round(bits_model / tf.n_clusters, 3),
+                        "gain": round(bits_abs / bits_model, 3),
+                        "basis": "zeroth-order empirical entropy of the frame's symbols; 0.01 cm steps"},
+    }
+    log(f"second phase: {out}")
+    return out
+
+
+def bench_minbias64(rx, tpcca, torch, args, log, knobs):
+    """64 minimum-bias events (10 to 8000 tracks) as one batch of 2304 units
+    in one launch per kernel (graph replay), one and two batches in flight,
+    against the same events one launch sequence per event, and the oracle
+    on a sample of the units."""
+    import tpcgen
+    b = tpcgen.minbias_batch(seed=0, n_events=64)
+    dcl = torch.from_numpy(b.cl).cuda()
+    drow = torch.from_numpy(b.row).cuda()
+    torch.cuda.synchronize()
+    cx = [tpcca.Context(rx, device=0), tpcca.Context(rx, device=0)]
+    for c in cx:
+        c.set_tuning(**knobs)
+    for _ in range(args.warmup):
+        cx[0].run_batch(dcl, drow, b.units, device=True, graph=True)
+        cx[0].sync()
+    steps = max(args.steps, 10)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cx[0].run_batch(dcl, drow, b.units, device=True, graph=True)
+        cx[0].sync()
+    one_dt = (time.perf_counter() - t0) / steps
+    _, ncl, ntr, _ = cx[0].batch_totals()
+    for i in range(2 * args.warmup):
+        cx[i % 2].run_batch(dcl, drow, b.units, device=True, graph=True)
+    for c in cx:
+        c.sync()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        cx[i % 2].run_batch(dcl, drow, b.units, device=True, graph=True)
+    for c in cx:
+        c.sync()
+    two_dt = (time.perf_counter() - t0) / steps
+    # the same events, one plain launch sequence per event
+    pe = cx[0]
+    slots = np.unique(b.units[:, 2])
+
+    def per_event_pass():
+        for ev in slots:
+            pe.reset()
+            for u in np.nonzero(b.units[:, 2] == ev)[0]:
+                beg, n, slot, sec = (int(v) for v in b.units[u])
+                pe.load_sector(slot, sec, dcl[beg:beg + n], drow[beg:beg + n], device=True)
+            pe.run_all(int(ev), -1)
+            pe.sync()
+    per_event_pass()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        per_event_pass()
+    pe_dt = (time.perf_counter() - t0) / 3
+    for c in cx:
+        c.close()
+    # the oracle on every 9th unit, 16 threads
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    cores = max(1, min(16, os.cpu_count() or 1))
+    sample = list(range(0, b.units.shape[0], 9))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        done = sum(ex.map(lambda u: (oracle.run_sector(b.unit(u)[0], b.unit(u)[1], rx, precision=32),
+                                     int(b.units[u, 1]))[1], sample))
+    or_dt = time.perf_counter() - t0
+    out = {"workload": f"64 minimum-bias Pb-Pb events ({int(b.meta['multiplicity'].min())}.."
+                       f"{int(b.meta['multiplicity'].max())} tracks), {b.units.shape[0]} units, {ncl} clusters, "
+                       "one launch per kernel (graph replay), device-resident",
+           "units": int(b.units.shape[0]), "clusters": int(ncl), "tracks": int(ntr),
+           "value": round(ncl / two_dt, 1), "unit": "clusters/s", "ms": round(two_dt * 1e3, 4), "in_flight": 2,
+           "one_in_flight": {"value": round(ncl / one_dt, 1), "ms": round(one_dt * 1e3, 4)},
+           "per_event": {"value": round(ncl / pe_dt, 1), "ms_for_64_events": round(pe_dt * 1e3, 3),
+                         "basis": "the same 64 events, one launch sequence per event"},
+           "batched_over_per_event": round(pe_dt / two_dt, 3),
+           "oracle": {"value": round(done / or_dt, 1), "unit": "clusters/s", "cores": cores,
+                      "sample": f"every 9th unit ({len(sample)} units, {done} clusters), FP32 oracle, "
+                                f"{or_dt:.1f} s"}}
+    log(f"64 minimum-bias events: {out}")
+    return out
 
 
 def cpu_baseline(ev, rx, seconds):

@@ -42,6 +42,7 @@ struct P2Out {
 struct P2Counts {
   int32_t n_seg, n_final, n_cand, n_group, n_vtx, n_slots;
   int64_t n_final_hits;
+  int64_t n_pairs;               // candidate pairs of the merge
 };
 
 struct P2Bufs {
@@ -59,6 +60,9 @@ struct P2Bufs {
   int32_t *bin_cnt;              // units x kP2Bins
   int32_t *bin_beg;              // units x (kP2Bins + 1), unit-local offsets
   int32_t *bin_seg;              // segments in bin order (unit u at seg_begin[u])
+  int2 *bin_rz;                  // (first won row, bits of inner z) in bin order
+  float4 *hrec;                  // per hit position: y, z, row and cluster ID (as bits)
+  float4 *seg_flag;              // per segment: kB q/pT, x_ref, sin phi, final-track flags (bits)
   unsigned long long *best_b;    // per A: (chi2 bits << 32) | key of its best B
   unsigned long long *best_a;    // per B: (chi2 bits << 32) | key of its best A
   int32_t *next, *prev;          // merge links (segment indices)
@@ -83,7 +87,11 @@ struct P2Bufs {
 };
 
 hipError_t p2_launch_merge(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, const P2Params &q,
-                           int n_units, int64_t seg_cap, hipStream_t s);
+                           int n_units, int64_t seg_cap, int64_t hit_span, hipStream_t s);
+// the candidate pairs (after p2_launch_merge counted them), merge links,
+// final tracks and their refit, vertex candidates
+hipError_t p2_launch_pairs(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, const P2Params &q, int64_t seg_cap,
+                           int2 *pairs, int64_t n_pairs, hipStream_t s);
 hipError_t p2_launch_vertices(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, const P2Params &q,
                               int32_t n_final, int32_t n_cand, int32_t n_slots, void *sort_tmp,
                               size_t sort_tmp_bytes, hipStream_t s);

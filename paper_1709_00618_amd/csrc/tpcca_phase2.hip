@@ -148,7 +148,7 @@ __device__ __forceinline__ int p2_bin(const int2 &zm, float z) {
 
 // ---------------------------------------------------------- segments ---
 // Segment index of every unit (one block): seg_begin = exclusive scan of the
-// units' accepted track counts; clears the per-unit z ranges.
+// units' accepted track counts.
 __global__ __launch_bounds__(1024) void k_p2_seg_index(Bufs B, P2Bufs Q) {
   __shared__ int64_t lds[1024 / 64 + 1];
   int64_t carry = 0;
@@ -157,15 +157,37 @@ __global__ __launch_bounds__(1024) void k_p2_seg_index(Bufs B, P2Bufs Q) {
     const int64_t v = u < Q.n_units ? B.unit_res[u].n_tracks : 0;
     int64_t tot;
     const int64_t ex = block_exclusive_scan<int64_t>(v, lds, &tot);
-    if (u < Q.n_units) {
-      Q.seg_begin[u] = (int32_t)(carry + ex);
-      Q.zmm[u] = make_int2(0x7FFFFFFF, (int)0x80000000);
-    }
+    if (u < Q.n_units) Q.seg_begin[u] = (int32_t)(carry + ex);
     carry += tot;
   }
   if (threadIdx.x == 0) {
     Q.seg_begin[Q.n_units] = (int32_t)carry;
     Q.cnt->n_seg = (int32_t)carry;
+  }
+}
+
+// Per hit position of the track hit array: the hit's y, z, pad row and
+// cluster ID gathered once (one coalesced pass), so that the per-track
+// kernels below read their hits contiguously instead of chasing cluster IDs.
+__global__ __launch_bounds__(256) void k_p2_hits(Bufs B, P2Bufs Q) {
+  const int U = Q.n_units;
+  const int64_t h_lo = B.unit_res[0].hit_begin;
+  const int64_t h_hi = B.unit_res[U - 1].hit_begin + B.unit_res[U - 1].n_track_hits;
+  for (int64_t h = h_lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < h_hi;
+       h += (int64_t)gridDim.x * blockDim.x) {
+    // unit whose hit range holds h (ranges ascend with the unit; runs leave gaps)
+    int lo = 0, hi = U;
+    while (hi - lo > 1) {
+      const int m = (lo + hi) >> 1;
+      if (B.unit_res[m].hit_begin <= h) lo = m;
+      else hi = m;
+    }
+    const tpcca_unit_result_t &r = B.unit_res[lo];
+    if (h >= r.hit_begin + r.n_track_hits) continue;
+    const UnitDev U_ = B.units[lo];
+    const int id = B.hits_out[h];
+    const float4 c = U_.cl[id];
+    Q.hrec[h] = make_float4(c.y, c.z, __int_as_float((int)U_.row[id]), __int_as_float(id));
   }
 }
 
@@ -176,17 +198,20 @@ __global__ __launch_bounds__(256) void k_p2_seg_prep(Bufs B, P2Bufs Q, ParamsDev
   const int n = Q.cnt->n_seg;
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
     const int u = p2_unit_of(Q, g);
-    const UnitDev U = B.units[u];
     const tpcca_track_t &t = p2_track(B, Q, g, u);
     const int64_t h0 = p2_hit0(B, t, u);
+    const int nh = t.n_hits;
     KState st = p2_inner(t);
     bool ok = true;
-    int r_first = 0, r_last = 0;
-    for (int k = 0; k < t.n_hits; ++k) {
-      const int r = U.row[B.hits_out[h0 + k]];
-      if (k == 0) r_first = r;
-      r_last = r;
-      if (ok && !kf_propagate(P, st, B.row_x[r])) ok = false;
+    const float4 *hr = Q.hrec + h0;
+    const int r_first = __float_as_int(hr[0].z);
+    int r_last = r_first;
+    float4 nxt = hr[0];
+    for (int k = 0; k < nh; ++k) {
+      const float4 cur = nxt;
+      if (k + 1 < nh) nxt = hr[k + 1];  // the next record's load overlaps this step
+      r_last = __float_as_int(cur.z);
+      if (ok && !kf_propagate(P, st, B.row_x[r_last])) ok = false;
     }
     P2Out o;
     o.x = st.x;
@@ -197,7 +222,7 @@ __global__ __launch_bounds__(256) void k_p2_seg_prep(Bufs B, P2Bufs Q, ParamsDev
     o.ok = ok ? 1 : 0;
     Q.seg_out[g] = o;
     Q.seg_unit[g] = u;
-    Q.seg_nh[g] = t.n_hits;
+    Q.seg_nh[g] = nh;
     Q.seg_hb[g] = h0;
     Q.seg_rows[g] = make_int2(r_first, r_last);
     const float zr = t.p[1];
@@ -207,8 +232,32 @@ __global__ __launch_bounds__(256) void k_p2_seg_prep(Bufs B, P2Bufs Q, ParamsDev
     Q.best_b[g] = ~0ull;
     Q.next[g] = -1;
     Q.prev[g] = -1;
-    atomicMin(&Q.zmm[u].x, ord_i(zr));
-    atomicMax(&Q.zmm[u].y, ord_i(zr));
+  }
+}
+
+// z range of each unit's inner z values (one block per unit, no atomics)
+__global__ __launch_bounds__(256) void k_p2_zrange(P2Bufs Q) {
+  __shared__ int lmin[4], lmax[4];
+  for (int u = blockIdx.x; u < Q.n_units; u += gridDim.x) {
+    int mn = 0x7FFFFFFF, mx = (int)0x80000000;
+    for (int g = Q.seg_begin[u] + (int)threadIdx.x; g < Q.seg_begin[u + 1]; g += blockDim.x) {
+      const int o = ord_i(Q.seg_zin[g]);
+      mn = min(mn, o);
+      mx = max(mx, o);
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+      mn = min(mn, __shfl_xor(mn, d, 64));
+      mx = max(mx, __shfl_xor(mx, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      lmin[threadIdx.x >> 6] = mn;
+      lmax[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      Q.zmm[u] = make_int2(min(min(lmin[0], lmin[1]), min(lmin[2], lmin[3])),
+                           max(max(lmax[0], lmax[1]), max(lmax[2], lmax[3])));
+    __syncthreads();
   }
 }
 
@@ -243,6 +292,7 @@ __global__ __launch_bounds__(256) void k_p2_bin_scatter(P2Bufs Q) {
     const int u = Q.seg_unit[g];
     const int pos = atomicAdd(&Q.bin_cnt[(int64_t)u * kP2Bins + p2_bin(Q.zmm[u], Q.seg_zin[g])], 1);
     Q.bin_seg[Q.seg_begin[u] + pos] = g;
+    Q.bin_rz[Q.seg_begin[u] + pos] = make_int2(Q.seg_rows[g].x, __float_as_int(Q.seg_zin[g]));
   }
 }
 
@@ -254,67 +304,96 @@ __device__ __forceinline__ uint32_t p2_key(const P2Bufs &Q, int g, int u, int se
 }
 
 // ------------------------------------------------------------- pairing ---
-// One thread per segment A with an outer end: every B of the two
-// neighbouring units whose inner z lies within merge_dz_ends of A's outer z
-// (z-binned index; the exact tests follow) is tested; A keeps its best B,
-// and each B the best A through a 64-bit atomic minimum of (chi^2 bits, key).
-__global__ __launch_bounds__(256) void k_p2_pairs(Bufs B, P2Bufs Q, ParamsDev P, P2Params q) {
+// Candidate pairs are enumerated per segment A with an outer end: every B of
+// the two neighbouring units whose inner z lies within merge_dz_ends of A's
+// outer z (the z-binned index, read as compact (row, z) records) and whose
+// first won row follows A's last by 1 to merge_max_gap.  The enumeration
+// runs twice, first counting each A's candidates, then (after a scan gives
+// the offsets) writing the pairs, which a third kernel tests one per thread:
+// the expensive test then never leaves lanes of a wave waiting for the few
+// lanes whose A has a candidate.
+template <typename Fn>
+__device__ __forceinline__ void p2_candidates(const P2Bufs &Q, const P2Params &q, int a, Fn &&fn) {
+  const P2Out &oa = Q.seg_out[a];
+  if (!oa.ok) return;
+  const int ua = Q.seg_unit[a];
+  const P2Unit UA = Q.units[ua];
+  const float zA = Q.seg_zout[a];
+  const int rowA = Q.seg_rows[a].y;
+  for (int side = 0; side < 2; ++side) {
+    const int ub = side == 0 ? UA.prev : UA.next;
+    if (ub < 0) continue;
+    if (Q.seg_begin[ub + 1] == Q.seg_begin[ub]) continue;
+    const int2 zm = Q.zmm[ub];
+    const float pad = 1e-3f + 1e-6f * fabsf(zA);
+    const int b0 = p2_bin(zm, zA - q.dz_ends - pad), b1 = p2_bin(zm, zA + q.dz_ends + pad);
+    const int32_t *beg = Q.bin_beg + (int64_t)ub * (kP2Bins + 1);
+    const int i0 = Q.seg_begin[ub] + beg[b0], i1 = Q.seg_begin[ub] + beg[b1 + 1];
+    for (int i = i0; i < i1; ++i) {
+      const int2 rz = Q.bin_rz[i];
+      const int gap = rz.x - rowA;
+      if (gap < 1 || gap > q.max_gap) continue;
+      if (!(fabsf(__int_as_float(rz.y) - zA) <= q.dz_ends)) continue;
+      fn(i);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_p2_pair_count(P2Bufs Q, P2Params q, int32_t *count) {
   const int n = Q.cnt->n_seg;
   for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
+    int c = 0;
+    p2_candidates(Q, q, a, [&](int) { ++c; });
+    count[a] = c;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_p2_pair_fill(P2Bufs Q, P2Params q, const int64_t *begin, int2 *pairs) {
+  const int n = Q.cnt->n_seg;
+  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
+    int64_t w = begin[a];
+    p2_candidates(Q, q, a, [&](int i) { pairs[w++] = make_int2(a, Q.bin_seg[i]); });
+  }
+}
+
+// One pair per thread: B's inner state rotated into A's frame, A's outer end
+// propagated to that plane, windows and the chi^2 of the difference; A keeps
+// its best B and B its best A through 64-bit atomic minima of (chi^2 bits,
+// key).
+__global__ __launch_bounds__(256) void k_p2_pair_eval(Bufs B, P2Bufs Q, ParamsDev P, P2Params q, const int2 *pairs,
+                                                      int64_t n_pairs) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_pairs;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int2 pr = pairs[k];
+    const int a = pr.x, b = pr.y;
+    const int ua = Q.seg_unit[a], ub = Q.seg_unit[b];
+    const int sa_sec = Q.units[ua].sector, sb_sec = Q.units[ub].sector;
+    const float zrA = Q.seg_zin[a], zrB = Q.seg_zin[b];
+    const tpcca_track_t &tb = B.tracks[B.unit_res[ub].track_begin + (b - Q.seg_begin[ub])];
+    KState sb = p2_inner(tb);
+    const float sn = p2_next_sector(sa_sec) == sb_sec ? q.sn : -q.sn;
+    if (!p2_rotate(q.max_sin, q.cs, sn, sb)) continue;
     const P2Out &oa = Q.seg_out[a];
-    if (!oa.ok) continue;
-    const int ua = Q.seg_unit[a];
-    const P2Unit UA = Q.units[ua];
-    const float zrA = Q.seg_zin[a];
-    const float zA = Q.seg_zout[a];
-    const int rowA = Q.seg_rows[a].y;
-    const uint32_t keyA = p2_key(Q, a, ua, UA.sector);
-    unsigned long long best = ~0ull;
-    for (int side = 0; side < 2; ++side) {
-      const int ub = side == 0 ? UA.prev : UA.next;
-      if (ub < 0) continue;
-      const P2Unit UB = Q.units[ub];
-      const int nb = Q.seg_begin[ub + 1] - Q.seg_begin[ub];
-      if (nb == 0) continue;
-      const int2 zm = Q.zmm[ub];
-      const float pad = 1e-3f + 1e-6f * fabsf(zA);
-      const int b0 = p2_bin(zm, zA - q.dz_ends - pad), b1 = p2_bin(zm, zA + q.dz_ends + pad);
-      const int32_t *beg = Q.bin_beg + (int64_t)ub * (kP2Bins + 1);
-      const int i0 = Q.seg_begin[ub] + beg[b0], i1 = Q.seg_begin[ub] + beg[b1 + 1];
-      const float sn = p2_next_sector(UA.sector) == UB.sector ? q.sn : -q.sn;
-      for (int i = i0; i < i1; ++i) {
-        const int b = Q.bin_seg[i];
-        const int gap = Q.seg_rows[b].x - rowA;
-        if (gap < 1 || gap > q.max_gap) continue;
-        const float zrB = Q.seg_zin[b];
-        if (!(fabsf(zrB - zA) <= q.dz_ends)) continue;
-        const tpcca_track_t &tb = B.tracks[B.unit_res[ub].track_begin + (b - Q.seg_begin[ub])];
-        KState sb = p2_inner(tb);
-        if (!p2_rotate(q.max_sin, q.cs, sn, sb)) continue;
-        KState sa;
-        sa.x = oa.x;
+    KState sa;
+    sa.x = oa.x;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) sa.p[k] = oa.p[k];
+    for (int j = 0; j < 5; ++j) sa.p[j] = oa.p[j];
 #pragma unroll
-        for (int k = 0; k < 15; ++k) sa.C[k] = oa.C[k];
-        if (!kf_propagate(P, sa, sb.x)) continue;
-        float d[5];
-        d[0] = sb.p[0] - sa.p[0];
-        d[1] = (zrB - zrA) - sa.p[1];
-        d[2] = sb.p[2] - sa.p[2];
-        d[3] = sb.p[3] - sa.p[3];
-        d[4] = sb.p[4] - sa.p[4];
-        if (!(fabsf(d[0]) <= q.wy) || !(fabsf(d[1]) <= q.wz)) continue;
-        float c;
-        if (!p2_chi2_5(d, sa.C, sb.C, c)) continue;
-        if (!(c <= q.chi2)) continue;
-        const unsigned long long hi = (unsigned long long)__float_as_uint(c) << 32;
-        const unsigned long long kb = hi | p2_key(Q, b, ub, UB.sector);
-        if (kb < best) best = kb;
-        atomicMin(&Q.best_a[b], hi | keyA);
-      }
-    }
-    Q.best_b[a] = best;
+    for (int j = 0; j < 15; ++j) sa.C[j] = oa.C[j];
+    if (!kf_propagate(P, sa, sb.x)) continue;
+    float d[5];
+    d[0] = sb.p[0] - sa.p[0];
+    d[1] = (zrB - zrA) - sa.p[1];
+    d[2] = sb.p[2] - sa.p[2];
+    d[3] = sb.p[3] - sa.p[3];
+    d[4] = sb.p[4] - sa.p[4];
+    if (!(fabsf(d[0]) <= q.wy) || !(fabsf(d[1]) <= q.wz)) continue;
+    float c;
+    if (!p2_chi2_5(d, sa.C, sb.C, c)) continue;
+    if (!(c <= q.chi2)) continue;
+    const unsigned long long hi = (unsigned long long)__float_as_uint(c) << 32;
+    atomicMin(&Q.best_b[a], hi | p2_key(Q, b, ub, sb_sec));
+    atomicMin(&Q.best_a[b], hi | p2_key(Q, a, ua, sa_sec));
   }
 }
 
@@ -416,6 +495,14 @@ struct PutStart {
     if (v) final_start[ex] = i;
   }
 };
+struct GetCount {
+  const int32_t *c;
+  __device__ int64_t operator()(int i) const { return c[i]; }
+};
+struct PutOffset {
+  int64_t *off;
+  __device__ void operator()(int i, int64_t ex, int64_t) const { off[i] = ex; }
+};
 struct GetFinalHits {
   const int32_t *nh;
   __device__ int64_t operator()(int i) const { return nh[i]; }
@@ -503,7 +590,6 @@ __global__ __launch_bounds__(256) void k_p2_refit(Bufs B, P2Bufs Q, ParamsDev P,
       for (int k = m - 1; k >= 0 && ok; --k) {
         const int g = chain[k];
         const int u = Q.seg_unit[g];
-        const UnitDev U = B.units[u];
         if (k < m - 1) {
           const int so = Q.units[Q.seg_unit[chain[k + 1]]].sector;
           const float sn = p2_next_sector(Q.units[u].sector) == so ? q.sn : -q.sn;
@@ -512,18 +598,19 @@ __global__ __launch_bounds__(256) void k_p2_refit(Bufs B, P2Bufs Q, ParamsDev P,
             break;
           }
         }
-        const tpcca_track_t &t = p2_track(B, Q, g, u);
-        const int64_t h0 = p2_hit0(B, t, u);
-        for (int j = t.n_hits - 1; j >= 0; --j) {
-          const int id = B.hits_out[h0 + j];
-          const int r = U.row[id];
-          const float4 c = U.cl[id];
+        const float4 *hr = Q.hrec + Q.seg_hb[g];
+        const int nhs = Q.seg_nh[g];
+        float4 nxt = hr[nhs - 1];
+        for (int j = nhs - 1; j >= 0; --j) {
+          const float4 c = nxt;
+          if (j > 0) nxt = hr[j - 1];  // the next record's load overlaps this step
+          const int r = __float_as_int(c.z);
           if (nh > 0 && !kf_propagate(P, st, B.row_x[r])) {
             ok = false;
             break;
           }
           float c2;
-          if (!kf_update(P, st, c.y, c.z - zr, c2)) {
+          if (!kf_update(P, st, c.x, c.y - zr, c2)) {
             ok = false;
             break;
           }
@@ -706,28 +793,47 @@ __global__ __launch_bounds__(256) void k_p2_attach(P2Bufs Q, P2Params q) {
 }
 
 // ---------------------------------------------------------------- flags ---
-__global__ __launch_bounds__(256) void k_p2_flags(Bufs B, P2Bufs Q, ParamsDev P, P2Params q) {
-  const int n = Q.cnt->n_final;
-  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < n; f += gridDim.x * blockDim.x) {
-    const tpcca_final_t &o = Q.finals[f];
-    int m = 0;
-    for (int g = Q.final_start[f]; g >= 0 && m < 18; g = Q.next[g], ++m) {
-      const int u = Q.seg_unit[g];
-      const UnitDev U = B.units[u];
-      const tpcca_track_t &t = p2_track(B, Q, g, u);
-      const float qpt = o.status == 0 ? o.p[4] : t.p[4];
-      uint8_t fl = 0;
-      if (fabsf(qpt) > q.rej_qpt) fl |= 1;
-      if (fabsf(qpt) > q.rej_looper && o.vertex < 0) fl |= 2;
-      const float kk = P.kB * t.p[4];
-      const int64_t h0 = p2_hit0(B, t, u);
-      for (int j = 0; j < t.n_hits; ++j) {
-        const int id = B.hits_out[h0 + j];
-        const float dx = B.row_x[U.row[id]] - t.x_ref;
-        const float s = __builtin_fmaf(kk, dx, t.p[2]);
-        Q.flags[U.cl_begin + id] = (uint8_t)(fl | (fabsf(s) > q.rej_sin ? 4 : 0));
+// Per segment, what its clusters' rejection flags need: the flags of its
+// final track (q/pT of the refit, or the segment's own where the refit
+// failed; the vertex) and the segment's state for the inclination test.
+__global__ __launch_bounds__(256) void k_p2_seg_flags(Bufs B, P2Bufs Q, ParamsDev P, P2Params q) {
+  const int n = Q.cnt->n_seg;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
+    const int u = Q.seg_unit[g];
+    const tpcca_track_t &t = p2_track(B, Q, g, u);
+    const tpcca_final_t &o = Q.finals[Q.final_of[g]];
+    const float qpt = o.status == 0 ? o.p[4] : t.p[4];
+    int fl = 0;
+    if (fabsf(qpt) > q.rej_qpt) fl |= 1;
+    if (fabsf(qpt) > q.rej_looper && o.vertex < 0) fl |= 2;
+    Q.seg_flag[g] = make_float4(P.kB * t.p[4], t.x_ref, t.p[2], __int_as_float(fl));
+  }
+}
+
+// Rejection flags, one thread per cluster (coalesced over the batch's
+// clusters): an assigned cluster takes its segment's flags and the
+// inclination of the segment's state at the cluster's row,
+// fma(kB q/pT, x_row - x_ref, sin phi).
+__global__ __launch_bounds__(256) void k_p2_flags(Bufs B, P2Bufs Q, P2Params q, int64_t n_cl) {
+  for (int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gi < n_cl;
+       gi += (int64_t)gridDim.x * blockDim.x) {
+    const int a = B.assign[gi];
+    uint8_t fl = 0;
+    if (a >= 0) {
+      // unit of cluster gi (cl_begin ascends with the unit)
+      int lo = 0, hi = Q.n_units;
+      while (hi - lo > 1) {
+        const int m = (lo + hi) >> 1;
+        if (B.units[m].cl_begin <= gi) lo = m;
+        else hi = m;
       }
+      const UnitDev &U = B.units[lo];
+      const float4 sf = Q.seg_flag[Q.seg_begin[lo] + a];
+      const float dx = B.row_x[U.row[gi - U.cl_begin]] - sf.y;
+      const float s = __builtin_fmaf(sf.x, dx, sf.z);
+      fl = (uint8_t)(__float_as_int(sf.w) | (fabsf(s) > q.rej_sin ? 4 : 0));
     }
+    Q.flags[gi] = fl;
   }
 }
 
@@ -776,13 +882,12 @@ __global__ __launch_bounds__(256) void k_p2_compress(Bufs B, P2Bufs Q, ParamsDev
   const int n = Q.cnt->n_seg;
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
     const int u = Q.seg_unit[g];
-    const UnitDev U = B.units[u];
     const tpcca_track_t &t = p2_track(B, Q, g, u);
-    const int64_t h0 = p2_hit0(B, t, u);
-    const int id0 = B.hits_out[h0];
-    const float4 c0 = U.cl[id0];
-    const int row0 = U.row[id0];
-    const int32_t yq0 = p2_quant(c0.y, q.qy), zq0 = p2_quant(c0.z, q.qz);
+    const int64_t h0 = Q.seg_hb[g];
+    const float4 *hr = Q.hrec + h0;
+    const float4 c0 = hr[0];
+    const int row0 = __float_as_int(c0.z);
+    const int32_t yq0 = p2_quant(c0.x, q.qy), zq0 = p2_quant(c0.y, q.qz);
     int32_t *rc = Q.rec + 6 * (int64_t)g;
     rc[0] = row0;
     rc[1] = yq0;
@@ -795,13 +900,15 @@ __global__ __launch_bounds__(256) void k_p2_compress(Bufs B, P2Bufs Q, ParamsDev
     int32_t *rs = Q.res + 3 * h0;
     rs[0] = rs[1] = rs[2] = 0;
     int prev = row0;
-    for (int j = 1; j < t.n_hits; ++j) {
-      const int id = B.hits_out[h0 + j];
-      const int r = U.row[id];
-      const float4 c = U.cl[id];
+    const int nh = Q.seg_nh[g];
+    float4 nxt = nh > 1 ? hr[1] : c0;
+    for (int j = 1; j < nh; ++j) {
+      const float4 c = nxt;
+      if (j + 1 < nh) nxt = hr[j + 1];  // the next record's load overlaps this step
+      const int r = __float_as_int(c.z);
       int32_t py, pz;
       const bool ok = fit.predict(P, q, B.row_x, r, py, pz);
-      const int32_t yq = p2_quant(c.y, q.qy), zq = p2_quant(c.z, q.qz);
+      const int32_t yq = p2_quant(c.x, q.qy), zq = p2_quant(c.y, q.qz);
       rs[3 * j] = r - prev;
       rs[3 * j + 1] = yq - py;
       rs[3 * j + 2] = zq - pz;
@@ -857,16 +964,32 @@ inline int p2_grid(int64_t n, int block, int cap) {
 }  // namespace
 
 hipError_t p2_launch_merge(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, const P2Params &q, int n_units,
-                           int64_t seg_cap, hipStream_t s) {
+                           int64_t seg_cap, int64_t hit_span, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;
   const int gs = p2_grid(seg_cap, 256, 8192);
   k_p2_fill_i32<<<p2_grid((int64_t)n_units * kP2Bins, 256, 4096), 256, 0, s>>>(Q.bin_cnt, (int64_t)n_units * kP2Bins, 0);
   k_p2_seg_index<<<1, 1024, 0, s>>>(B, Q);
+  k_p2_hits<<<p2_grid(hit_span, 256, 16384), 256, 0, s>>>(B, Q);
   k_p2_seg_prep<<<gs, 256, 0, s>>>(B, Q, P);
+  k_p2_zrange<<<std::min(n_units, 4096), 256, 0, s>>>(Q);
   k_p2_bin_count<<<gs, 256, 0, s>>>(Q);
   k_p2_bin_scan<<<std::min(n_units, 4096), kP2Bins, 0, s>>>(Q);
   k_p2_bin_scatter<<<gs, 256, 0, s>>>(Q);
-  k_p2_pairs<<<gs, 256, 0, s>>>(B, Q, P, q);
+  // candidate pairs: counts and their offsets (the total goes to the host)
+  k_p2_pair_count<<<gs, 256, 0, s>>>(Q, q, Q.final_nhits);
+  return p2_scan(GetCount{Q.final_nhits}, PutOffset{Q.final_hbeg}, &Q.cnt->n_seg, seg_cap, Q.scan_tmp, nullptr,
+                 &Q.cnt->n_pairs, s);
+}
+
+hipError_t p2_launch_pairs(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, const P2Params &q, int64_t seg_cap,
+                           int2 *pairs, int64_t n_pairs, hipStream_t s) {
+  const int gs = p2_grid(seg_cap, 256, 8192);
+  // the count and offset arrays are borrowed from the final tracks' arrays,
+  // which the steps below fill afresh
+  if (n_pairs > 0) {
+    k_p2_pair_fill<<<gs, 256, 0, s>>>(Q, q, Q.final_hbeg, pairs);
+    k_p2_pair_eval<<<p2_grid(n_pairs, 256, 16384), 256, 0, s>>>(B, Q, P, q, pairs, n_pairs);
+  }
   k_p2_links<<<gs, 256, 0, s>>>(Q);
   // final tracks: chain starts, their hit counts, hit offsets, refit
   hipError_t e = p2_scan(GetStart{Q.prev}, PutStart{Q.final_start}, &Q.cnt->n_seg, seg_cap, Q.scan_tmp,
@@ -931,8 +1054,8 @@ hipError_t p2_launch_vertices(const Bufs &B, const P2Bufs &Q, const ParamsDev &P
 
 hipError_t p2_launch_finish(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, const P2Params &q,
                             int32_t n_seg, int32_t n_final, int64_t n_clusters, hipStream_t s) {
-  if (n_clusters > 0) k_p2_fill_u8<<<p2_grid(n_clusters, 256, 8192), 256, 0, s>>>(Q.flags, n_clusters);
-  if (n_final > 0) k_p2_flags<<<p2_grid(n_final, 256, 8192), 256, 0, s>>>(B, Q, P, q);
+  if (n_seg > 0) k_p2_seg_flags<<<p2_grid(n_seg, 256, 8192), 256, 0, s>>>(B, Q, P, q);
+  if (n_clusters > 0) k_p2_flags<<<p2_grid(n_clusters, 256, 16384), 256, 0, s>>>(B, Q, q, n_clusters);
   if (n_seg > 0) k_p2_compress<<<p2_grid(n_seg, 256, 8192), 256, 0, s>>>(B, Q, P, q);
   return hipGetLastError();
 }

@@ -88,7 +88,7 @@ struct tpcca_ctx {
   // compression and rejection)
   tpcca_phase2_params_t p2params{};
   DevBuf p2units, p2seg_begin, p2seg_unit, p2seg_nh, p2seg_hb, p2seg_rows, p2seg_zin, p2seg_zout, p2seg_out,
-      p2zmm, p2bin_cnt, p2bin_beg, p2bin_seg, p2best_b, p2best_a, p2next, p2prev, p2final_of, p2final_start,
+      p2zmm, p2bin_cnt, p2bin_beg, p2bin_seg, p2bin_rz, p2hrec, p2seg_flag, p2pairs, p2best_b, p2best_a, p2next, p2prev, p2final_of, p2final_start,
       p2final_nhits, p2final_hbeg, p2finals, p2final_hits, p2vkey0, p2vkey1, p2vval0, p2vval1, p2gstart,
       p2group_pos, p2vertices, p2slot_first, p2slot_vbeg, p2slot_vend, p2flags, p2rec, p2res, p2scan, p2cnt,
       p2sort_tmp;
@@ -649,7 +649,7 @@ int tpcca_destroy(tpcca_ctx_t *c) {
                    &c->assign, &c->unit_res, &c->scan_tmp, &c->in_cl, &c->in_row,
                    &c->p2units, &c->p2seg_begin, &c->p2seg_unit, &c->p2seg_nh, &c->p2seg_hb, &c->p2seg_rows,
                    &c->p2seg_zin, &c->p2seg_zout, &c->p2seg_out, &c->p2zmm, &c->p2bin_cnt, &c->p2bin_beg,
-                   &c->p2bin_seg, &c->p2best_b, &c->p2best_a, &c->p2next, &c->p2prev, &c->p2final_of,
+                   &c->p2bin_seg, &c->p2bin_rz, &c->p2hrec, &c->p2seg_flag, &c->p2pairs, &c->p2best_b, &c->p2best_a, &c->p2next, &c->p2prev, &c->p2final_of,
                    &c->p2final_start, &c->p2final_nhits, &c->p2final_hbeg, &c->p2finals, &c->p2final_hits,
                    &c->p2vkey0, &c->p2vkey1, &c->p2vval0, &c->p2vval1, &c->p2gstart, &c->p2group_pos,
                    &c->p2vertices, &c->p2slot_first, &c->p2slot_vbeg, &c->p2slot_vend, &c->p2flags, &c->p2rec,
@@ -1432,7 +1432,9 @@ int p2_ensure(tpcca_ctx *c, int64_t U, int64_t T, int64_t N, int64_t S) {
       {&c->p2seg_zin, sizeof(float) * T}, {&c->p2seg_zout, sizeof(float) * T},
       {&c->p2seg_out, sizeof(P2Out) * T}, {&c->p2zmm, sizeof(int2) * U},
       {&c->p2bin_cnt, sizeof(int32_t) * U * kP2Bins}, {&c->p2bin_beg, sizeof(int32_t) * U * (kP2Bins + 1)},
-      {&c->p2bin_seg, sizeof(int32_t) * T}, {&c->p2best_b, sizeof(unsigned long long) * T},
+      {&c->p2bin_seg, sizeof(int32_t) * T}, {&c->p2bin_rz, sizeof(int2) * T},
+      {&c->p2hrec, sizeof(float4) * N}, {&c->p2seg_flag, sizeof(float4) * T},
+      {&c->p2best_b, sizeof(unsigned long long) * T},
       {&c->p2best_a, sizeof(unsigned long long) * T}, {&c->p2next, sizeof(int32_t) * T},
       {&c->p2prev, sizeof(int32_t) * T}, {&c->p2final_of, sizeof(int32_t) * T},
       {&c->p2final_start, sizeof(int32_t) * T}, {&c->p2final_nhits, sizeof(int32_t) * T},
@@ -1462,6 +1464,9 @@ int p2_ensure(tpcca_ctx *c, int64_t U, int64_t T, int64_t N, int64_t S) {
   Q.bin_cnt = ptr<int32_t>(c->p2bin_cnt);
   Q.bin_beg = ptr<int32_t>(c->p2bin_beg);
   Q.bin_seg = ptr<int32_t>(c->p2bin_seg);
+  Q.bin_rz = ptr<int2>(c->p2bin_rz);
+  Q.hrec = ptr<float4>(c->p2hrec);
+  Q.seg_flag = ptr<float4>(c->p2seg_flag);
   Q.best_b = ptr<unsigned long long>(c->p2best_b);
   Q.best_a = ptr<unsigned long long>(c->p2best_a);
   Q.next = ptr<int32_t>(c->p2next);
@@ -1569,8 +1574,12 @@ int tpcca_phase2(tpcca_ctx_t *c) {
   RCCHK(copy_sync(c, c->p2units.p, pu.data(), sizeof(P2Unit) * U, hipMemcpyHostToDevice));
   const P2Params q = p2_dev(c->p2params);
   const ParamsDev P = p2_prop_params(c);
-  hipError_t e = p2_launch_merge(c->B, c->P2, P, q, U, T, c->stream);
+  hipError_t e = p2_launch_merge(c->B, c->P2, P, q, U, T, c->n_total, c->stream);
   if (e != hipSuccess) return dev_err(c, e, "second phase (merge)");
+  RCCHK(copy_sync(c, &c->p2c, c->p2cnt.p, sizeof(P2Counts), hipMemcpyDeviceToHost));
+  RCCHK(ensure(c, c->p2pairs, sizeof(int2) * (size_t)std::max<int64_t>(c->p2c.n_pairs, 1), 0));
+  e = p2_launch_pairs(c->B, c->P2, P, q, T, ptr<int2>(c->p2pairs), c->p2c.n_pairs, c->stream);
+  if (e != hipSuccess) return dev_err(c, e, "second phase (pairs, refit)");
   RCCHK(copy_sync(c, &c->p2c, c->p2cnt.p, sizeof(P2Counts), hipMemcpyDeviceToHost));
   const size_t tmp = p2_sort_tmp_bytes(c->p2c.n_cand);
   RCCHK(ensure(c, c->p2sort_tmp, std::max<size_t>(tmp, 256), 0));
