@@ -9,7 +9,6 @@
 
 namespace tpcca {
 
-constexpr int kP2Bins = 1024;   // z bins of a unit's segment index (pairing)
 constexpr int kP2Tile = 2048;   // elements per tile of the phase's scans
 
 // Device copy of tpcca_phase2_params_t.
@@ -57,8 +56,10 @@ struct P2Bufs {
   float *seg_zout;               // absolute z of the outer end
   P2Out *seg_out;
   int2 *zmm;                     // per unit: ordered-int min, max of seg_zin
-  int32_t *bin_cnt;              // units x kP2Bins
-  int32_t *bin_beg;              // units x (kP2Bins + 1), unit-local offsets
+  int32_t *unit_nz;              // per unit: z bins per row of its pairing grid
+  int64_t *unit_bbase;           // per unit: first cell of its pairing grid
+  int32_t *bin_cnt;              // cells of all units' grids (row-major per unit)
+  int32_t *bin_beg;              // cell starts (unit-local offsets), one extra entry per unit
   int32_t *bin_seg;              // segments in bin order (unit u at seg_begin[u])
   int2 *bin_rz;                  // (first won row, bits of inner z) in bin order
   float4 *hrec;                  // per hit position: y, z, row and cluster ID (as bits)
@@ -98,6 +99,7 @@ hipError_t p2_launch_vertices(const Bufs &B, const P2Bufs &Q, const ParamsDev &P
 hipError_t p2_launch_finish(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, const P2Params &q,
                             int32_t n_seg, int32_t n_final, int64_t n_clusters, hipStream_t s);
 size_t p2_sort_tmp_bytes(int32_t n);
+int64_t p2_grid_cells(int64_t seg_cap, int64_t n_units, int R);
 hipError_t p2_launch_decompress(const ParamsDev &P, const P2Params &q, const float *row_x, int32_t n_seg,
                                 const int32_t *n_hits, const int64_t *hit_begin, const int32_t *rec,
                                 const int32_t *res, int32_t *yq, int32_t *zq, uint8_t *rows, hipStream_t s);

@@ -138,33 +138,87 @@ __device__ __forceinline__ KState p2_inner(const tpcca_track_t &t) {
   return s;
 }
 
-__device__ __forceinline__ int p2_bin(const int2 &zm, float z) {
+// z bin of the pairing grid of a unit with nz bins per row over its z range
+__device__ __forceinline__ int p2_zbin(const int2 &zm, int nz, float z) {
   const float z0 = from_ord(zm.x), z1 = from_ord(zm.y);
-  const float inv = (float)kP2Bins / fmaxf(z1 - z0, 1e-3f);
+  const float inv = (float)nz / fmaxf(z1 - z0, 1e-3f);
   float v = (z - z0) * inv;
-  v = fminf(fmaxf(v, 0.0f), (float)(kP2Bins - 1));
+  v = fminf(fmaxf(v, 0.0f), (float)(nz - 1));
   return (int)v;
 }
 
 // ---------------------------------------------------------- segments ---
 // Segment index of every unit (one block): seg_begin = exclusive scan of the
 // units' accepted track counts.
-__global__ __launch_bounds__(1024) void k_p2_seg_index(Bufs B, P2Bufs Q) {
+// The unit's pairing grid: R rows x nz z bins, nz from the unit's segment
+// count (about two segments per row and bin), so that a segment's candidates
+// are read from the few bins its row gap and z window cover.
+__device__ __forceinline__ int p2_grid_nz(int n_seg, int R) { return max(1, min(1024, (2 * n_seg) / R)); }
+
+__global__ __launch_bounds__(1024) void k_p2_seg_index(Bufs B, P2Bufs Q, int R) {
   __shared__ int64_t lds[1024 / 64 + 1];
-  int64_t carry = 0;
+  int64_t carry = 0, bcarry = 0;
   for (int u0 = 0; u0 < Q.n_units; u0 += 1024) {
     const int u = u0 + (int)threadIdx.x;
-    const int64_t v = u < Q.n_units ? B.unit_res[u].n_tracks : 0;
+    const int ns = u < Q.n_units ? B.unit_res[u].n_tracks : 0;
     int64_t tot;
-    const int64_t ex = block_exclusive_scan<int64_t>(v, lds, &tot);
-    if (u < Q.n_units) Q.seg_begin[u] = (int32_t)(carry + ex);
+    const int64_t ex = block_exclusive_scan<int64_t>(ns, lds, &tot);
+    const int nz = p2_grid_nz(ns, R);
+    int64_t btot;
+    const int64_t bex = block_exclusive_scan<int64_t>(u < Q.n_units ? (int64_t)R * nz : 0, lds, &btot);
+    if (u < Q.n_units) {
+      Q.seg_begin[u] = (int32_t)(carry + ex);
+      Q.unit_nz[u] = nz;
+      Q.unit_bbase[u] = bcarry + bex;
+    }
     carry += tot;
+    bcarry += btot;
   }
   if (threadIdx.x == 0) {
     Q.seg_begin[Q.n_units] = (int32_t)carry;
     Q.cnt->n_seg = (int32_t)carry;
   }
 }
+
+// ---------------------------------------------------------- compression ---
+__device__ __forceinline__ int32_t p2_quant(float v, float q) {
+  const float r = __builtin_rintf(v / q);
+  return fabsf(r) < 1073741824.0f ? (int32_t)r : 0;
+}
+
+struct CmpFit {
+  KState st;
+  float zr;
+  __device__ void start(const ParamsDev &P, const P2Params &q, const float *row_x, int row0, int32_t yq0,
+                        int32_t zq0, float s, float t, float qpt) {
+    st.x = row_x[row0];
+    st.p[0] = (float)yq0 * q.qy;
+    zr = (float)zq0 * q.qz;
+    st.p[1] = 0.0f;
+    st.p[2] = s;
+    st.p[3] = t;
+    st.p[4] = qpt;
+#pragma unroll
+    for (int k = 0; k < 15; ++k) st.C[k] = 0.0f;
+    st.C[0] = P.ery;
+    st.C[2] = P.erz;
+    st.C[5] = q.c22;
+    st.C[9] = q.c33;
+    st.C[14] = q.c44;
+  }
+  __device__ bool predict(const ParamsDev &P, const P2Params &q, const float *row_x, int r, int32_t &py,
+                          int32_t &pz) {
+    const bool ok = kf_propagate(P, st, row_x[r]);
+    py = p2_quant(st.p[0], q.qy);
+    pz = p2_quant(st.p[1] + zr, q.qz);
+    return ok;
+  }
+  __device__ void take(const ParamsDev &P, const P2Params &q, bool ok, int32_t yq, int32_t zq) {
+    if (!ok) return;
+    float c2;
+    (void)kf_update(P, st, (float)yq * q.qy, (float)zq * q.qz - zr, c2);
+  }
+};
 
 // Per hit position of the track hit array: the hit's y, z, pad row and
 // cluster ID gathered once (one coalesced pass), so that the per-track
@@ -191,10 +245,11 @@ __global__ __launch_bounds__(256) void k_p2_hits(Bufs B, P2Bufs Q) {
   }
 }
 
-// Per segment: rows of its first and last won hit, inner and outer z, and
-// the outer end (the fitted inner state propagated to each won hit's row in
-// ascending order); clears the pairing words.
-__global__ __launch_bounds__(256) void k_p2_seg_prep(Bufs B, P2Bufs Q, ParamsDev P) {
+// Per segment: rows of its first and last won hit, inner and outer z, the
+// outer end (the fitted inner state propagated to each won hit's row in
+// ascending order) and the segment's compressed form (record and residuals);
+// clears the pairing words.
+__global__ __launch_bounds__(256) void k_p2_seg_prep(Bufs B, P2Bufs Q, ParamsDev P, P2Params q) {
   const int n = Q.cnt->n_seg;
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
     const int u = p2_unit_of(Q, g);
@@ -202,16 +257,39 @@ __global__ __launch_bounds__(256) void k_p2_seg_prep(Bufs B, P2Bufs Q, ParamsDev
     const int64_t h0 = p2_hit0(B, t, u);
     const int nh = t.n_hits;
     KState st = p2_inner(t);
-    bool ok = true;
     const float4 *hr = Q.hrec + h0;
-    const int r_first = __float_as_int(hr[0].z);
+    const float4 c0 = hr[0];
+    const int r_first = __float_as_int(c0.z);
     int r_last = r_first;
-    float4 nxt = hr[0];
-    for (int k = 0; k < nh; ++k) {
-      const float4 cur = nxt;
+    bool ok = kf_propagate(P, st, B.row_x[r_first]);
+    // Sec. 3 compression of the segment in the same pass over its hits (the
+    // two fits are independent chains of operations)
+    const int32_t yq0 = p2_quant(c0.x, q.qy), zq0 = p2_quant(c0.y, q.qz);
+    int32_t *rc = Q.rec + 6 * (int64_t)g;
+    rc[0] = r_first;
+    rc[1] = yq0;
+    rc[2] = zq0;
+    rc[3] = (int32_t)__float_as_uint(t.p[2]);
+    rc[4] = (int32_t)__float_as_uint(t.p[3]);
+    rc[5] = (int32_t)__float_as_uint(t.p[4]);
+    CmpFit fit;
+    fit.start(P, q, B.row_x, r_first, yq0, zq0, t.p[2], t.p[3], t.p[4]);
+    int32_t *rs = Q.res + 3 * h0;
+    rs[0] = rs[1] = rs[2] = 0;
+    float4 nxt = nh > 1 ? hr[1] : c0;
+    for (int k = 1; k < nh; ++k) {
+      const float4 c = nxt;
       if (k + 1 < nh) nxt = hr[k + 1];  // the next record's load overlaps this step
-      r_last = __float_as_int(cur.z);
-      if (ok && !kf_propagate(P, st, B.row_x[r_last])) ok = false;
+      const int r = __float_as_int(c.z);
+      if (ok && !kf_propagate(P, st, B.row_x[r])) ok = false;
+      int32_t py, pz;
+      const bool pok = fit.predict(P, q, B.row_x, r, py, pz);
+      const int32_t yq = p2_quant(c.x, q.qy), zq = p2_quant(c.y, q.qz);
+      rs[3 * k] = r - r_last;
+      rs[3 * k + 1] = yq - py;
+      rs[3 * k + 2] = zq - pz;
+      fit.take(P, q, pok, yq, zq);
+      r_last = r;
     }
     P2Out o;
     o.x = st.x;
@@ -261,27 +339,40 @@ __global__ __launch_bounds__(256) void k_p2_zrange(P2Bufs Q) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_p2_bin_count(P2Bufs Q) {
-  const int n = Q.cnt->n_seg;
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
-    const int u = Q.seg_unit[g];
-    atomicAdd(&Q.bin_cnt[(int64_t)u * kP2Bins + p2_bin(Q.zmm[u], Q.seg_zin[g])], 1);
-  }
+// grid cell of segment g in its unit: (first won row, z bin)
+__device__ __forceinline__ int64_t p2_cell(const P2Bufs &Q, int g, int u) {
+  const int nz = Q.unit_nz[u];
+  return Q.unit_bbase[u] + (int64_t)Q.seg_rows[g].x * nz + p2_zbin(Q.zmm[u], nz, Q.seg_zin[g]);
 }
 
-// per unit: exclusive scan of its bin counts (one block per unit); the
-// counts become the scatter cursors
-__global__ __launch_bounds__(kP2Bins) void k_p2_bin_scan(P2Bufs Q) {
-  __shared__ int32_t lds[kP2Bins / 64 + 1];
+__global__ __launch_bounds__(256) void k_p2_bin_count(P2Bufs Q) {
+  const int n = Q.cnt->n_seg;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x)
+    atomicAdd(&Q.bin_cnt[p2_cell(Q, g, Q.seg_unit[g])], 1);
+}
+
+// per unit: exclusive scan of its cell counts (one block per unit, in
+// passes of 1024 cells); the counts become the scatter cursors; the cell
+// starts of unit u sit at bin_beg[unit_bbase[u] + u ..] (one extra entry)
+__global__ __launch_bounds__(1024) void k_p2_bin_scan(P2Bufs Q, int R) {
+  __shared__ int32_t lds[1024 / 64 + 1];
   for (int u = blockIdx.x; u < Q.n_units; u += gridDim.x) {
-    int32_t *cnt = Q.bin_cnt + (int64_t)u * kP2Bins;
-    int32_t *beg = Q.bin_beg + (int64_t)u * (kP2Bins + 1);
-    const int32_t v = cnt[threadIdx.x];
-    int32_t tot;
-    const int32_t ex = block_exclusive_scan<int32_t>(v, lds, &tot);
-    beg[threadIdx.x] = ex;
-    cnt[threadIdx.x] = ex;
-    if (threadIdx.x == 0) beg[kP2Bins] = tot;
+    const int nb = R * Q.unit_nz[u];
+    int32_t *cnt = Q.bin_cnt + Q.unit_bbase[u];
+    int32_t *beg = Q.bin_beg + Q.unit_bbase[u] + u;
+    int32_t carry = 0;
+    for (int i0 = 0; i0 < nb; i0 += 1024) {
+      const int i = i0 + (int)threadIdx.x;
+      const int32_t v = i < nb ? cnt[i] : 0;
+      int32_t tot;
+      const int32_t ex = block_exclusive_scan<int32_t>(v, lds, &tot) + carry;
+      if (i < nb) {
+        beg[i] = ex;
+        cnt[i] = ex;
+      }
+      carry += tot;
+    }
+    if (threadIdx.x == 0) beg[nb] = carry;
     __syncthreads();
   }
 }
@@ -290,7 +381,7 @@ __global__ __launch_bounds__(256) void k_p2_bin_scatter(P2Bufs Q) {
   const int n = Q.cnt->n_seg;
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
     const int u = Q.seg_unit[g];
-    const int pos = atomicAdd(&Q.bin_cnt[(int64_t)u * kP2Bins + p2_bin(Q.zmm[u], Q.seg_zin[g])], 1);
+    const int pos = atomicAdd(&Q.bin_cnt[p2_cell(Q, g, u)], 1);
     Q.bin_seg[Q.seg_begin[u] + pos] = g;
     Q.bin_rz[Q.seg_begin[u] + pos] = make_int2(Q.seg_rows[g].x, __float_as_int(Q.seg_zin[g]));
   }
@@ -313,7 +404,7 @@ __device__ __forceinline__ uint32_t p2_key(const P2Bufs &Q, int g, int u, int se
 // the expensive test then never leaves lanes of a wave waiting for the few
 // lanes whose A has a candidate.
 template <typename Fn>
-__device__ __forceinline__ void p2_candidates(const P2Bufs &Q, const P2Params &q, int a, Fn &&fn) {
+__device__ __forceinline__ void p2_candidates(const P2Bufs &Q, const P2Params &q, int R, int a, Fn &&fn) {
   const P2Out &oa = Q.seg_out[a];
   if (!oa.ok) return;
   const int ua = Q.seg_unit[a];
@@ -325,34 +416,39 @@ __device__ __forceinline__ void p2_candidates(const P2Bufs &Q, const P2Params &q
     if (ub < 0) continue;
     if (Q.seg_begin[ub + 1] == Q.seg_begin[ub]) continue;
     const int2 zm = Q.zmm[ub];
+    const int nz = Q.unit_nz[ub];
     const float pad = 1e-3f + 1e-6f * fabsf(zA);
-    const int b0 = p2_bin(zm, zA - q.dz_ends - pad), b1 = p2_bin(zm, zA + q.dz_ends + pad);
-    const int32_t *beg = Q.bin_beg + (int64_t)ub * (kP2Bins + 1);
-    const int i0 = Q.seg_begin[ub] + beg[b0], i1 = Q.seg_begin[ub] + beg[b1 + 1];
-    for (int i = i0; i < i1; ++i) {
-      const int2 rz = Q.bin_rz[i];
-      const int gap = rz.x - rowA;
-      if (gap < 1 || gap > q.max_gap) continue;
-      if (!(fabsf(__int_as_float(rz.y) - zA) <= q.dz_ends)) continue;
-      fn(i);
+    const int b0 = p2_zbin(zm, nz, zA - q.dz_ends - pad), b1 = p2_zbin(zm, nz, zA + q.dz_ends + pad);
+    const int32_t *beg = Q.bin_beg + Q.unit_bbase[ub] + ub;
+    const int sb = Q.seg_begin[ub];
+    const int r1 = min(rowA + q.max_gap, R - 1);
+    for (int r = rowA + 1; r <= r1; ++r) {
+      const int i0 = sb + beg[r * nz + b0], i1 = sb + beg[r * nz + b1 + 1];
+      for (int i = i0; i < i1; ++i) {
+        const int2 rz = Q.bin_rz[i];
+        const int gap = rz.x - rowA;
+        if (gap < 1 || gap > q.max_gap) continue;
+        if (!(fabsf(__int_as_float(rz.y) - zA) <= q.dz_ends)) continue;
+        fn(i);
+      }
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_p2_pair_count(P2Bufs Q, P2Params q, int32_t *count) {
+__global__ __launch_bounds__(256) void k_p2_pair_count(P2Bufs Q, P2Params q, int R, int32_t *count) {
   const int n = Q.cnt->n_seg;
   for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
     int c = 0;
-    p2_candidates(Q, q, a, [&](int) { ++c; });
+    p2_candidates(Q, q, R, a, [&](int) { ++c; });
     count[a] = c;
   }
 }
 
-__global__ __launch_bounds__(256) void k_p2_pair_fill(P2Bufs Q, P2Params q, const int64_t *begin, int2 *pairs) {
+__global__ __launch_bounds__(256) void k_p2_pair_fill(P2Bufs Q, P2Params q, int R, const int64_t *begin, int2 *pairs) {
   const int n = Q.cnt->n_seg;
   for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
     int64_t w = begin[a];
-    p2_candidates(Q, q, a, [&](int i) { pairs[w++] = make_int2(a, Q.bin_seg[i]); });
+    p2_candidates(Q, q, R, a, [&](int i) { pairs[w++] = make_int2(a, Q.bin_seg[i]); });
   }
 }
 
@@ -837,87 +933,6 @@ __global__ __launch_bounds__(256) void k_p2_flags(Bufs B, P2Bufs Q, P2Params q, 
   }
 }
 
-// ---------------------------------------------------------- compression ---
-__device__ __forceinline__ int32_t p2_quant(float v, float q) {
-  const float r = __builtin_rintf(v / q);
-  return fabsf(r) < 1073741824.0f ? (int32_t)r : 0;
-}
-
-struct CmpFit {
-  KState st;
-  float zr;
-  __device__ void start(const ParamsDev &P, const P2Params &q, const float *row_x, int row0, int32_t yq0,
-                        int32_t zq0, float s, float t, float qpt) {
-    st.x = row_x[row0];
-    st.p[0] = (float)yq0 * q.qy;
-    zr = (float)zq0 * q.qz;
-    st.p[1] = 0.0f;
-    st.p[2] = s;
-    st.p[3] = t;
-    st.p[4] = qpt;
-#pragma unroll
-    for (int k = 0; k < 15; ++k) st.C[k] = 0.0f;
-    st.C[0] = P.ery;
-    st.C[2] = P.erz;
-    st.C[5] = q.c22;
-    st.C[9] = q.c33;
-    st.C[14] = q.c44;
-  }
-  __device__ bool predict(const ParamsDev &P, const P2Params &q, const float *row_x, int r, int32_t &py,
-                          int32_t &pz) {
-    const bool ok = kf_propagate(P, st, row_x[r]);
-    py = p2_quant(st.p[0], q.qy);
-    pz = p2_quant(st.p[1] + zr, q.qz);
-    return ok;
-  }
-  __device__ void take(const ParamsDev &P, const P2Params &q, bool ok, int32_t yq, int32_t zq) {
-    if (!ok) return;
-    float c2;
-    (void)kf_update(P, st, (float)yq * q.qy, (float)zq * q.qz - zr, c2);
-  }
-};
-
-// One thread per segment: the record and the residuals of its hits.
-__global__ __launch_bounds__(256) void k_p2_compress(Bufs B, P2Bufs Q, ParamsDev P, P2Params q) {
-  const int n = Q.cnt->n_seg;
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
-    const int u = Q.seg_unit[g];
-    const tpcca_track_t &t = p2_track(B, Q, g, u);
-    const int64_t h0 = Q.seg_hb[g];
-    const float4 *hr = Q.hrec + h0;
-    const float4 c0 = hr[0];
-    const int row0 = __float_as_int(c0.z);
-    const int32_t yq0 = p2_quant(c0.x, q.qy), zq0 = p2_quant(c0.y, q.qz);
-    int32_t *rc = Q.rec + 6 * (int64_t)g;
-    rc[0] = row0;
-    rc[1] = yq0;
-    rc[2] = zq0;
-    rc[3] = (int32_t)__float_as_uint(t.p[2]);
-    rc[4] = (int32_t)__float_as_uint(t.p[3]);
-    rc[5] = (int32_t)__float_as_uint(t.p[4]);
-    CmpFit fit;
-    fit.start(P, q, B.row_x, row0, yq0, zq0, t.p[2], t.p[3], t.p[4]);
-    int32_t *rs = Q.res + 3 * h0;
-    rs[0] = rs[1] = rs[2] = 0;
-    int prev = row0;
-    const int nh = Q.seg_nh[g];
-    float4 nxt = nh > 1 ? hr[1] : c0;
-    for (int j = 1; j < nh; ++j) {
-      const float4 c = nxt;
-      if (j + 1 < nh) nxt = hr[j + 1];  // the next record's load overlaps this step
-      const int r = __float_as_int(c.z);
-      int32_t py, pz;
-      const bool ok = fit.predict(P, q, B.row_x, r, py, pz);
-      const int32_t yq = p2_quant(c.x, q.qy), zq = p2_quant(c.y, q.qz);
-      rs[3 * j] = r - prev;
-      rs[3 * j + 1] = yq - py;
-      rs[3 * j + 2] = zq - pz;
-      fit.take(P, q, ok, yq, zq);
-      prev = r;
-    }
-  }
-}
-
 __global__ __launch_bounds__(256) void k_p2_decompress(ParamsDev P, P2Params q, const float *row_x, int n_seg,
                                                       int R, const int32_t *n_hits, const int64_t *hit_begin,
                                                       const int32_t *rec, const int32_t *res, int32_t *yq,
@@ -963,20 +978,25 @@ inline int p2_grid(int64_t n, int block, int cap) {
 
 }  // namespace
 
+// cells of the units' pairing grids: R x nz per unit, nz <= max(1, 2 n / R)
+int64_t p2_grid_cells(int64_t seg_cap, int64_t n_units, int R) { return 2 * seg_cap + (int64_t)R * n_units; }
+
 hipError_t p2_launch_merge(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, const P2Params &q, int n_units,
                            int64_t seg_cap, int64_t hit_span, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;
   const int gs = p2_grid(seg_cap, 256, 8192);
-  k_p2_fill_i32<<<p2_grid((int64_t)n_units * kP2Bins, 256, 4096), 256, 0, s>>>(Q.bin_cnt, (int64_t)n_units * kP2Bins, 0);
-  k_p2_seg_index<<<1, 1024, 0, s>>>(B, Q);
+  const int R = P.n_rows;
+  const int64_t cells = p2_grid_cells(seg_cap, n_units, R);
+  k_p2_fill_i32<<<p2_grid(cells, 256, 8192), 256, 0, s>>>(Q.bin_cnt, cells, 0);
+  k_p2_seg_index<<<1, 1024, 0, s>>>(B, Q, R);
   k_p2_hits<<<p2_grid(hit_span, 256, 16384), 256, 0, s>>>(B, Q);
-  k_p2_seg_prep<<<gs, 256, 0, s>>>(B, Q, P);
+  k_p2_seg_prep<<<gs, 256, 0, s>>>(B, Q, P, q);
   k_p2_zrange<<<std::min(n_units, 4096), 256, 0, s>>>(Q);
   k_p2_bin_count<<<gs, 256, 0, s>>>(Q);
-  k_p2_bin_scan<<<std::min(n_units, 4096), kP2Bins, 0, s>>>(Q);
+  k_p2_bin_scan<<<std::min(n_units, 4096), 1024, 0, s>>>(Q, R);
   k_p2_bin_scatter<<<gs, 256, 0, s>>>(Q);
   // candidate pairs: counts and their offsets (the total goes to the host)
-  k_p2_pair_count<<<gs, 256, 0, s>>>(Q, q, Q.final_nhits);
+  k_p2_pair_count<<<gs, 256, 0, s>>>(Q, q, R, Q.final_nhits);
   return p2_scan(GetCount{Q.final_nhits}, PutOffset{Q.final_hbeg}, &Q.cnt->n_seg, seg_cap, Q.scan_tmp, nullptr,
                  &Q.cnt->n_pairs, s);
 }
@@ -987,7 +1007,7 @@ hipError_t p2_launch_pairs(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, c
   // the count and offset arrays are borrowed from the final tracks' arrays,
   // which the steps below fill afresh
   if (n_pairs > 0) {
-    k_p2_pair_fill<<<gs, 256, 0, s>>>(Q, q, Q.final_hbeg, pairs);
+    k_p2_pair_fill<<<gs, 256, 0, s>>>(Q, q, P.n_rows, Q.final_hbeg, pairs);
     k_p2_pair_eval<<<p2_grid(n_pairs, 256, 16384), 256, 0, s>>>(B, Q, P, q, pairs, n_pairs);
   }
   k_p2_links<<<gs, 256, 0, s>>>(Q);
@@ -1056,7 +1076,6 @@ hipError_t p2_launch_finish(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, 
                             int32_t n_seg, int32_t n_final, int64_t n_clusters, hipStream_t s) {
   if (n_seg > 0) k_p2_seg_flags<<<p2_grid(n_seg, 256, 8192), 256, 0, s>>>(B, Q, P, q);
   if (n_clusters > 0) k_p2_flags<<<p2_grid(n_clusters, 256, 16384), 256, 0, s>>>(B, Q, q, n_clusters);
-  if (n_seg > 0) k_p2_compress<<<p2_grid(n_seg, 256, 8192), 256, 0, s>>>(B, Q, P, q);
   return hipGetLastError();
 }
 

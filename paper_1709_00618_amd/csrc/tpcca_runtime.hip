@@ -88,7 +88,7 @@ struct tpcca_ctx {
   // compression and rejection)
   tpcca_phase2_params_t p2params{};
   DevBuf p2units, p2seg_begin, p2seg_unit, p2seg_nh, p2seg_hb, p2seg_rows, p2seg_zin, p2seg_zout, p2seg_out,
-      p2zmm, p2bin_cnt, p2bin_beg, p2bin_seg, p2bin_rz, p2hrec, p2seg_flag, p2pairs, p2best_b, p2best_a, p2next, p2prev, p2final_of, p2final_start,
+      p2zmm, p2unit_nz, p2unit_bbase, p2bin_cnt, p2bin_beg, p2bin_seg, p2bin_rz, p2hrec, p2seg_flag, p2pairs, p2best_b, p2best_a, p2next, p2prev, p2final_of, p2final_start,
       p2final_nhits, p2final_hbeg, p2finals, p2final_hits, p2vkey0, p2vkey1, p2vval0, p2vval1, p2gstart,
       p2group_pos, p2vertices, p2slot_first, p2slot_vbeg, p2slot_vend, p2flags, p2rec, p2res, p2scan, p2cnt,
       p2sort_tmp;
@@ -648,7 +648,7 @@ int tpcca_destroy(tpcca_ctx_t *c) {
                    &c->trk_hits, &c->owner, &c->accv, &c->wonmask, &c->accx, &c->tracks, &c->hits_out,
                    &c->assign, &c->unit_res, &c->scan_tmp, &c->in_cl, &c->in_row,
                    &c->p2units, &c->p2seg_begin, &c->p2seg_unit, &c->p2seg_nh, &c->p2seg_hb, &c->p2seg_rows,
-                   &c->p2seg_zin, &c->p2seg_zout, &c->p2seg_out, &c->p2zmm, &c->p2bin_cnt, &c->p2bin_beg,
+                   &c->p2seg_zin, &c->p2seg_zout, &c->p2seg_out, &c->p2zmm, &c->p2unit_nz, &c->p2unit_bbase, &c->p2bin_cnt, &c->p2bin_beg,
                    &c->p2bin_seg, &c->p2bin_rz, &c->p2hrec, &c->p2seg_flag, &c->p2pairs, &c->p2best_b, &c->p2best_a, &c->p2next, &c->p2prev, &c->p2final_of,
                    &c->p2final_start, &c->p2final_nhits, &c->p2final_hbeg, &c->p2finals, &c->p2final_hits,
                    &c->p2vkey0, &c->p2vkey1, &c->p2vval0, &c->p2vval1, &c->p2gstart, &c->p2group_pos,
@@ -1431,7 +1431,9 @@ int p2_ensure(tpcca_ctx *c, int64_t U, int64_t T, int64_t N, int64_t S) {
       {&c->p2seg_hb, sizeof(int64_t) * T}, {&c->p2seg_rows, sizeof(int2) * T},
       {&c->p2seg_zin, sizeof(float) * T}, {&c->p2seg_zout, sizeof(float) * T},
       {&c->p2seg_out, sizeof(P2Out) * T}, {&c->p2zmm, sizeof(int2) * U},
-      {&c->p2bin_cnt, sizeof(int32_t) * U * kP2Bins}, {&c->p2bin_beg, sizeof(int32_t) * U * (kP2Bins + 1)},
+      {&c->p2unit_nz, sizeof(int32_t) * U}, {&c->p2unit_bbase, sizeof(int64_t) * U},
+      {&c->p2bin_cnt, sizeof(int32_t) * p2_grid_cells(T, U, c->R)},
+      {&c->p2bin_beg, sizeof(int32_t) * (p2_grid_cells(T, U, c->R) + U)},
       {&c->p2bin_seg, sizeof(int32_t) * T}, {&c->p2bin_rz, sizeof(int2) * T},
       {&c->p2hrec, sizeof(float4) * N}, {&c->p2seg_flag, sizeof(float4) * T},
       {&c->p2best_b, sizeof(unsigned long long) * T},
@@ -1461,6 +1463,8 @@ int p2_ensure(tpcca_ctx *c, int64_t U, int64_t T, int64_t N, int64_t S) {
   Q.seg_zout = ptr<float>(c->p2seg_zout);
   Q.seg_out = ptr<P2Out>(c->p2seg_out);
   Q.zmm = ptr<int2>(c->p2zmm);
+  Q.unit_nz = ptr<int32_t>(c->p2unit_nz);
+  Q.unit_bbase = ptr<int64_t>(c->p2unit_bbase);
   Q.bin_cnt = ptr<int32_t>(c->p2bin_cnt);
   Q.bin_beg = ptr<int32_t>(c->p2bin_beg);
   Q.bin_seg = ptr<int32_t>(c->p2bin_seg);
