@@ -37,6 +37,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3     # published vector FP32 (packed); 78.6 without packed FP32
 LINK_BYTES_PER_CLUSTER = 16  # read y, z (8 B) + write up, down (8 B)
+# random 8-B loads over 2 GiB, each one 128-B line (profiles/memory_ceilings_random_access.md)
+RANDOM_LINE_CEILING_GPS = 53.5
 # FP32 operations of the fit per counted event (fma = 2, div / sqrt = 1):
 FIT_FLOPS = {
     "fit_steps": 154,       # propagation: 52 state + 102 covariance
@@ -222,6 +224,12 @@ def main():
     phase2 = None
     if not args.profile:
         phase2 = bench_phase2(ctx, dcl, drow, tf, args, log)
+    else:
+        # two calls of the second phase on the frame just tracked (their
+        # kernels are the k_p2_* dispatches of the profile)
+        for _ in range(2):
+            ctx.phase2()
+            ctx.sync()
 
     # --------------------------------------------- per-event plain path
     pe = tpcca.Context(rx, device=0)
@@ -346,7 +354,19 @@ def main():
     fit_ms = stages["fit"]
     flops = sum(FIT_FLOPS[k] * work[k] for k in FIT_FLOPS)
     fit_tf = flops / (fit_ms * 1e-3) / 1e12
+    # what binds the fit is the memory system's rate of random accesses (one
+    # 128-B line per 8-B load, partial-line stores, memory-side atomics):
+    # its counted line fetches against the measured random-load ceiling
+    fit_lines = (traffic.get("k_kf_fetch") or 0) / 128.0
+    random_access = {"ceiling_G_lines_per_s": RANDOM_LINE_CEILING_GPS,
+                     "achieved_G_lines_per_s": (round(fit_lines / (fit_ms * 1e-3) / 1e9, 2) if fit_lines else None),
+                     "frac": (round(fit_lines / (fit_ms * 1e-3) / 1e9 / RANDOM_LINE_CEILING_GPS, 4)
+                              if fit_lines else None),
+                     "basis": "FETCH_SIZE of the committed counter pass / 128 B per line, over the fit's time "
+                              "(null when the kernel sources changed since the pass)"}
     roofline = {"kernel": "k_kf (tracklet fit and track following)", "bound": "alu",
+                "binding_resource": "random 128-B line fetches (see random_access)",
+                "random_access": random_access,
                 "achieved": round(fit_tf, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(fit_tf / FP32_PEAK_TFLOPS, 4),
                 "traffic": traffic.get("k_kf"), "flops_per_launch": int(flops),
@@ -415,7 +435,8 @@ def main():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_timeframe128.json")
-KERNEL_SOURCES = ("paper_1709_00618_amd/csrc/tpcca_kernels.hip", "paper_1709_00618_amd/csrc/tpcca_internal.h")
+KERNEL_SOURCES = ("paper_1709_00618_amd/csrc/tpcca_kernels.hip", "paper_1709_00618_amd/csrc/tpcca_internal.h",
+                  "paper_1709_00618_amd/csrc/tpcca_kf.h", "paper_1709_00618_amd/csrc/tpcca_dev.h")
 
 
 def kernel_source_hash():
@@ -449,7 +470,11 @@ def measured_traffic():
         t = json.load(f)
     if t.get("source_hash") != kernel_source_hash():
         return {}
-    return {k: v["bytes"] for k, v in t["kernels"].items()}
+    out = {k: v["bytes"] for k, v in t["kernels"].items()}
+    for k, v in t["kernels"].items():
+        if "fetch_size" in v:
+            out[k + "_fetch"] = v["fetch_size"]
+    return out
 
 
 def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
@@ -466,7 +491,7 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
         return fs[0]
 
     def short(name):
-        n = name.split("(")[0].replace("void ", "").strip()
+        n = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").strip()
         return n.replace("tpcca::", "")
 
     tf_n = 4  # bench.py --profile: 1 warm-up + 3 timed replays of the time frame
@@ -517,7 +542,8 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
         fac[cname] = (1 << 20) / float(np.median(big)) if big else 1.0
         byk = {}
         for name, v, in_tf in seq:
-            if "tpcca" in name and in_tf:
+            # the time frame's kernels, and the second phase's (run on it after the replays)
+            if "tpcca" in name and (in_tf or short(name).startswith("k_p2")):
                 byk.setdefault(short(name), []).append(v * 1024.0 * fac[cname])
         for k, v in byk.items():
             e = out["kernels"].setdefault(k, {})
@@ -535,7 +561,8 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
     md = ["# Kernel trace and HBM traffic: batched time frame (128 events, 32.5 M clusters)", "",
           "Command (run from the repository root; `$R` = repository root):", "", "```", command, "```", "",
           "`bench.py --profile`: a 1 GiB device copy (counter calibration), then 1 warm-up + 3 timed graph "
-          "replays of the time frame (the TF dispatches below), then the per-event path (other dispatches).", "",
+          "replays of the time frame (the TF dispatches below), then two calls of the second phase on that frame "
+          "(its `k_p2_*` kernels and the radix sort) and the per-event path (other dispatches).", "",
           "## Durations (kernel trace)", ""] + lines + ["",
           f"Sum of TF kernel time over {tf_n} replays: {total / 1e3:.2f} ms ({total / tf_n / 1e3:.2f} ms per replay).",
           "", "## HBM traffic per TF dispatch (FETCH_SIZE + WRITE_SIZE, scaled by the copy)", "",
@@ -692,8 +719,8 @@ def write_ceilings(text):
     """profiles/memory_ceilings_random_access.md from the output of membench."""
     md = ["# Random-access ceilings of one MI355X", "",
           "Command (run from the repository root): `python3 bench.py --ceilings` (runs "
-          "`paper_1709_00618_amd/membench`, built from `paper_1709_00618_amd/csrc/membench.hip` by "
-          "`__graft_entry__.build()`).", "",
+          "`paper_1709_00618_amd/membench`, which `--ceilings` builds from "
+          "`paper_1709_00618_amd/csrc/membench.hip`; it is a measurement tool, not part of the library).", "",
           "256 x 32 blocks of 256 threads; random addresses over the table size in brackets "
           "(2 GiB where none is given); one warm launch, the rate of 5 timed launches. "
           "`wg scope`: workgroup-scope atomics, each XCD on a region of its own. The last line "
@@ -885,9 +912,12 @@ def cpu_baseline(ev, rx, seconds):
     dt = time.perf_counter() - t0
     # one thread, the 36 sectors in turn
     t1 = time.perf_counter()
+    near, decisions = 0, 0
     for u in units:
         cl, row, _, _, _ = ev.unit(u)
-        oracle.run_sector(cl, row, rx, precision=32)
+        r = oracle.run_sector(cl, row, rx, precision=32)
+        near += r.near_ties
+        decisions += r.decisions
     st_dt = time.perf_counter() - t1
     model = ""
     try:
@@ -899,6 +929,8 @@ def cpu_baseline(ev, rx, seconds):
         pass
     return {"value": round(done_cl / dt, 1), "unit": "clusters/s", "cores": cores, "kind": "oracle",
             "single_thread": round(ev.n_clusters / st_dt, 1), "nproc": os.cpu_count(), "cpu_model": model,
+            "near_ties": {"decisions": int(decisions), "margin_below_1e-6": int(near),
+                          "note": "the oracle's count on this event; the GPU path needed no exception"},
             "sample": f"{rounds} pass(es) over the 36 sectors of one central Pb-Pb event "
                       f"({ev.n_clusters} clusters), FP32 oracle, one sector per thread, {dt:.1f} s wall"}
 
