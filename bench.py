@@ -613,6 +613,18 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
                       f"{a.get('SQ_INSTS_LDS', 0) / w:.0f} | {a.get('SQ_INSTS_VMEM_RD', 0) / w:.0f} | "
                       f"{a.get('SQ_INSTS_VMEM_WR', 0) / w:.0f} | "
                       f"{100 * a.get('SQ_WAIT_ANY', 0) / max(1.0, a.get('SQ_WAVE_CYCLES', 1)):.0f} |")
+    # the second phase's kernels (two calls on the time frame, after the replays)
+    p2 = {k: v for k, v in per_o.items() if k.startswith("k_p2") or "rocprim" in k}
+    if p2:
+        p2_tot = {k: sum(v) for k, v in p2.items()}
+        md += ["", "## Second phase on the time frame (two calls)", "",
+               "| kernel | dispatches | avg us | share | fetch MB | write MB |", "|---|---|---|---|---|---|"]
+        for k in sorted(p2_tot, key=lambda k: -p2_tot[k]):
+            e = out["kernels"].get(k, {})
+            name = "radix sort (hipCUB / rocPRIM)" if "rocprim" in k else k
+            md.append(f"| {name} | {len(p2[k])} | {np.mean(p2[k]):.1f} | {100 * p2_tot[k] / sum(p2_tot.values()):.1f}% | "
+                      f"{e.get('fetch_size', 0) / 1e6:.1f} | {e.get('write_size', 0) / 1e6:.1f} |")
+        md.append(f"Sum per call: {sum(p2_tot.values()) / 2e3:.2f} ms of kernel time.")
     md += ["", f"Kernel sources hash: `{out['source_hash']}` (bench.py reports traffic only while it matches)."]
     path = os.path.join(ROOT, "profiles", "tracker_timeframe128_kernel_trace.md")
     with open(path, "w") as f:
