@@ -66,6 +66,12 @@ def parse():
     ap.add_argument("--summarize-profile", nargs=4, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "COMMAND"),
                     help="write the profiles/ summaries from rocprofv3 outputs of --profile runs")
     ap.add_argument("--sq-dir", default=None, help="with --summarize-profile: an SQ counter pass to add")
+    ap.add_argument("--summary-name", default=None,
+                    help="with --summarize-profile: write profiles/<name>.md and leave the traffic file "
+                         "(the bench line's counters) alone")
+    ap.add_argument("--fit-rows", type=int, default=0,
+                    help="with --profile: the row-synchronous fit with chunks of this many tracklets "
+                         "(tuning knob fit_rows; 0: the schedule as tuned)")
     ap.add_argument("--ceilings", action="store_true",
                     help="run the random-access microbenchmark and write its summary under profiles/")
     ap.add_argument("--profile-pipelined", action="store_true",
@@ -78,7 +84,7 @@ def parse():
 def main():
     args = parse()
     if args.summarize_profile:
-        summarize_profile(*args.summarize_profile, sq_dir=args.sq_dir)
+        summarize_profile(*args.summarize_profile, sq_dir=args.sq_dir, out_name=args.summary_name)
         return
     if args.ceilings:
         ceilings()
@@ -158,6 +164,8 @@ def main():
     if args.profile:  # never tune under a profiler
         entry = autotune.lookup(tf.n_clusters, len(tf.units))
         knobs, knob_src = (entry["knobs"], "cache") if entry else (ctx.get_tuning(), "default")
+        if args.fit_rows:
+            knobs, knob_src = dict(knobs, fit_rows=args.fit_rows), knob_src + " + fit_rows"
         ctx.set_tuning(**knobs)
     else:
         # the schedule is tuned with two frames in flight, as the headline runs
@@ -477,7 +485,7 @@ def measured_traffic():
     return out
 
 
-def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
+def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None, out_name=None):
     """Turn the rocprofv3 outputs of `bench.py --profile` (a kernel trace and
     FETCH_SIZE / WRITE_SIZE passes) into the committed summaries: per-kernel
     durations of the time-frame dispatches and counter bytes scaled by the
@@ -556,9 +564,11 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
     for k in list(out["kernels"]):
         if "<" in k:
             out["kernels"].setdefault(k.split("<")[0], out["kernels"][k])
-    with open(TRAFFIC_FILE, "w") as f:
-        json.dump(out, f, indent=1, sort_keys=True)
-    md = ["# Kernel trace and HBM traffic: batched time frame (128 events, 32.5 M clusters)", "",
+    if not out_name:
+        with open(TRAFFIC_FILE, "w") as f:
+            json.dump(out, f, indent=1, sort_keys=True)
+    md = ["# Kernel trace and HBM traffic: batched time frame (128 events, 32.5 M clusters)"
+          + (f" — {out_name}" if out_name else ""), "",
           "Command (run from the repository root; `$R` = repository root):", "", "```", command, "```", "",
           "`bench.py --profile`: a 1 GiB device copy (counter calibration), then 1 warm-up + 3 timed graph "
           "replays of the time frame (the TF dispatches below), then two calls of the second phase on that frame "
@@ -606,8 +616,9 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
         for k in list(out["kernels"]):
             if "<" in k:
                 out["kernels"][k.split("<")[0]] = out["kernels"][k]
-        with open(TRAFFIC_FILE, "w") as f:
-            json.dump(out, f, indent=1, sort_keys=True)
+        if not out_name:
+            with open(TRAFFIC_FILE, "w") as f:
+                json.dump(out, f, indent=1, sort_keys=True)
         for _, k, w, a in sorted(rows_sq, reverse=True):
             md.append(f"| {k} | {w:.0f} | {a.get('SQ_INSTS_VALU', 0) / w:.0f} | {a.get('SQ_INSTS_SALU', 0) / w:.0f} | "
                       f"{a.get('SQ_INSTS_LDS', 0) / w:.0f} | {a.get('SQ_INSTS_VMEM_RD', 0) / w:.0f} | "
@@ -626,10 +637,10 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, command, sq_dir=None):
                       f"{e.get('fetch_size', 0) / 1e6:.1f} | {e.get('write_size', 0) / 1e6:.1f} |")
         md.append(f"Sum per call: {sum(p2_tot.values()) / 2e3:.2f} ms of kernel time.")
     md += ["", f"Kernel sources hash: `{out['source_hash']}` (bench.py reports traffic only while it matches)."]
-    path = os.path.join(ROOT, "profiles", "tracker_timeframe128_kernel_trace.md")
+    path = os.path.join(ROOT, "profiles", (out_name or "tracker_timeframe128_kernel_trace") + ".md")
     with open(path, "w") as f:
         f.write("\n".join(md) + "\n")
-    print(f"wrote {path} and {TRAFFIC_FILE}")
+    print(f"wrote {path}" + ("" if out_name else f" and {TRAFFIC_FILE}"))
 
 
 def profile_pipelined(rx):

@@ -291,6 +291,12 @@ typedef struct {
                                 rows (1..n_rows; overrides fit_long_first); 0: by unit */
   int32_t fit_tail_units;    /* with fit_row_bands: only the last this many units of a run are
                                 taken band by band, the others stay unit by unit; 0: all */
+  int32_t fit_rows;          /* 0: per-lane fit (each lane at its own row); 64..1024: row-
+                                synchronous fit, the lanes of a wave step through the rows
+                                together over chunks of at most this many tracklets (ordered
+                                by z), the rows' hits read once into LDS; EINVAL otherwise.
+                                The order knobs above (long first, row bands, XCD slices, pool)
+                                do not apply to it. */
 } tpcca_tuning_t;
 int tpcca_set_tuning(tpcca_ctx_t *ctx, const tpcca_tuning_t *t);
 /* The schedule a new context starts with (pool 64, claims in the fit,

@@ -10,8 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtpcca.so")
-SOURCES = ["tpcca_kernels.hip", "tpcca_runtime.hip", "tpcca_server.hip", "tpcca_phase2.hip"]
-HEADERS = ["tpcca_internal.h", "tpcca_kernels.h", "tpcca_dev.h", "tpcca_kf.h", "tpcca_runtime.h", "tpcca_phase2.h"]
+SOURCES = ["tpcca_kernels.hip", "tpcca_fit_rows.hip", "tpcca_runtime.hip", "tpcca_server.hip", "tpcca_phase2.hip"]
+HEADERS = ["tpcca_internal.h", "tpcca_kernels.h", "tpcca_dev.h", "tpcca_kf.h", "tpcca_fit.h", "tpcca_runtime.h", "tpcca_phase2.h"]
 ARCH = os.environ.get("TPCCA_OFFLOAD_ARCH", "gfx950")
 
 # -ffp-contract=off and correctly rounded FP32 divide/sqrt: the kernels must

@@ -98,6 +98,7 @@ struct ParamsDev {
   int32_t kf_split;    // chains of at least this many hits are fitted first (0: off)
   int32_t kf_bands;    // fit order by (start-row band, unit) with this many bands (0: unit-major)
   int32_t kf_tail;     // with bands: only the last this many units are reordered (0: all)
+  int32_t kf_rows;     // row-synchronous fit with chunks of at most this many tracklets (0: per-lane fit)
 };
 
 // Hit slots per tracklet: n_rows rounded up to whole 32-B groups, so that
@@ -139,7 +140,8 @@ struct Bufs {
   int32_t *trk_hits;     // tracklet x slot_stride(n_rows) hit slots
   unsigned long long *owner;  // by sorted index
   unsigned long long *accv;   // by tracklet: accepted << 40 | won hits
-  unsigned long long *wonmask;  // by tracklet: 4 x 64 bits, slot k won its hit
+  unsigned long long *wonmask;  // by tracklet: 4 x 64 bits, slot k won its hit (the row-synchronous
+                                // fit's seed records before the selection)
   unsigned long long *accx;   // exclusive scan of accv (+ total)
   tpcca_track_t *tracks;      // by tracklet slot of the run (compacted)
   int32_t *hits_out;          // by global cluster index (compacted per run)
@@ -147,6 +149,11 @@ struct Bufs {
   tpcca_unit_result_t *unit_res;
   int64_t *scan_tmp;          // tile sums
   int32_t *ids_tmp;           // translation scratch
+  // row-synchronous fit: (bucket, rank) per tracklet, bucket counts, chunks
+  // (unit, first position in the run's order, count, -)
+  int2 *zo_tmp;
+  int64_t *zo_cnt;
+  int4 *kf_chunks;
 };
 
 }  // namespace tpcca

@@ -23,6 +23,12 @@ hipError_t launch_clean(const Bufs &B, const ParamsDev &P, int run, const RunHos
 hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
                          hipStream_t s);
 hipError_t launch_kf(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s);
+// Row-synchronous fit (tpcca_fit_rows.hip): its processing order and chunks
+// (called by launch_chains), the fit itself (called by launch_kf).
+hipError_t launch_kf_order_rows(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s);
+hipError_t launch_kf_rows(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s);
+// Exclusive scan of n int64 values in place (one block); sums[n] = total.
+hipError_t launch_scan_tiles(int64_t *sums, int64_t n, hipStream_t s);
 hipError_t launch_select(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s);
 hipError_t launch_links_by_id(const Bufs &B, const int32_t *up, const int32_t *dn, int32_t *out_up,
                               int32_t *out_dn, int32_t cl_begin, int32_t n, hipStream_t s);

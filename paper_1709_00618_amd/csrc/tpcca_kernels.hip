@@ -23,6 +23,7 @@
 #include "tpcca_kernels.h"
 #include "tpcca_dev.h"
 #include "tpcca_kf.h"
+#include "tpcca_fit.h"
 
 #include <algorithm>
 #include <map>
@@ -31,13 +32,6 @@
 namespace tpcca {
 
 // ------------------------------------------------------------- helpers ---
-__device__ __forceinline__ int ordered_int(float f) {
-  int i = __float_as_int(f);
-  return i >= 0 ? i : (i ^ 0x7FFFFFFF);
-}
-__device__ __forceinline__ float from_ordered(int i) {
-  return __int_as_float(i >= 0 ? i : (i ^ 0x7FFFFFFF));
-}
 
 // pad row of a cluster after validation; invalid clusters go to row R
 __device__ __forceinline__ int valid_row(float4 c, int r, const float *row_x, int R) {
@@ -47,22 +41,6 @@ __device__ __forceinline__ int valid_row(float4 c, int r, const float *row_x, in
   return r;
 }
 
-__device__ __forceinline__ int zbin(const RowTab &t, float z) {
-  float v = (z - t.z0) * t.inv;
-  v = fminf(fmaxf(v, 0.0f), (float)(t.nb - 1));  // NaN -> 0
-  return (int)v;
-}
-
-// sorted-index range of the bins covering [z - lim, z + lim] (a superset
-// of the hits inside the window; the exact window test follows)
-__device__ __forceinline__ void bin_range(const RowTab &t, const int32_t *binbeg, float z,
-                                          float lim, int &b, int &e) {
-  const float pad = 1e-3f + 1e-6f * fabsf(z);
-  const int lo = zbin(t, z - lim - pad);
-  const int hi = zbin(t, z + lim + pad);
-  b = binbeg[t.bin0 + lo];
-  e = binbeg[t.bin0 + hi + 1];
-}
 
 // ----------------------------------------------------------- utilities ---
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
@@ -1029,19 +1007,9 @@ __global__ void k_empty_units(Bufs B, int run) {
 }
 
 // ------------------------------------------------------------ tracklets ---
-// Nearest hit (dy^2 + dz^2, ties to the lower ID) inside the prediction
-// window of row r; -1 if none.
-// A tracklet's hit slot holds the hit's unit-local sorted index (24 bits:
-// units hold fewer than 2^24 clusters) and its pad row (top 8 bits), so the
-// refit needs no row lookup.
-__device__ __forceinline__ int32_t slot_enc(int g, int ucl, int row) {
-  return (int32_t)(((uint32_t)row << 24) | (uint32_t)(g - ucl));
-}
-__device__ __forceinline__ int slot_hit(int32_t v, int ucl) { return ucl + (int)((uint32_t)v & 0xFFFFFFu); }
-__device__ __forceinline__ int slot_row(int32_t v) { return (int)((uint32_t)v >> 24); }
-
-// Nearest hit of the row described by t inside the window; its coordinates
-// are returned in bc.
+// Nearest hit (dy^2 + dz^2, ties to the lower ID) of the row described by t
+// inside the prediction window; -1 if none; its coordinates are returned
+// in bc.
 // The state's z is relative to zr (see k_kf); the bins are looked up around
 // the absolute prediction zr + z with a margin that covers its rounding.
 __device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, const RowTab &t,
@@ -1099,57 +1067,6 @@ __device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, cons
 // wave).  Lanes of a wave therefore stay busy while tracklets of very
 // different lengths and phases share it; each tracklet still sees exactly
 // the operation sequence of the sequential description above.
-enum : int { kIdle = 0, kChain = 1, kFollow = 2, kRefit = 3, kExtend = 4 };
-
-// Claim key of the selection: more hits, then smaller chi2 (FP32 bits of
-// a non-negative float order like its value), then smaller start ID.
-__device__ __forceinline__ unsigned long long claim_key(int n_hits, float chi2, int start_id) {
-  const float c = chi2 > 0.0f ? chi2 : 0.0f;
-  const unsigned int bits = __float_as_uint(c);
-  return ((unsigned long long)(unsigned int)n_hits << 56) |
-         ((unsigned long long)(0xFFFFFFFFu - bits) << 24) |
-         (unsigned long long)(0xFFFFFFu - (unsigned int)start_id);
-}
-
-__device__ __forceinline__ void kf_fail(const Bufs &B, int t, int start_id, int n_chain) {
-  tpcca_tracklet_t o;
-  for (int k = 0; k < 15; ++k) {
-    o.cov[k] = 0.0f;
-    o.cov_out[k] = 0.0f;
-  }
-  for (int k = 0; k < 5; ++k) {
-    o.p[k] = 0.0f;
-    o.p_out[k] = 0.0f;
-  }
-  o.start_id = start_id;
-  o.n_chain = n_chain;
-  o.status = 2;
-  o.n_hits = 0;
-  o.n_pass1 = 0;
-  o.ndf = 0;
-  o.row_ref = 0;
-  o.row_out = 0;
-  o.x_ref = 0.0f;
-  o.x_out = 0.0f;
-  o.chi2 = 0.0f;
-  B.trk[t] = o;
-}
-
-__device__ __forceinline__ void kf_restart(const ParamsDev &P, KState &st) {
-  if (P.inflate > 0.0f) {
-#pragma unroll
-    for (int k = 0; k < 15; ++k) st.C[k] = st.C[k] * P.inflate;
-  } else {
-#pragma unroll
-    for (int k = 0; k < 15; ++k) st.C[k] = 0.0f;
-    st.C[0] = P.r00;
-    st.C[2] = P.r11;
-    st.C[5] = P.c22;
-    st.C[9] = P.c33;
-    st.C[14] = P.c44;
-  }
-}
-
 template <int kMinWaves>
 __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P, int run) {
   RunDev &rd = B.runs[run];
@@ -1759,6 +1676,12 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
   return hipGetLastError();
 }
 
+hipError_t launch_scan_tiles(int64_t *sums, int64_t n, hipStream_t s) {
+  if (n < 0) return hipSuccess;
+  k_scan_tiles<<<1, 1024, 0, s>>>(sums, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_grid(const Bufs &B, const ParamsDev &P, int run, const RunHost &h,
                        hipStream_t s) {
   const int R = P.n_rows;
@@ -1819,6 +1742,7 @@ hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHo
     k_flag_sums<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
     k_scan_tiles<<<1, 1024, 0, s>>>(B.scan_tmp, nch);
     k_flag_apply<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
+    if (P.kf_rows <= 0) {  // the row-synchronous fit orders its tracklets itself (below)
     k_order_sums<<<grid_for(nch, 1, 8192), kBlock, 0, s>>>(B, run);
     k_scan_tiles<<<1, 1024, 0, s>>>(B.scan_tmp, 2 * (int64_t)nch);
     const bool bands = P.kf_bands > 0 && h.trk_cap > 0;
@@ -1831,8 +1755,10 @@ hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHo
       k_band_scan<<<1, 1024, 0, s>>>(B, P, run);
       k_band_apply<<<grid_for(h.trk_cap, kBlock, 4096), kBlock, 0, s>>>(B, P, run);
     }
+    }
   }
   if (nu > 0) k_empty_units<<<grid_for(nu, 64, 1024), 64, 0, s>>>(B, run);
+  if (P.kf_rows > 0) return launch_kf_order_rows(B, P, run, h, s);
   return hipGetLastError();
 }
 
@@ -1877,6 +1803,7 @@ hipError_t launch_kf(const Bufs &B, const ParamsDev &P, int run, const RunHost &
   // as its tracklets end)
   hipError_t e = launch_fill_u64(B.owner + h.cl0, h.cl1 - h.cl0, 0ull, s);
   if (e != hipSuccess) return e;
+  if (P.kf_rows > 0) return launch_kf_rows(B, P, run, h, s);
   if (h.trk_cap > 0) {
     switch (v) {
       case 2: k_kf<6><<<g, kKfBlock, 0, s>>>(B, P, run); break;

@@ -65,7 +65,7 @@ struct tpcca_ctx {
   // device buffers
   DevBuf row_x_d, units_d, chunks_d, runs_d, rowtab, row_cnt, row_fill, chunk_hist, rtmp, zmm, binbeg, yz, sid, up,
       dn, upc, dnc, flag, starts, tiles, sval, tofg, kf_order, kf_tmp, band_tmp, srow, cinfo, trk_start, trk_unit, unit_tbegin, trk, trk_hits, owner, accv, wonmask, accx,
-      tracks, hits_out, assign, unit_res, scan_tmp, in_cl, in_row;
+      tracks, hits_out, assign, unit_res, scan_tmp, zo_tmp, zo_cnt, kf_chunks, in_cl, in_row;
   Bufs B{};
 
   // graph replay of the batch path
@@ -220,7 +220,10 @@ static void refresh_bufs(tpcca_ctx *c);
   X(accv, accv, unsigned long long, T + 1, 0)                                    \
   X(wonmask, wonmask, unsigned long long, 4 * T, 0)                              \
   X(accx, accx, unsigned long long, T + 1, 0)                                    \
-  X(scan_tmp, scan_tmp, int64_t, NSCAN, 0)
+  X(scan_tmp, scan_tmp, int64_t, NSCAN, 0)                                      \
+  X(zo_tmp, zo_tmp, int2, T, 0)                                                  \
+  X(zo_cnt, zo_cnt, int64_t, T / 16 + 2 * U + 2, 0)                              \
+  X(kf_chunks, kf_chunks, int4, T / 64 + U + 2, 0)
 #define TPCCA_OUTPUT_BUFFERS(X)                                                 \
   X(tracks, tracks, tpcca_track_t, T, keepT)                                     \
   X(hits_out, hits_out, int32_t, N, keepN)                                       \
@@ -646,7 +649,7 @@ int tpcca_destroy(tpcca_ctx_t *c) {
                    &c->zmm, &c->binbeg, &c->yz, &c->sid, &c->up, &c->dn, &c->upc,
                    &c->dnc, &c->flag, &c->starts, &c->tiles, &c->sval, &c->tofg, &c->kf_order, &c->kf_tmp, &c->band_tmp, &c->srow, &c->cinfo, &c->trk_start, &c->trk_unit, &c->unit_tbegin, &c->trk,
                    &c->trk_hits, &c->owner, &c->accv, &c->wonmask, &c->accx, &c->tracks, &c->hits_out,
-                   &c->assign, &c->unit_res, &c->scan_tmp, &c->in_cl, &c->in_row,
+                   &c->assign, &c->unit_res, &c->scan_tmp, &c->zo_tmp, &c->zo_cnt, &c->kf_chunks, &c->in_cl, &c->in_row,
                    &c->p2units, &c->p2seg_begin, &c->p2seg_unit, &c->p2seg_nh, &c->p2seg_hb, &c->p2seg_rows,
                    &c->p2seg_zin, &c->p2seg_zout, &c->p2seg_out, &c->p2zmm, &c->p2unit_nz, &c->p2unit_bbase, &c->p2bin_cnt, &c->p2bin_beg,
                    &c->p2bin_seg, &c->p2bin_rz, &c->p2hrec, &c->p2seg_flag, &c->p2pairs, &c->p2best_b, &c->p2best_a, &c->p2next, &c->p2prev, &c->p2final_of,
@@ -1130,6 +1133,7 @@ int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
   c->P.kf_split = t->fit_long_first;
   c->P.kf_bands = t->fit_row_bands;
   c->P.kf_tail = t->fit_tail_units;
+  c->P.kf_rows = t->fit_rows;
   c->P.kf_pool = t->fit_pool ? t->fit_pool : 64;
   c->P.kf_blocks_per_cu = t->fit_blocks_per_cu;
   c->P.link_blocks_per_cu = t->link_blocks_per_cu;
@@ -1154,6 +1158,7 @@ int tpcca_get_tuning(tpcca_ctx_t *c, tpcca_tuning_t *t) {
   t->fit_long_first = c->P.kf_split;
   t->fit_row_bands = c->P.kf_bands;
   t->fit_tail_units = c->P.kf_tail;
+  t->fit_rows = c->P.kf_rows;
   return TPCCA_OK;
 }
 
@@ -1360,7 +1365,8 @@ bool tuning_valid(const tpcca_tuning_t *t, int n_rows) {
            t->link_blocks_per_cu < 0 || t->fit_min_waves < 0 || t->fit_claims < 0 || t->fit_claims > 1 ||
            t->fit_xcd_slices < 0 || t->fit_xcd_slices > 1 || t->link_stage < 0 || t->link_stage > 2 ||
            t->fit_long_first < 0 || t->fit_row_bands < 0 || t->fit_row_bands > n_rows ||
-           t->fit_tail_units < 0);
+           t->fit_tail_units < 0 || t->fit_rows < 0 || (t->fit_rows > 0 && t->fit_rows < 64) ||
+           t->fit_rows > 1024);
 }
 size_t ctx_allocated(tpcca_ctx *c) { return c->allocated; }
 }  // namespace tpcca

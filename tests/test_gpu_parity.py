@@ -288,6 +288,11 @@ def test_batch_equals_sector_by_sector(tpcca, row_x):
          fit_xcd_slices=1, link_stage=2, fit_long_first=3, fit_row_bands=159),
     dict(fit_pool=32, fit_min_waves=4, fit_blocks_per_cu=2, grid_hits_per_bin=4, link_blocks_per_cu=32,
          fit_claims=1, fit_xcd_slices=1, fit_row_bands=7, fit_tail_units=40),
+    # the row-synchronous fit: small chunks on few blocks, large chunks with
+    # the claims in a kernel of their own
+    dict(fit_rows=64, fit_blocks_per_cu=1),
+    dict(fit_rows=1024, fit_claims=0, grid_hits_per_bin=2),
+    dict(fit_rows=384),
 ])
 def test_schedule_does_not_change_results(tpcca, row_x, knobs):
     """Every launch schedule gives the default schedule's bytes and the oracle's results."""
@@ -421,3 +426,45 @@ def test_fit_within_1e4_of_fp64_replay(tpcca, row_x):
             _fp64.check(st)
             checked += st["tracklets"]
     assert checked > 1500
+
+
+def test_row_synchronous_fit_on_a_time_frame(tpcca, row_x):
+    """The row-synchronous fit on a 32-event time frame (dense rows, z' over
+    tens of metres) gives the per-lane fit's tracklets, tracks and
+    assignment byte for byte, the same device work counts, and the oracle's
+    results on three units."""
+    tf = tpcgen.timeframe(seed=3, n_events=32)
+    print(f"time frame: {tf.n_clusters} clusters in {tf.units.shape[0]} units", flush=True)
+    out = {}
+    for rows in (0, 384, 160):
+        with tpcca.Context(row_x) as ctx:
+            ctx.set_tuning(fit_rows=rows)
+            ctx.run_batch(tf.cl, tf.row, tf.units, graph=True)
+            res = [a.copy() for a in ctx.get_batch_results()]
+            trk = {}
+            for u in (0, 13, 35):
+                _, _, slot, sec, _ = tf.unit(u)
+                trk[u] = [a.copy() for a in ctx.get_tracklets(slot, sec)]
+            w = ctx.work_stats()
+        print(f"fit_rows={rows}: {w}", flush=True)
+        out[rows] = (res, trk, w)
+    base = out[0]
+    for rows in (384, 160):
+        res, trk, w = out[rows]
+        for x, y in zip(base[0], res):
+            assert x.tobytes() == y.tobytes()
+        for u in trk:
+            for x, y in zip(base[1][u], trk[u]):
+                assert x.tobytes() == y.tobytes()
+        for k in ("fit_steps", "fit_candidates", "fit_tests", "fit_updates", "tracklets", "tracks",
+                  "track_hits", "graph_fallbacks"):
+            assert w[k] == base[2][k], k
+    refs = _parity.oracle_units(tf, row_x, which={0, 13, 35})
+    units, tracks, hits, asg = out[384][0]
+    for u in (0, 13, 35):
+        ur = units[u]
+        t0, nt = int(ur["track_begin"]), int(ur["n_tracks"])
+        h0, nh = int(ur["hit_begin"]), int(ur["n_track_hits"])
+        c0, n = int(ur["cluster_begin"]), int(tf.units[u, 1])
+        _parity.compare_tracks(tracks[t0:t0 + nt], hits[h0:h0 + nh], refs[u])
+        assert np.array_equal(asg[c0:c0 + n], refs[u].assignment)
