@@ -37,6 +37,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3     # published vector FP32 (packed); 78.6 without packed FP32
 LINK_BYTES_PER_CLUSTER = 16  # read y, z (8 B) + write up, down (8 B)
+# algorithmic bytes of the fit per candidate examined, per update and per row step
+FIT_BYTES_PER_ITEM = 8
 # random 8-B loads over 2 GiB, each one 128-B line (profiles/memory_ceilings_random_access.md)
 RANDOM_LINE_CEILING_GPS = 53.5
 # FP32 operations of the fit per counted event (fma = 2, div / sqrt = 1):
@@ -357,14 +359,19 @@ def main():
     ctx.close()
 
     # ---------------------------------------------------------- roofline
-    # dominant kernel: the Kalman fit (ALU / latency bound)
+    # dominant kernel: the Kalman fit.  What binds it is the memory system's
+    # handling of random accesses (one 128-B line per 8-B load, partial-line
+    # stores, memory-side atomics): quoted against HBM with its algorithmic
+    # bytes (8 B, the y and z of a hit, per candidate examined and per
+    # update, and 8 B per row step for the bin pair of the row), its
+    # measured traffic beside them, its line fetches against the measured
+    # random-load ceiling, and its arithmetic against the FP32 peak
     traffic = measured_traffic()
     fit_ms = stages["fit"]
     flops = sum(FIT_FLOPS[k] * work[k] for k in FIT_FLOPS)
     fit_tf = flops / (fit_ms * 1e-3) / 1e12
-    # what binds the fit is the memory system's rate of random accesses (one
-    # 128-B line per 8-B load, partial-line stores, memory-side atomics):
-    # its counted line fetches against the measured random-load ceiling
+    fit_alg = FIT_BYTES_PER_ITEM * (work["fit_candidates"] + work["fit_updates"] + work["fit_steps"])
+    fit_gbs = fit_alg / (fit_ms * 1e-3) / 1e9
     fit_lines = (traffic.get("k_kf_fetch") or 0) / 128.0
     random_access = {"ceiling_G_lines_per_s": RANDOM_LINE_CEILING_GPS,
                      "achieved_G_lines_per_s": (round(fit_lines / (fit_ms * 1e-3) / 1e9, 2) if fit_lines else None),
@@ -372,13 +379,16 @@ def main():
                               if fit_lines else None),
                      "basis": "FETCH_SIZE of the committed counter pass / 128 B per line, over the fit's time "
                               "(null when the kernel sources changed since the pass)"}
-    roofline = {"kernel": "k_kf (tracklet fit and track following)", "bound": "alu",
-                "binding_resource": "random 128-B line fetches (see random_access)",
+    roofline = {"kernel": "k_kf (tracklet fit and track following)", "bound": "hbm",
+                "binding_resource": "random 128-B line fetches, partial stores and atomics (see random_access)",
+                "achieved": round(fit_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(fit_gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get("k_kf"),
+                "algorithmic_bytes": int(fit_alg),
+                "bytes_basis": "8 B per candidate examined, per update and per row step (device work counters)",
                 "random_access": random_access,
-                "achieved": round(fit_tf, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(fit_tf / FP32_PEAK_TFLOPS, 4),
-                "traffic": traffic.get("k_kf"), "flops_per_launch": int(flops),
-                "flops_per_step": round(flops / max(1, work["fit_steps"]), 1),
+                "alu": {"achieved": round(fit_tf, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(fit_tf / FP32_PEAK_TFLOPS, 4), "flops_per_launch": int(flops),
+                        "flops_per_step": round(flops / max(1, work["fit_steps"]), 1)},
                 "lane_use": round(work["fit_steps"] / max(1, 64 * work["fit_wave_iterations"]), 4),
                 "valu_busy": (round(measured_valu_busy()["k_kf"], 4)
                               if "k_kf" in measured_valu_busy() else None),
