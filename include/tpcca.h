@@ -297,6 +297,11 @@ typedef struct {
                                 by z), the rows' hits read once into LDS; EINVAL otherwise.
                                 The order knobs above (long first, row bands, XCD slices, pool)
                                 do not apply to it. */
+  int32_t link_tile;         /* hits of one pad row per neighbour-finding block: 0 (256), 128,
+                                256 or 512; set before loading units (ESTATE if it would change
+                                the tile reservations of loaded units); EINVAL otherwise */
+  int32_t fit_block;         /* threads per block of the per-lane fit: 0 (128), 64, 128 or 256;
+                                EINVAL otherwise */
 } tpcca_tuning_t;
 int tpcca_set_tuning(tpcca_ctx_t *ctx, const tpcca_tuning_t *t);
 /* The schedule a new context starts with (pool 64, claims in the fit,

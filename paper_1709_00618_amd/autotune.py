@@ -3,12 +3,15 @@
 The knobs (``tpcca_tuning_t``) change occupancy, load balance and grid
 granularity, never a result: every decision compares cluster IDs and each
 tracklet sees the same operation sequence whatever the schedule.  The tuner
-replays the batch graph of a sample batch for every point of a small grid of
-schedules, keeps the fastest, and caches it in ``tuning_cache.json`` keyed by
-device name and a size bucket of the batch (clusters, units).  Given a second
-context, a point is timed with two batches in flight (the contexts fed
-alternately), the way the batched bench and the server run: then the cost
-per batch includes how well one batch's stages fill the other's fit drain.
+replays the batch graph of a sample batch and searches the knobs one at a
+time (coordinate descent from the default schedule: each knob's values are
+timed with the others at their best so far, in the order of ``SPACE``, for
+``rounds`` passes), keeps the fastest point, and caches it in
+``tuning_cache.json`` keyed by device name and a size bucket of the batch
+(clusters, units).  Given a second context, a point is timed with two
+batches in flight (the contexts fed alternately), the way the batched bench
+and the server run: then the cost per batch includes how well one batch's
+stages fill the other's fit drain.
 """
 from __future__ import annotations
 
@@ -21,12 +24,16 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning_cache.json")
 
+# knob -> values; the first value is the default schedule's
 SPACE = {
-    "fit_pool": [64, 128],
+    "fit_block": [0, 64, 256],
+    "fit_blocks_per_cu": [0, 6, 4, 8, 12],
     "fit_min_waves": [0, 4],
-    "fit_blocks_per_cu": [0, 6],
-    "link_stage": [0, 1],
+    "fit_pool": [64, 128, 32],
+    "link_stage": [0, 1, 2],
+    "link_tile": [0, 128, 512],
 }
+DEFAULT = {k: v[0] for k, v in SPACE.items()}
 
 
 def bucket(n_clusters: int, n_units: int) -> str:
@@ -92,28 +99,38 @@ def _time_pipelined(ctxs, run, frames=8, reps=2):
     return ts[len(ts) // 2]
 
 
-def tune(ctx, cl, row, units, device=True, reps=3, space=None, log=None, ctx2=None):
-    """Sweep the schedule grid on one batch; returns (best dict, table).
-    With ctx2, every point is timed with two batches in flight."""
+def tune(ctx, cl, row, units, device=True, reps=3, space=None, log=None, ctx2=None, rounds=1):
+    """Coordinate search of the schedule on one batch; returns (best dict,
+    table of (seconds, knobs) for every point timed).  With ctx2, every
+    point is timed with two batches in flight."""
     space = space or SPACE
-    names = list(space)
-    table = []
     ctxs = [ctx] if ctx2 is None else [ctx, ctx2]
+    seen = {}
 
     def run(c=ctx):
         c.run_batch(cl, row, units, device=device, graph=True)
 
-    for combo in itertools.product(*(space[n] for n in names)):
-        knobs = dict(zip(names, combo))
-        for c in ctxs:
-            c.reset()
-            c.set_tuning(**knobs)
-        t = _time(ctx, run, reps) if ctx2 is None else _time_pipelined(ctxs, run)
-        table.append((t, knobs))
-        if log:
-            log(f"autotune {knobs}: {t * 1e3:.3f} ms")
-    table.sort(key=lambda x: x[0])
-    best = dict(table[0][1])
+    def timed(knobs):
+        key = tuple(sorted(knobs.items()))
+        if key not in seen:
+            for c in ctxs:
+                c.reset()
+                c.set_tuning(**knobs)
+            seen[key] = _time(ctx, run, reps) if ctx2 is None else _time_pipelined(ctxs, run)
+            if log:
+                log(f"autotune {knobs}: {seen[key] * 1e3:.3f} ms")
+        return seen[key]
+
+    best = {k: v[0] for k, v in space.items()}
+    best_t = timed(best)
+    for _ in range(rounds):
+        for name, vals in space.items():
+            for v in vals:
+                point = dict(best, **{name: v})
+                t = timed(point)
+                if t < best_t:
+                    best, best_t = point, t
+    table = sorted(((t, dict(k)) for k, t in seen.items()), key=lambda x: x[0])
     for c in ctxs:
         c.reset()
         c.set_tuning(**best)
@@ -140,5 +157,4 @@ def tuned(ctx, cl, row, units, n_clusters, device=True, log=None, retune=False, 
 
 
 def _default(table):
-    d = {"fit_pool": 64, "fit_min_waves": 0, "fit_blocks_per_cu": 0, "link_stage": 0}
-    return d if any(k == d for _, k in table) else None
+    return DEFAULT if any(k == DEFAULT for _, k in table) else None

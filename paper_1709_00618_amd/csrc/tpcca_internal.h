@@ -28,7 +28,8 @@ struct UnitDev {
   int32_t tile_base;     // first row tile slot reserved for the unit
 };
 
-constexpr int kTile = 256;  // hits of one row per neighbour-finding tile
+constexpr int kTile = 256;     // hits of one row per neighbour-finding tile (default)
+constexpr int kTileMin = 128;  // smallest tile the schedule may ask for (tile table capacity)
 constexpr int kMaxBinsRow = 8192;  // z bins per row (the row sort keeps them in LDS)
 
 // A chunk of <= kChunk consecutive clusters of one unit.
@@ -99,7 +100,13 @@ struct ParamsDev {
   int32_t kf_bands;    // fit order by (start-row band, unit) with this many bands (0: unit-major)
   int32_t kf_tail;     // with bands: only the last this many units are reordered (0: all)
   int32_t kf_rows;     // row-synchronous fit with chunks of at most this many tracklets (0: per-lane fit)
+  int32_t link_tile;   // hits per neighbour-finding tile (128, 256 or 512)
+  int32_t kf_block;    // threads per block of the per-lane fit (64, 128 or 256)
 };
+
+// Schedule knobs with defaults (0 in the tuning means the default).
+__host__ __device__ inline int link_tile_of(const ParamsDev &P) { return P.link_tile > 0 ? P.link_tile : kTile; }
+__host__ __device__ inline int kf_block_of(const ParamsDev &P) { return P.kf_block > 0 ? P.kf_block : kKfBlock; }
 
 // Hit slots per tracklet: n_rows rounded up to whole 32-B groups, so that
 // every tracklet's slots start 32-B aligned and move eight at a time.

@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_count(Bufs B, int run, int R) {
 }
 
 // Pass 2 (one block per unit): row offsets and z-bin layout of every row.
-__global__ __launch_bounds__(kBlock) void k_plan(Bufs B, int run, int R, int hits_per_bin) {
+__global__ __launch_bounds__(kBlock) void k_plan(Bufs B, int run, int R, int hits_per_bin, int tile) {
   __shared__ int64_t lds64[kBlock / 64 + 1];
   __shared__ int32_t lds32[kBlock / 64 + 1];
   const RunDev &rd = B.runs[run];
@@ -222,15 +222,15 @@ __global__ __launch_bounds__(kBlock) void k_plan(Bufs B, int run, int R, int hit
       t.inv = (float)nb / span;
       B.rowtab[(int64_t)u * (R + 1) + r] = t;
     }
-    // row tiles of at most kTile hits for the neighbour search; the unused
+    // row tiles of at most `tile` hits for the neighbour search; the unused
     // slots of the unit's reservation are marked empty
-    const int nt = r <= R ? (cnt + kTile - 1) / kTile : 0;
+    const int nt = r <= R ? (cnt + tile - 1) / tile : 0;
     int32_t ttot;
     const int32_t toff = block_exclusive_scan<int32_t>(nt, lds32, &ttot);
     for (int i = 0; i < nt; ++i)
       B.tiles[U.tile_base + toff + i] =
-          make_int4(u, r, U.cl_begin + begin + i * kTile, min(kTile, cnt - i * kTile));
-    const int cap = U.n / kTile + R + 2;
+          make_int4(u, r, U.cl_begin + begin + i * tile, min(tile, cnt - i * tile));
+    const int cap = U.n / tile + R + 2;
     for (int i = ttot + r; i < cap; i += blockDim.x) B.tiles[U.tile_base + i] = make_int4(u, 0, 0, 0);
     __syncthreads();
   }
@@ -435,8 +435,8 @@ __device__ __forceinline__ int row_of(const RowTab *t, int R, int g) {
 // inside |dy|, |dz| <= W dx that minimises (chi2, id_u, id_d), where chi2 is
 // the squared deviation of the hit from the line d -> u at the hit's row.
 //
-// One block per row tile (<= kTile hits of one row, contiguous in z-bin
-// order).  The z bins of rows r-1 and r+1 that any hit of the tile can reach
+// One block per row tile (<= kT hits of one row, contiguous in z-bin
+// order; the tile size is a schedule knob: 128, 256 or 512).  The z bins of rows r-1 and r+1 that any hit of the tile can reach
 // are a contiguous range of sorted hits; they are staged in LDS with their
 // bin offsets, so every candidate test reads LDS.  Tiles whose neighbour
 // ranges exceed the LDS capacity read the candidates from global memory.
@@ -568,13 +568,13 @@ __device__ __forceinline__ LinkBest link_hit_lds(const Bufs &B, float2 h, float 
   return b;
 }
 
-template <int kV>
-__global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
+template <int kV, int kT>
+__global__ __launch_bounds__(kT) void k_links(Bufs B, ParamsDev P, int run) {
   constexpr int kNbrCap = LinkCaps<kV>::nbr, kBinCap = LinkCaps<kV>::bins;
   static_assert(kNbrCap < 65536, "bin offsets are 16-bit");
   __shared__ float2 s_up[kNbrCap + 1], s_dn[kNbrCap + 1];  // + the spare entry of window_mask
   __shared__ uint16_t s_bup[kBinCap + 1], s_bdn[kBinCap + 1];  // bin starts - ua / - da
-  __shared__ int s_red[2 * (kTile / 64)];
+  __shared__ int s_red[2 * (kT / 64)];
   // defined contents for the entries after a tile's staged range (read by
   // window_mask's last step, never used); the tile loop's first barrier
   // orders this before any read
@@ -620,13 +620,13 @@ __global__ __launch_bounds__(kTile) void k_links(Bufs B, ParamsDev P, int run) {
     }
     if ((i & 63) == 0) {
       s_red[i >> 6] = zmin;
-      s_red[(kTile / 64) + (i >> 6)] = zmax;
+      s_red[(kT / 64) + (i >> 6)] = zmax;
     }
     __syncthreads();
-    float zlo = from_ordered(s_red[0]), zhi = from_ordered(s_red[kTile / 64]);
-    for (int q = 1; q < kTile / 64; ++q) {
+    float zlo = from_ordered(s_red[0]), zhi = from_ordered(s_red[kT / 64]);
+    for (int q = 1; q < kT / 64; ++q) {
       zlo = fminf(zlo, from_ordered(s_red[q]));
-      zhi = fmaxf(zhi, from_ordered(s_red[(kTile / 64) + q]));
+      zhi = fmaxf(zhi, from_ordered(s_red[(kT / 64) + q]));
     }
     // tile-wide bin ranges of the neighbour rows (a superset of every hit's)
     const float tpad = 1e-3f + 1e-6f * fmaxf(fabsf(zlo), fabsf(zhi));
@@ -1067,8 +1067,8 @@ __device__ __forceinline__ int kf_search(const Bufs &B, const ParamsDev &P, cons
 // wave).  Lanes of a wave therefore stay busy while tracklets of very
 // different lengths and phases share it; each tracklet still sees exactly
 // the operation sequence of the sequential description above.
-template <int kMinWaves>
-__global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P, int run) {
+template <int kMinWaves, int kBlk>
+__global__ __launch_bounds__(kBlk, kMinWaves) void k_kf(Bufs B, ParamsDev P, int run) {
   RunDev &rd = B.runs[run];
   const int R = P.n_rows;
   const int n_trk = rd.n_trk;
@@ -1087,7 +1087,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
   KState st;
   // aux state in LDS (frees registers for occupancy): the pass-1 state at
   // the outermost hit, then the pass-2 state at the innermost hit
-  __shared__ float s_aux[21][kKfBlock];
+  __shared__ float s_aux[21][kBlk];
   const int tid = threadIdx.x;
   // hit slots go to memory eight at a time (one aligned 32-B group): a lane
   // collects a group in LDS and writes it when complete or when its phase
@@ -1095,7 +1095,7 @@ __global__ __launch_bounds__(kKfBlock, kMinWaves) void k_kf(Bufs B, ParamsDev P,
   // narrower than a memory segment cost a read-modify-write each, so fewer,
   // wider ones matter.
   constexpr int G = kSlotGrp, GM = kSlotGrp - 1;
-  __shared__ int32_t s_slot[G][kKfBlock];
+  __shared__ int32_t s_slot[G][kBlk];
   const int Rs = slot_stride(R);
   auto slot_flush = [&](int j) {  // the group holding slot j
     int4 *dst = reinterpret_cast<int4 *>(B.trk_hits + (int64_t)t * Rs + (j & ~GM));
@@ -1688,7 +1688,7 @@ hipError_t launch_grid(const Bufs &B, const ParamsDev &P, int run, const RunHost
   const int nch = h.c1 - h.c0, nu = h.u1 - h.u0;
   k_run_reset<<<grid_for((int64_t)nu * (R + 1), 256, 1024), 256, 0, s>>>(B, run, R);
   if (nch > 0) k_count<<<grid_for(nch, 1, 2048), kBlock, 0, s>>>(B, run, R);
-  if (nu > 0) k_plan<<<grid_for(nu, 1, 4096), kBlock, 0, s>>>(B, run, R, P.hits_per_bin);
+  if (nu > 0) k_plan<<<grid_for(nu, 1, 4096), kBlock, 0, s>>>(B, run, R, P.hits_per_bin, link_tile_of(P));
   if (nch > 0) k_rowscatter<<<grid_for((nch + kGroup - 1) / kGroup, 1, 8192), kBlock, 0, s>>>(B, run, R);
   if (nu > 0) {
     // dense rows (time frames): the staged sort, one 1024-thread block per CU
@@ -1707,11 +1707,20 @@ hipError_t launch_links(const Bufs &B, const ParamsDev &P, int run, const RunHos
   if (nt > 0) {
     int g = grid_for(nt, 1, 256 * (P.link_blocks_per_cu > 0 ? P.link_blocks_per_cu : 32));
     g = (g + 7) & ~7;  // a multiple of the 8 XCDs
-    switch (P.link_stage) {
-      case 2: k_links<2><<<g, kTile, 0, s>>>(B, P, run); break;
-      case 1: k_links<1><<<g, kTile, 0, s>>>(B, P, run); break;
-      default: k_links<0><<<g, kTile, 0, s>>>(B, P, run); break;
+    const int tile = link_tile_of(P);
+#define TPCCA_LINKS(V, T) k_links<V, T><<<g, T, 0, s>>>(B, P, run)
+    switch (P.link_stage * 4 + (tile == 128 ? 0 : tile == 512 ? 2 : 1)) {
+      case 8: TPCCA_LINKS(2, 128); break;
+      case 9: TPCCA_LINKS(2, 256); break;
+      case 10: TPCCA_LINKS(2, 512); break;
+      case 4: TPCCA_LINKS(1, 128); break;
+      case 5: TPCCA_LINKS(1, 256); break;
+      case 6: TPCCA_LINKS(1, 512); break;
+      case 0: TPCCA_LINKS(0, 128); break;
+      case 2: TPCCA_LINKS(0, 512); break;
+      default: TPCCA_LINKS(0, 256); break;
     }
+#undef TPCCA_LINKS
   }
   return hipGetLastError();
 }
@@ -1763,12 +1772,19 @@ hipError_t launch_chains(const Bufs &B, const ParamsDev &P, int run, const RunHo
 }
 
 // Compute units and resident fit blocks per CU of the current device, for
-// each register variant; queried once per device (contexts on several host
-// threads launch concurrently, hence the lock).
+// each register variant and block size; queried once per device (contexts
+// on several host threads launch concurrently, hence the lock).
 struct KfOccupancy {
   int cus = 1;
-  int per[3] = {1, 1, 1};
+  int per[3][3] = {{1, 1, 1}, {1, 1, 1}, {1, 1, 1}};  // [register variant][64, 128, 256 threads]
 };
+
+template <int kBlk>
+static void kf_occ_row(int per[3]) {
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_kf<5, kBlk>, kBlk, 0);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_kf<4, kBlk>, kBlk, 0);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_kf<6, kBlk>, kBlk, 0);
+}
 
 static const KfOccupancy &kf_occupancy() {
   static std::mutex mu;
@@ -1779,37 +1795,48 @@ static const KfOccupancy &kf_occupancy() {
   auto it = cache.find(dev);
   if (it != cache.end()) return it->second;
   KfOccupancy o;
-  int cus = 0, per[3] = {0, 0, 0};
+  int cus = 0, per[3][3] = {};
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_kf<5>, kKfBlock, 0);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_kf<4>, kKfBlock, 0);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_kf<6>, kKfBlock, 0);
+  kf_occ_row<64>(per[0]);
+  kf_occ_row<128>(per[1]);
+  kf_occ_row<256>(per[2]);
   o.cus = std::max(1, cus);
-  for (int k = 0; k < 3; ++k) o.per[k] = std::max(1, per[k]);
+  for (int v = 0; v < 3; ++v)
+    for (int b = 0; b < 3; ++b) o.per[v][b] = std::max(1, per[b][v]);
   return cache.emplace(dev, o).first->second;
 }
 
 hipError_t launch_kf(const Bufs &B, const ParamsDev &P, int run, const RunHost &h, hipStream_t s) {
   // persistent: exactly the resident capacity of the chip, work taken from a
   // counter
-  // register budgets: 5 (default), 4 or 6 resident waves per SIMD (more
-  // are not reachable: the block's LDS allows 7)
+  // register budgets: 5 (default), 4 or 6 resident waves per SIMD; block
+  // sizes 64, 128 (default) or 256 threads
   const int v = P.kf_min_waves >= 6 ? 2 : P.kf_min_waves == 4 ? 1 : 0;
+  const int blk = kf_block_of(P);
+  const int bi = blk == 64 ? 0 : blk == 256 ? 2 : 1;
   const KfOccupancy &o = kf_occupancy();
   const int cus = o.cus;
-  const int bpc = P.kf_blocks_per_cu > 0 ? std::min(P.kf_blocks_per_cu, o.per[v]) : o.per[v];
-  const int g = grid_for(h.trk_cap, kKfBlock, cus * bpc);
+  const int bpc = P.kf_blocks_per_cu > 0 ? std::min(P.kf_blocks_per_cu, o.per[v][bi]) : o.per[v][bi];
+  const int g = grid_for(h.trk_cap, blk, cus * bpc);
   // the claim words of the selection start at zero (the fit may write them
   // as its tracklets end)
   hipError_t e = launch_fill_u64(B.owner + h.cl0, h.cl1 - h.cl0, 0ull, s);
   if (e != hipSuccess) return e;
   if (P.kf_rows > 0) return launch_kf_rows(B, P, run, h, s);
   if (h.trk_cap > 0) {
-    switch (v) {
-      case 2: k_kf<6><<<g, kKfBlock, 0, s>>>(B, P, run); break;
-      case 1: k_kf<4><<<g, kKfBlock, 0, s>>>(B, P, run); break;
-      default: k_kf<5><<<g, kKfBlock, 0, s>>>(B, P, run); break;
+#define TPCCA_KF(W, T) k_kf<W, T><<<g, T, 0, s>>>(B, P, run)
+    switch (v * 3 + bi) {
+      case 0: TPCCA_KF(5, 64); break;
+      case 2: TPCCA_KF(5, 256); break;
+      case 3: TPCCA_KF(4, 64); break;
+      case 4: TPCCA_KF(4, 128); break;
+      case 5: TPCCA_KF(4, 256); break;
+      case 6: TPCCA_KF(6, 64); break;
+      case 7: TPCCA_KF(6, 128); break;
+      case 8: TPCCA_KF(6, 256); break;
+      default: TPCCA_KF(5, 128); break;
     }
+#undef TPCCA_KF
   }
   return hipGetLastError();
 }

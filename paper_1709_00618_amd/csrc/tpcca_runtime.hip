@@ -32,7 +32,7 @@ struct UnitHost {
 
 int64_t bins_cap_of(int64_t n, int hpb, int R) { return n / hpb + 2 * (int64_t)(R + 1) + 1; }
 int64_t trk_cap_of(int64_t n, int min_chain) { return n / std::max(1, min_chain) + 1; }
-int64_t tile_cap_of(int64_t n, int R) { return n / kTile + R + 2; }
+int64_t tile_cap_of(int64_t n, int R, int tile) { return n / tile + R + 2; }
 
 struct DevBuf {
   void *p = nullptr;
@@ -236,7 +236,7 @@ static void refresh_bufs(tpcca_ctx *c);
   const size_t N = (size_t)std::max<int64_t>((n_cl), 1), U = (size_t)std::max<int64_t>((n_units), 1); \
   const size_t NB = (size_t)std::max<int64_t>((n_bins), 1), T = (size_t)std::max<int64_t>((n_trk), 1); \
   const size_t NC = (size_t)std::max<int64_t>((n_chunks), 1);                                  \
-  const size_t NTILE = N / kTile + U * (R + 2) + 1;                                            \
+  const size_t NTILE = N / kTileMin + U * (R + 2) + 1;                                            \
   const size_t NSCAN = std::max(NB / kScanTile + 2, std::max(2 * NC + 2, T / kScanTile + 2));
 
 static void refresh_bufs(tpcca_ctx *c) {
@@ -320,7 +320,7 @@ static RunHost make_run(tpcca_ctx *c, int u0, int u1) {
   h.trk0 = c->units[u0].trk_base;
   h.trk_cap = (int32_t)(L.trk_base + trk_cap_of(L.n, c->P.min_chain) - h.trk0);
   h.tile0 = c->units[u0].tile_base;
-  h.tile1 = (int32_t)(L.tile_base + tile_cap_of(L.n, c->R));
+  h.tile1 = (int32_t)(L.tile_base + tile_cap_of(L.n, c->R, link_tile_of(c->P)));
   h.dense = (int64_t)(h.cl1 - h.cl0) / ((int64_t)(u1 - u0) * (c->R + 1)) >= 1024 ? 1 : 0;
   return h;
 }
@@ -511,7 +511,7 @@ static int load_unit(tpcca_ctx *c, int32_t slot, int32_t sector, const tpcca_clu
   c->n_total += n;
   c->bins_total += bins_cap_of(n, c->P.hits_per_bin, c->R);
   c->trk_total += trk_cap_of(n, c->P.min_chain);
-  c->tiles_total += tile_cap_of(n, c->R);
+  c->tiles_total += tile_cap_of(n, c->R, link_tile_of(c->P));
   c->tables_dirty = true;
   return TPCCA_OK;
 }
@@ -940,7 +940,7 @@ int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
   capr.cl1 = (int32_t)capN;
   capr.bin1 = capB;
   capr.trk_cap = (int32_t)capT;
-  capr.tile1 = (int32_t)(capN / kTile + capU * (c->R + 2) + 1);
+  capr.tile1 = (int32_t)(capN / link_tile_of(c->P) + capU * (c->R + 2) + 1);
   const bool reuse = c->gexec[0] && c->gen_captured == c->generation && c->gcap.u1 == capr.u1 &&
                      c->gcap.c1 == capr.c1 && c->gcap.cl1 == capr.cl1 && c->gcap.bin1 == capr.bin1 &&
                      c->gcap.trk_cap == capr.trk_cap && c->gcap.tile1 == capr.tile1 &&
@@ -1123,9 +1123,11 @@ void tpcca_tuning_default(tpcca_tuning_t *t) {
 int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
   if (!c || !t) return TPCCA_EINVAL;
   if (!tpcca::tuning_valid(t, c->R)) return TPCCA_EINVAL;
-  // the grid layout of loaded units depends on hits per bin
+  // the grid layout and the tile reservations of loaded units depend on
+  // hits per bin and the tile size
   if (t->grid_hits_per_bin && !c->units.empty() && t->grid_hits_per_bin != c->P.hits_per_bin)
     return TPCCA_ESTATE;
+  if (!c->units.empty() && (t->link_tile ? t->link_tile : kTile) != link_tile_of(c->P)) return TPCCA_ESTATE;
   c->P.kf_min_waves = t->fit_min_waves;
   c->P.kf_claims = t->fit_claims;
   c->P.kf_xcd = t->fit_xcd_slices;
@@ -1134,6 +1136,8 @@ int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
   c->P.kf_bands = t->fit_row_bands;
   c->P.kf_tail = t->fit_tail_units;
   c->P.kf_rows = t->fit_rows;
+  c->P.link_tile = t->link_tile;
+  c->P.kf_block = t->fit_block;
   c->P.kf_pool = t->fit_pool ? t->fit_pool : 64;
   c->P.kf_blocks_per_cu = t->fit_blocks_per_cu;
   c->P.link_blocks_per_cu = t->link_blocks_per_cu;
@@ -1159,6 +1163,8 @@ int tpcca_get_tuning(tpcca_ctx_t *c, tpcca_tuning_t *t) {
   t->fit_row_bands = c->P.kf_bands;
   t->fit_tail_units = c->P.kf_tail;
   t->fit_rows = c->P.kf_rows;
+  t->link_tile = c->P.link_tile;
+  t->fit_block = c->P.kf_block;
   return TPCCA_OK;
 }
 
@@ -1251,7 +1257,7 @@ extern "C" int tpcca_run_batch_noalloc(const tpcca_geometry_t *geo, const tpcca_
     n_total += n;
     bins_total += bins_cap_of(n, P.hits_per_bin, R);
     trk_total += trk_cap_of(n, P.min_chain);
-    tiles_total += tile_cap_of(n, R);
+    tiles_total += tile_cap_of(n, R, link_tile_of(P));
     n_chunks += (n + kChunk - 1) / kChunk;
   }
   if (n_total > 0 && (!bt->cl || !bt->row)) return TPCCA_EINVAL;
@@ -1298,7 +1304,7 @@ extern "C" int tpcca_run_batch_noalloc(const tpcca_geometry_t *geo, const tpcca_
     cl += n;
     bins += bins_cap_of(n, P.hits_per_bin, R);
     trk += trk_cap_of(n, P.min_chain);
-    tiles += tile_cap_of(n, R);
+    tiles += tile_cap_of(n, R, link_tile_of(P));
   }
   RunHost h{};
   h.u0 = 0;
@@ -1366,7 +1372,9 @@ bool tuning_valid(const tpcca_tuning_t *t, int n_rows) {
            t->fit_xcd_slices < 0 || t->fit_xcd_slices > 1 || t->link_stage < 0 || t->link_stage > 2 ||
            t->fit_long_first < 0 || t->fit_row_bands < 0 || t->fit_row_bands > n_rows ||
            t->fit_tail_units < 0 || t->fit_rows < 0 || (t->fit_rows > 0 && t->fit_rows < 64) ||
-           t->fit_rows > 1024);
+           t->fit_rows > 1024 ||
+           !(t->link_tile == 0 || t->link_tile == 128 || t->link_tile == 256 || t->link_tile == 512) ||
+           !(t->fit_block == 0 || t->fit_block == 64 || t->fit_block == 128 || t->fit_block == 256));
 }
 size_t ctx_allocated(tpcca_ctx *c) { return c->allocated; }
 }  // namespace tpcca

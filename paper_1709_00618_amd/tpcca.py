@@ -63,7 +63,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("fit_pool", c_i32), ("fit_blocks_per_cu", c_i32), ("grid_hits_per_bin", c_i32),
                 ("link_blocks_per_cu", c_i32), ("fit_min_waves", c_i32), ("fit_claims", c_i32),
                 ("fit_xcd_slices", c_i32), ("link_stage", c_i32), ("fit_long_first", c_i32),
-                ("fit_row_bands", c_i32), ("fit_tail_units", c_i32), ("fit_rows", c_i32)]
+                ("fit_row_bands", c_i32), ("fit_tail_units", c_i32), ("fit_rows", c_i32),
+                ("link_tile", c_i32), ("fit_block", c_i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

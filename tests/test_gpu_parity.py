@@ -293,6 +293,9 @@ def test_batch_equals_sector_by_sector(tpcca, row_x):
     dict(fit_rows=64, fit_blocks_per_cu=1),
     dict(fit_rows=1024, fit_claims=0, grid_hits_per_bin=2),
     dict(fit_rows=384),
+    # neighbour tiles of 128 and 512 hits, fit blocks of 64 and 256 threads
+    dict(link_tile=128, fit_block=64, fit_blocks_per_cu=10),
+    dict(link_tile=512, fit_block=256, link_stage=1, fit_min_waves=4),
 ])
 def test_schedule_does_not_change_results(tpcca, row_x, knobs):
     """Every launch schedule gives the default schedule's bytes and the oracle's results."""
@@ -426,6 +429,31 @@ def test_fit_within_1e4_of_fp64_replay(tpcca, row_x):
             _fp64.check(st)
             checked += st["tracklets"]
     assert checked > 1500
+
+
+def test_tile_size_is_fixed_once_units_are_loaded(tpcca, row_x):
+    """The neighbour tile size sets the tile reservations of loaded units:
+    changing it then is refused; after a reset it is accepted."""
+    b = tpcgen.minbias_batch(seed=2, n_events=1)
+    with tpcca.Context(row_x) as ctx:
+        cl, row, slot, sec, _ = b.unit(0)
+        ctx.load_sector(slot, sec, cl, row)
+        with pytest.raises(tpcca.TpccaError):
+            ctx.set_tuning(link_tile=128)
+        ctx.set_tuning(link_tile=256, fit_block=64)  # the default tile: accepted
+        ctx.reset()
+        ctx.set_tuning(link_tile=512)
+        ctx.load_sector(slot, sec, cl, row)
+        ctx.run_all(slot, sec)
+        ctx.sync()
+        tr, h = ctx.get_tracks(slot, sec)
+    ref = _parity.oracle_units(b, row_x, which={0})[0]
+    _parity.compare_tracks(tr, h, ref)
+    with tpcca.Context(row_x) as ctx:
+        with pytest.raises(tpcca.TpccaError):
+            ctx.set_tuning(link_tile=300)
+        with pytest.raises(tpcca.TpccaError):
+            ctx.set_tuning(fit_block=96)
 
 
 def test_row_synchronous_fit_on_a_time_frame(tpcca, row_x):
