@@ -415,7 +415,7 @@ typedef struct {
   const tpcca_vertex_t *vertices; /* slot field = compact slot index */
   const uint8_t *flags;         /* per cluster, batch order (as the assignment) */
   const int32_t *rec;           /* 6 per segment */
-  const int32_t *res;           /* 3 per hit, at the hit's position in the track hit array */
+  const int32_t *res;           /* 4 per hit (16-B aligned), at the hit's position in the track hit array */
   const int32_t *seg_n_hits;    /* per segment */
   const int64_t *seg_hit_begin; /* per segment: first hit in the track hit array */
 } tpcca_phase2_view_t;
@@ -443,15 +443,16 @@ int tpcca_get_vertices(tpcca_ctx_t *ctx, int32_t slot, tpcca_vertex_t *out, int3
 int tpcca_get_flags(tpcca_ctx_t *ctx, int32_t slot, int32_t sector, uint8_t *flags, int32_t n);
 /* Compressed form of the unit's tracks (ascending start_id): 6 int32 per
    track (row, y and z step counts of the first won cluster, FP32 bits of
-   sin phi, tan lambda, q/pT) and 3 int32 per won hit (row step, residual of
-   y, of z; zeros for the first). */
+   sin phi, tan lambda, q/pT) and 4 int32 per won hit (row step, residual of
+   y, of z, 0; zeros for the first); hits_cap counts hits. */
 int tpcca_get_compressed(tpcca_ctx_t *ctx, int32_t slot, int32_t sector, int32_t *rec, int32_t seg_cap,
                          int32_t *res, int64_t hits_cap, int32_t *n_seg, int64_t *n_hits);
 int tpcca_phase2_view(tpcca_ctx_t *ctx, tpcca_phase2_view_t *out);
 /* Decompression (device pointers, queued on ctx's stream): n_seg records
-   (6 int32), their hits' residuals (3 int32 per hit, hit_begin / n_hits per
+   (6 int32), their hits' residuals (4 int32 per hit, 16-B aligned, hit_begin / n_hits per
    record) -> the quantised coordinates yq, zq and the rows of every hit, at
-   the same positions.  Uses ctx's geometry and phase parameters. */
+   the same positions.  Uses ctx's geometry and phase parameters.  EINVAL if
+   res is not 16-B aligned. */
 int tpcca_decompress(tpcca_ctx_t *ctx, int32_t n_seg, const int32_t *n_hits, const int64_t *hit_begin,
                      const int32_t *rec, const int32_t *res, int32_t *yq, int32_t *zq, uint8_t *rows);
 

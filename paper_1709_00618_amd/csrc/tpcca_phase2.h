@@ -42,6 +42,8 @@ struct P2Counts {
   int32_t n_seg, n_final, n_cand, n_group, n_vtx, n_slots;
   int64_t n_final_hits;
   int64_t n_pairs;               // candidate pairs of the merge
+  int32_t seg_next, fin_next;    // work counters of the per-lane segment and refit kernels
+  int32_t pad_[2];
 };
 
 struct P2Bufs {
@@ -68,6 +70,7 @@ struct P2Bufs {
   unsigned long long *best_a;    // per B: (chi2 bits << 32) | key of its best A
   int32_t *next, *prev;          // merge links (segment indices)
   int32_t *final_of;             // per segment
+  int32_t *seg_fpos;             // per segment: first position of its hits in its final's hit list
   int32_t *final_start;          // per final: innermost segment
   int32_t *final_nhits;
   int64_t *final_hbeg;           // per final: first entry in final_hits
@@ -82,7 +85,7 @@ struct P2Bufs {
   int32_t *slot_vbeg, *slot_vend;// per slot: vertex range
   uint8_t *flags;                // per global cluster index
   int32_t *rec;                  // 6 per segment
-  int32_t *res;                  // 3 per hit (global hit index of hits_out)
+  int32_t *res;                  // 4 per hit (global hit index of hits_out), 16-B aligned
   int64_t *scan_tmp;
   P2Counts *cnt;
 };

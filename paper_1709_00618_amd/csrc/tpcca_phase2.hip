@@ -177,6 +177,8 @@ __global__ __launch_bounds__(1024) void k_p2_seg_index(Bufs B, P2Bufs Q, int R) 
   if (threadIdx.x == 0) {
     Q.seg_begin[Q.n_units] = (int32_t)carry;
     Q.cnt->n_seg = (int32_t)carry;
+    Q.cnt->seg_next = 0;
+    Q.cnt->fin_next = 0;
   }
 }
 
@@ -223,25 +225,51 @@ struct CmpFit {
 // Per hit position of the track hit array: the hit's y, z, pad row and
 // cluster ID gathered once (one coalesced pass), so that the per-track
 // kernels below read their hits contiguously instead of chasing cluster IDs.
-__global__ __launch_bounds__(256) void k_p2_hits(Bufs B, P2Bufs Q) {
+__global__ __launch_bounds__(256) void k_p2_hits(Bufs B, P2Bufs Q, int R) {
+  // the pad-row positions: the row of an assigned cluster is the one its x
+  // lies on (it passed that test when it was loaded; rows lie more than
+  // 2e-3 cm apart), found in LDS instead of a random read of its row byte
+  __shared__ float s_rx[kMaxRows + 1];
+  __shared__ int s_unit;
+  for (int i = threadIdx.x; i < R; i += blockDim.x) s_rx[i] = B.row_x[i];
   const int U = Q.n_units;
   const int64_t h_lo = B.unit_res[0].hit_begin;
   const int64_t h_hi = B.unit_res[U - 1].hit_begin + B.unit_res[U - 1].n_track_hits;
-  for (int64_t h = h_lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < h_hi;
-       h += (int64_t)gridDim.x * blockDim.x) {
-    // unit whose hit range holds h (ranges ascend with the unit; runs leave gaps)
-    int lo = 0, hi = U;
-    while (hi - lo > 1) {
-      const int m = (lo + hi) >> 1;
-      if (B.unit_res[m].hit_begin <= h) lo = m;
-      else hi = m;
+  for (int64_t hb = h_lo + blockIdx.x * (int64_t)blockDim.x; hb < h_hi; hb += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t h = hb + threadIdx.x;
+    // unit whose hit range holds the block's first hit (ranges ascend with
+    // the unit; runs leave gaps), found once per block
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int lo = 0, hi = U;
+      while (hi - lo > 1) {
+        const int m = (lo + hi) >> 1;
+        if (B.unit_res[m].hit_begin <= hb) lo = m;
+        else hi = m;
+      }
+      s_unit = lo;
     }
-    const tpcca_unit_result_t &r = B.unit_res[lo];
+    __syncthreads();
+    if (h >= h_hi) continue;
+    int u = s_unit;
+    while (u + 1 < U && B.unit_res[u + 1].hit_begin <= h) ++u;  // the block's range crosses a unit
+    const tpcca_unit_result_t &r = B.unit_res[u];
     if (h >= r.hit_begin + r.n_track_hits) continue;
-    const UnitDev U_ = B.units[lo];
+    const UnitDev U_ = B.units[u];
     const int id = B.hits_out[h];
     const float4 c = U_.cl[id];
-    Q.hrec[h] = make_float4(c.y, c.z, __int_as_float((int)U_.row[id]), __int_as_float(id));
+    int lo = 0, n = R;  // first row with x >= c.x - 1e-3
+    while (n > 0) {
+      const int half = n >> 1;
+      if (s_rx[lo + half] < c.x - 1e-3f) {
+        lo += half + 1;
+        n -= half + 1;
+      } else {
+        n = half;
+      }
+    }
+    const int row = (lo < R && fabsf(c.x - s_rx[lo]) <= 1e-3f) ? lo : (int)U_.row[id];
+    Q.hrec[h] = make_float4(c.y, c.z, __int_as_float(row), __int_as_float(id));
   }
 }
 
@@ -250,66 +278,111 @@ __global__ __launch_bounds__(256) void k_p2_hits(Bufs B, P2Bufs Q) {
 // ascending order) and the segment's compressed form (record and residuals);
 // clears the pairing words.
 __global__ __launch_bounds__(256) void k_p2_seg_prep(Bufs B, P2Bufs Q, ParamsDev P, P2Params q) {
+  __shared__ float s_rx[kMaxRows + 1];  // pad-row positions (off the dependent chain)
+  for (int i = threadIdx.x; i < P.n_rows; i += blockDim.x) s_rx[i] = B.row_x[i];
+  __syncthreads();
   const int n = Q.cnt->n_seg;
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
-    const int u = p2_unit_of(Q, g);
-    const tpcca_track_t &t = p2_track(B, Q, g, u);
-    const int64_t h0 = p2_hit0(B, t, u);
-    const int nh = t.n_hits;
-    KState st = p2_inner(t);
-    const float4 *hr = Q.hrec + h0;
-    const float4 c0 = hr[0];
-    const int r_first = __float_as_int(c0.z);
-    int r_last = r_first;
-    bool ok = kf_propagate(P, st, B.row_x[r_first]);
-    // Sec. 3 compression of the segment in the same pass over its hits (the
-    // two fits are independent chains of operations)
-    const int32_t yq0 = p2_quant(c0.x, q.qy), zq0 = p2_quant(c0.y, q.qz);
-    int32_t *rc = Q.rec + 6 * (int64_t)g;
-    rc[0] = r_first;
-    rc[1] = yq0;
-    rc[2] = zq0;
-    rc[3] = (int32_t)__float_as_uint(t.p[2]);
-    rc[4] = (int32_t)__float_as_uint(t.p[3]);
-    rc[5] = (int32_t)__float_as_uint(t.p[4]);
-    CmpFit fit;
-    fit.start(P, q, B.row_x, r_first, yq0, zq0, t.p[2], t.p[3], t.p[4]);
-    int32_t *rs = Q.res + 3 * h0;
-    rs[0] = rs[1] = rs[2] = 0;
-    float4 nxt = nh > 1 ? hr[1] : c0;
-    for (int k = 1; k < nh; ++k) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1;
+  // Persistent, one segment per lane at a time: every iteration takes one
+  // hit step of each lane's segment, and a lane whose segment is done writes
+  // its outputs and takes the next one from its wave's pool (64 consecutive
+  // segments claimed with one atomic), so lanes do not wait for the longest
+  // segment of their wave.  Each segment sees the same operation sequence.
+  int g = -1, u = 0, k = 0, nh = 0, r_first = 0, r_last = 0;
+  int64_t h0 = 0;
+  bool ok = false;
+  float zin = 0.0f;
+  KState st;
+  CmpFit fit;
+  float4 nxt = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  int pnext = 0, pend = 0;
+  bool exhausted = false;
+  for (;;) {
+    if (g >= 0 && k >= nh) {
+      // the segment is done: its outer end and pairing words
+      P2Out o;
+      o.x = st.x;
+#pragma unroll
+      for (int j = 0; j < 5; ++j) o.p[j] = st.p[j];
+#pragma unroll
+      for (int j = 0; j < 15; ++j) o.C[j] = st.C[j];
+      o.ok = ok ? 1 : 0;
+      Q.seg_out[g] = o;
+      Q.seg_unit[g] = u;
+      Q.seg_nh[g] = nh;
+      Q.seg_hb[g] = h0;
+      Q.seg_rows[g] = make_int2(r_first, r_last);
+      Q.seg_zin[g] = zin;
+      Q.seg_zout[g] = st.p[1] + zin;
+      Q.best_a[g] = ~0ull;
+      Q.best_b[g] = ~0ull;
+      Q.next[g] = -1;
+      Q.prev[g] = -1;
+      g = -1;
+    }
+    const unsigned long long idle = __ballot(g < 0);
+    if (idle) {
+      if (pnext == pend && !exhausted) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&Q.cnt->seg_next, 64);
+        base = __shfl(base, 0, 64);
+        if (base >= n) {
+          exhausted = true;
+        } else {
+          pnext = base;
+          pend = min(base + 64, n);
+        }
+      }
+      if (pnext < pend) {
+        const int take = min(__popcll(idle), pend - pnext);
+        const int rank = __popcll(idle & below);
+        if (g < 0 && rank < take) {
+          g = pnext + rank;
+          u = p2_unit_of(Q, g);
+          const tpcca_track_t &t = p2_track(B, Q, g, u);
+          h0 = p2_hit0(B, t, u);
+          nh = t.n_hits;
+          zin = t.p[1];
+          st = p2_inner(t);
+          const float4 *hr = Q.hrec + h0;
+          const float4 c0 = hr[0];
+          r_first = __float_as_int(c0.z);
+          r_last = r_first;
+          ok = kf_propagate(P, st, s_rx[r_first]);
+          // Sec. 3 compression of the segment in the same pass over its hits
+          // (the two fits are independent chains of operations)
+          const int32_t yq0 = p2_quant(c0.x, q.qy), zq0 = p2_quant(c0.y, q.qz);
+          int32_t *rc = Q.rec + 6 * (int64_t)g;
+          rc[0] = r_first;
+          rc[1] = yq0;
+          rc[2] = zq0;
+          rc[3] = (int32_t)__float_as_uint(t.p[2]);
+          rc[4] = (int32_t)__float_as_uint(t.p[3]);
+          rc[5] = (int32_t)__float_as_uint(t.p[4]);
+          fit.start(P, q, s_rx, r_first, yq0, zq0, t.p[2], t.p[3], t.p[4]);
+          // residuals: one aligned 16-B record per hit (row step, y, z, 0)
+          reinterpret_cast<int4 *>(Q.res)[h0] = make_int4(0, 0, 0, 0);
+          nxt = nh > 1 ? hr[1] : c0;
+          k = 1;
+        }
+        pnext += take;
+      }
+    }
+    if (!__any(g >= 0)) break;
+    if (g >= 0 && k < nh) {
       const float4 c = nxt;
-      if (k + 1 < nh) nxt = hr[k + 1];  // the next record's load overlaps this step
+      if (k + 1 < nh) nxt = Q.hrec[h0 + k + 1];  // the next record's load overlaps this step
       const int r = __float_as_int(c.z);
-      if (ok && !kf_propagate(P, st, B.row_x[r])) ok = false;
+      if (ok && !kf_propagate(P, st, s_rx[r])) ok = false;
       int32_t py, pz;
-      const bool pok = fit.predict(P, q, B.row_x, r, py, pz);
+      const bool pok = fit.predict(P, q, s_rx, r, py, pz);
       const int32_t yq = p2_quant(c.x, q.qy), zq = p2_quant(c.y, q.qz);
-      rs[3 * k] = r - r_last;
-      rs[3 * k + 1] = yq - py;
-      rs[3 * k + 2] = zq - pz;
+      reinterpret_cast<int4 *>(Q.res)[h0 + k] = make_int4(r - r_last, yq - py, zq - pz, 0);
       fit.take(P, q, pok, yq, zq);
       r_last = r;
+      ++k;
     }
-    P2Out o;
-    o.x = st.x;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) o.p[k] = st.p[k];
-#pragma unroll
-    for (int k = 0; k < 15; ++k) o.C[k] = st.C[k];
-    o.ok = ok ? 1 : 0;
-    Q.seg_out[g] = o;
-    Q.seg_unit[g] = u;
-    Q.seg_nh[g] = nh;
-    Q.seg_hb[g] = h0;
-    Q.seg_rows[g] = make_int2(r_first, r_last);
-    const float zr = t.p[1];
-    Q.seg_zin[g] = zr;
-    Q.seg_zout[g] = st.p[1] + zr;
-    Q.best_a[g] = ~0ull;
-    Q.best_b[g] = ~0ull;
-    Q.next[g] = -1;
-    Q.prev[g] = -1;
   }
 }
 
@@ -629,6 +702,7 @@ __global__ __launch_bounds__(256) void k_p2_final_count(Bufs B, P2Bufs Q) {
     // boundary per link); the bound also guards the loop
     for (int g = Q.final_start[f]; g >= 0 && m < 18; g = Q.next[g], ++m) {
       const int u = Q.seg_unit[g];
+      Q.seg_fpos[g] = nh;
       nh += p2_track(B, Q, g, u).n_hits;
       Q.final_of[g] = f;
     }
@@ -636,132 +710,211 @@ __global__ __launch_bounds__(256) void k_p2_final_count(Bufs B, P2Bufs Q) {
   }
 }
 
-// Refit of each final track (one thread each), its extrapolation to the
-// axis and its hit list.  The refit starts from the outermost segment's
-// outer end with the covariance times refit_inflate, updates with every won
-// hit from the outside in (propagating hit to hit), rotates the state into
-// the next inner segment's frame between segments, and keeps z relative to
-// the outermost segment's inner z.
+// Hit lists of the final tracks, inner segment first: sixteen lanes per
+// segment copy its won hits (sector << 24 | cluster ID) to its place in its
+// final's list, contiguous reads and writes.
+__global__ __launch_bounds__(256) void k_p2_final_hits(Bufs B, P2Bufs Q) {
+  const int n = Q.cnt->n_seg;
+  const int gl = threadIdx.x & 15;
+  const int ng = (gridDim.x * blockDim.x) >> 4;
+  for (int g = (blockIdx.x * blockDim.x + threadIdx.x) >> 4; g < n; g += ng) {
+    const int f = Q.final_of[g];
+    const int64_t dst = Q.final_hbeg[f] + Q.seg_fpos[g];
+    const int64_t src = Q.seg_hb[g];
+    const int nh = Q.seg_nh[g];
+    const int32_t sec = Q.units[Q.seg_unit[g]].sector << 24;
+    for (int j = gl; j < nh; j += 16) Q.final_hits[dst + j] = sec | B.hits_out[src + j];
+  }
+}
+
+// Refit of each final track and its extrapolation to the axis.  The refit
+// starts from the outermost segment's outer end with the covariance times
+// refit_inflate, updates with every won hit from the outside in
+// (propagating hit to hit), rotates the state into the next inner segment's
+// frame between segments, and keeps z relative to the outermost segment's
+// inner z; then z at the plane x = 0 in dca_steps equal steps (Sec. 5).
+//
+// Persistent, one final track per lane at a time: every iteration takes one
+// step (a hit, a rotation into the next segment's frame, or a step to the
+// axis) of each lane's track, and a lane whose track is done takes the next
+// one from its wave's pool (64 consecutive tracks claimed with one atomic),
+// so tracks of 1 and of 18 segments do not hold each other up.  Each track
+// sees the same operation sequence.
+__device__ __forceinline__ void p2_final_failed(const P2Bufs &Q, int f) {
+  tpcca_final_t &o = Q.finals[f];
+  o.status = 2;
+  o.n_hits = Q.final_nhits[f];
+  o.ndf = 0;
+  o.row_ref = 0;
+  o.x_ref = 0.0f;
+  o.chi2 = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) o.p[k] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 15; ++k) o.cov[k] = 0.0f;
+  o.z0_ok = 0;
+  o.z0 = 0.0f;
+  o.t0 = 0.0f;
+  o.z_conv = 0.0f;
+}
+
 __global__ __launch_bounds__(256) void k_p2_refit(Bufs B, P2Bufs Q, ParamsDev P, P2Params q) {
+  // the pad-row positions in LDS: a row step reads its plane without a
+  // global load on the dependent chain
+  __shared__ float s_rx[kMaxRows + 1];
+  for (int i = threadIdx.x; i < P.n_rows; i += blockDim.x) s_rx[i] = B.row_x[i];
+  __syncthreads();
   const int n = Q.cnt->n_final;
-  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < n; f += gridDim.x * blockDim.x) {
-    const int g0 = Q.final_start[f];
-    // rows grow along a chain and each link crosses a sector boundary of one
-    // side: at most 18 segments
-    int chain[18];
-    int m = 0;
-    for (int g = g0; g >= 0 && m < 18; g = Q.next[g]) chain[m++] = g;
-    tpcca_final_t o;
-    const int u0 = Q.seg_unit[g0];
-    o.slot = Q.units[u0].slot;
-    o.sector = Q.units[u0].sector;
-    o.n_seg = m;
-    o.vertex = -1;
-    o.z0_ok = 0;
-    o.first_seg = (int32_t)p2_key(Q, g0, u0, o.sector);
-    o.hit_begin = Q.final_hbeg[f];
-    o.pad_ = 0;
-    // hit list, inner to outer
-    int64_t w = o.hit_begin;
-    for (int k = 0; k < m; ++k) {
-      const int g = chain[k];
-      const int u = Q.seg_unit[g];
-      const tpcca_track_t &t = p2_track(B, Q, g, u);
-      const int64_t h0 = p2_hit0(B, t, u);
-      const int32_t sec = Q.units[u].sector << 24;
-      for (int j = 0; j < t.n_hits; ++j) Q.final_hits[w++] = sec | B.hits_out[h0 + j];
-    }
-    bool ok = Q.seg_out[chain[m - 1]].ok != 0;
-    KState st;
-    float zr = 0.0f, chi2 = 0.0f;
-    int nh = 0, row_ref = 0;
-    if (ok) {
-      const P2Out &oe = Q.seg_out[chain[m - 1]];
-      st.x = oe.x;
+  const int N = q.dca_steps;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1;
+  enum : int { kFree = 0, kHits = 1, kAxis = 2 };
+  int phase = kFree;
+  int f = 0, gc = 0, sec_c = 0, sector0 = 0, j = 0, nh = 0, row_ref = 0, kd = 0;
+  int64_t hb = 0;
+  float zr = 0.0f, chi2 = 0.0f, x0 = 0.0f;
+  KState st;
+  float4 nxt = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  int pnext = 0, pend = 0;
+  bool exhausted = false;
+  for (;;) {
+    // ---- transitions of lanes whose current segment, hits or axis steps
+    // are done
+    if (phase == kHits && j < 0) {
+      const int gp = Q.prev[gc];  // the next inner segment of the chain
+      if (gp < 0) {
+        // every hit taken: the fit at the innermost hit
+        tpcca_final_t &o = Q.finals[f];
+        o.status = 0;
+        o.n_hits = nh;
+        o.ndf = 2 * nh - 5;
+        o.row_ref = row_ref;
+        o.x_ref = st.x;
+        o.chi2 = chi2;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) st.p[k] = oe.p[k];
+        for (int k = 0; k < 5; ++k) o.p[k] = st.p[k];
+        o.p[1] = st.p[1] + zr;
 #pragma unroll
-      for (int k = 0; k < 15; ++k) st.C[k] = oe.C[k] * q.inflate;
-      zr = Q.seg_zin[chain[m - 1]];
-      for (int k = m - 1; k >= 0 && ok; --k) {
-        const int g = chain[k];
-        const int u = Q.seg_unit[g];
-        if (k < m - 1) {
-          const int so = Q.units[Q.seg_unit[chain[k + 1]]].sector;
-          const float sn = p2_next_sector(Q.units[u].sector) == so ? q.sn : -q.sn;
-          if (!p2_rotate(q.max_sin, q.cs, sn, st)) {
-            ok = false;
-            break;
-          }
-        }
-        const float4 *hr = Q.hrec + Q.seg_hb[g];
-        const int nhs = Q.seg_nh[g];
-        float4 nxt = hr[nhs - 1];
-        for (int j = nhs - 1; j >= 0; --j) {
-          const float4 c = nxt;
-          if (j > 0) nxt = hr[j - 1];  // the next record's load overlaps this step
-          const int r = __float_as_int(c.z);
-          if (nh > 0 && !kf_propagate(P, st, B.row_x[r])) {
-            ok = false;
-            break;
-          }
-          float c2;
-          if (!kf_update(P, st, c.x, c.y - zr, c2)) {
-            ok = false;
-            break;
-          }
-          chi2 = chi2 + c2;
-          ++nh;
-          row_ref = r;
-        }
-      }
-    }
-    if (ok) {
-      o.status = 0;
-      o.n_hits = nh;
-      o.ndf = 2 * nh - 5;
-      o.row_ref = row_ref;
-      o.x_ref = st.x;
-      o.chi2 = chi2;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) o.p[k] = st.p[k];
-      o.p[1] = st.p[1] + zr;
-#pragma unroll
-      for (int k = 0; k < 15; ++k) o.cov[k] = st.C[k];
-      // Sec. 5: z at the plane x = 0 of the frame in dca_steps equal steps
-      KState sz = st;
-      const int N = q.dca_steps;
-      const float x0 = st.x;
-      bool zok = true;
-      for (int k = 1; k <= N && zok; ++k) {
-        const float xk = (x0 * (float)(N - k)) / (float)N;
-        zok = kf_propagate(P, sz, xk);
-      }
-      if (zok) {
-        const float z0 = sz.p[1] + zr;
-        o.z0_ok = 1;
-        o.z0 = z0;
-        o.t0 = p2_side(o.sector) == 0 ? -z0 / q.vdrift : z0 / q.vdrift;
+        for (int k = 0; k < 15; ++k) o.cov[k] = st.C[k];
+        o.z_conv = st.p[1] + zr;
+        x0 = st.x;
+        kd = 1;
+        phase = kAxis;
       } else {
+        const int sec_p = Q.units[Q.seg_unit[gp]].sector;
+        const float sn = p2_next_sector(sec_p) == sec_c ? q.sn : -q.sn;
+        if (!p2_rotate(q.max_sin, q.cs, sn, st)) {
+          p2_final_failed(Q, f);
+          phase = kFree;
+        } else {
+          gc = gp;
+          sec_c = sec_p;
+          hb = Q.seg_hb[gc];
+          j = Q.seg_nh[gc] - 1;
+          nxt = Q.hrec[hb + j];
+        }
+      }
+    }
+    if (phase == kAxis && kd > N) {
+      tpcca_final_t &o = Q.finals[f];
+      const float z0 = st.p[1] + zr;
+      o.z0_ok = 1;
+      o.z0 = z0;
+      o.t0 = p2_side(sector0) == 0 ? -z0 / q.vdrift : z0 / q.vdrift;
+      phase = kFree;
+    }
+    // ---- idle lanes take the next tracks of their wave's pool
+    const unsigned long long idle = __ballot(phase == kFree);
+    if (idle) {
+      if (pnext == pend && !exhausted) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&Q.cnt->fin_next, 64);
+        base = __shfl(base, 0, 64);
+        if (base >= n) {
+          exhausted = true;
+        } else {
+          pnext = base;
+          pend = min(base + 64, n);
+        }
+      }
+      if (pnext < pend) {
+        const int take = min(__popcll(idle), pend - pnext);
+        const int rank = __popcll(idle & below);
+        if (phase == kFree && rank < take) {
+          f = pnext + rank;
+          const int g0 = Q.final_start[f];
+          // rows grow along a chain and each link crosses a sector boundary
+          // of one side: at most 18 segments
+          int last = g0, m = 1;
+          for (int g = Q.next[g0]; g >= 0 && m < 18; g = Q.next[g]) {
+            last = g;
+            ++m;
+          }
+          const int u0 = Q.seg_unit[g0];
+          sector0 = Q.units[u0].sector;
+          tpcca_final_t &o = Q.finals[f];
+          o.slot = Q.units[u0].slot;
+          o.sector = sector0;
+          o.n_seg = m;
+          o.vertex = -1;
+          o.z0_ok = 0;
+          o.first_seg = (int32_t)p2_key(Q, g0, u0, sector0);
+          o.hit_begin = Q.final_hbeg[f];
+          o.pad_ = 0;
+          const P2Out &oe = Q.seg_out[last];
+          if (oe.ok == 0) {
+            p2_final_failed(Q, f);
+          } else {
+            st.x = oe.x;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) st.p[k] = oe.p[k];
+#pragma unroll
+            for (int k = 0; k < 15; ++k) st.C[k] = oe.C[k] * q.inflate;
+            zr = Q.seg_zin[last];
+            chi2 = 0.0f;
+            nh = 0;
+            row_ref = 0;
+            gc = last;
+            sec_c = Q.units[Q.seg_unit[last]].sector;
+            hb = Q.seg_hb[gc];
+            j = Q.seg_nh[gc] - 1;
+            nxt = Q.hrec[hb + j];
+            phase = kHits;
+          }
+        }
+        pnext += take;
+      }
+    }
+    if (!__any(phase != kFree)) {
+      if (exhausted) break;
+      continue;
+    }
+    // ---- one step
+    if (phase == kHits && j >= 0) {
+      const float4 c = nxt;
+      if (j > 0) nxt = Q.hrec[hb + j - 1];  // the next record's load overlaps this step
+      const int r = __float_as_int(c.z);
+      float c2;
+      if ((nh > 0 && !kf_propagate(P, st, s_rx[r])) || !kf_update(P, st, c.x, c.y - zr, c2)) {
+        p2_final_failed(Q, f);
+        phase = kFree;
+      } else {
+        chi2 = chi2 + c2;
+        ++nh;
+        row_ref = r;
+        --j;
+      }
+    } else if (phase == kAxis) {
+      const float xk = (x0 * (float)(N - kd)) / (float)N;
+      if (!kf_propagate(P, st, xk)) {
+        tpcca_final_t &o = Q.finals[f];
         o.z0 = 0.0f;
         o.t0 = 0.0f;
+        phase = kFree;
+      } else {
+        ++kd;
       }
-    } else {
-      o.status = 2;
-      o.n_hits = Q.final_nhits[f];
-      o.ndf = 0;
-      o.row_ref = 0;
-      o.x_ref = 0.0f;
-      o.chi2 = 0.0f;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) o.p[k] = 0.0f;
-#pragma unroll
-      for (int k = 0; k < 15; ++k) o.cov[k] = 0.0f;
-      o.z0 = 0.0f;
-      o.t0 = 0.0f;
     }
-    o.z_conv = o.p[1];
-    Q.finals[f] = o;
   }
 }
 
@@ -949,12 +1102,12 @@ __global__ __launch_bounds__(256) void k_p2_decompress(ParamsDev P, P2Params q, 
     zq[h0] = rc[2];
     rows[h0] = (uint8_t)r;
     for (int j = 1; j < n_hits[g]; ++j) {
-      const int32_t *rs = res + 3 * (h0 + j);
-      r += rs[0];
+      const int4 rs = reinterpret_cast<const int4 *>(res)[h0 + j];
+      r += rs.x;
       if (r < 0 || r >= R) break;  // corrupt input: leave the rest untouched
       int32_t py, pz;
       const bool ok = fit.predict(P, q, row_x, r, py, pz);
-      const int32_t y = rs[1] + py, z = rs[2] + pz;
+      const int32_t y = rs.y + py, z = rs.z + pz;
       yq[h0 + j] = y;
       zq[h0 + j] = z;
       rows[h0 + j] = (uint8_t)r;
@@ -989,8 +1142,8 @@ hipError_t p2_launch_merge(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, c
   const int64_t cells = p2_grid_cells(seg_cap, n_units, R);
   k_p2_fill_i32<<<p2_grid(cells, 256, 8192), 256, 0, s>>>(Q.bin_cnt, cells, 0);
   k_p2_seg_index<<<1, 1024, 0, s>>>(B, Q, R);
-  k_p2_hits<<<p2_grid(hit_span, 256, 16384), 256, 0, s>>>(B, Q);
-  k_p2_seg_prep<<<gs, 256, 0, s>>>(B, Q, P, q);
+  k_p2_hits<<<p2_grid(hit_span, 256, 16384), 256, 0, s>>>(B, Q, R);
+  k_p2_seg_prep<<<p2_grid(seg_cap, 256, 2048), 256, 0, s>>>(B, Q, P, q);  // persistent
   k_p2_zrange<<<std::min(n_units, 4096), 256, 0, s>>>(Q);
   k_p2_bin_count<<<gs, 256, 0, s>>>(Q);
   k_p2_bin_scan<<<std::min(n_units, 4096), 1024, 0, s>>>(Q, R);
@@ -1019,7 +1172,8 @@ hipError_t p2_launch_pairs(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, c
   e = p2_scan(GetFinalHits{Q.final_nhits}, PutFinalHits{Q.final_hbeg}, &Q.cnt->n_final, seg_cap, Q.scan_tmp,
               nullptr, &Q.cnt->n_final_hits, s);
   if (e != hipSuccess) return e;
-  k_p2_refit<<<gs, 256, 0, s>>>(B, Q, P, q);
+  k_p2_final_hits<<<p2_grid((int64_t)seg_cap * 16, 256, 16384), 256, 0, s>>>(B, Q);
+  k_p2_refit<<<p2_grid(seg_cap, 256, 2048), 256, 0, s>>>(B, Q, P, q);  // persistent
   // vertex candidates, compacted with their sort keys
   e = p2_scan(GetCand{Q.finals, q}, PutCand{Q.finals, Q.vkey[0], Q.vval[0]}, &Q.cnt->n_final, seg_cap,
               Q.scan_tmp, &Q.cnt->n_cand, nullptr, s);

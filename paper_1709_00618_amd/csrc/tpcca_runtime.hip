@@ -87,7 +87,7 @@ struct tpcca_ctx {
   // second phase (Sec. 2 merging and refit, Sec. 5 vertices, Sec. 3
   // compression and rejection)
   tpcca_phase2_params_t p2params{};
-  DevBuf p2units, p2seg_begin, p2seg_unit, p2seg_nh, p2seg_hb, p2seg_rows, p2seg_zin, p2seg_zout, p2seg_out,
+  DevBuf p2units, p2seg_begin, p2seg_unit, p2seg_nh, p2seg_hb, p2seg_fpos, p2seg_rows, p2seg_zin, p2seg_zout, p2seg_out,
       p2zmm, p2unit_nz, p2unit_bbase, p2bin_cnt, p2bin_beg, p2bin_seg, p2bin_rz, p2hrec, p2seg_flag, p2pairs, p2best_b, p2best_a, p2next, p2prev, p2final_of, p2final_start,
       p2final_nhits, p2final_hbeg, p2finals, p2final_hits, p2vkey0, p2vkey1, p2vval0, p2vval1, p2gstart,
       p2group_pos, p2vertices, p2slot_first, p2slot_vbeg, p2slot_vend, p2flags, p2rec, p2res, p2scan, p2cnt,
@@ -650,7 +650,8 @@ int tpcca_destroy(tpcca_ctx_t *c) {
                    &c->dnc, &c->flag, &c->starts, &c->tiles, &c->sval, &c->tofg, &c->kf_order, &c->kf_tmp, &c->band_tmp, &c->srow, &c->cinfo, &c->trk_start, &c->trk_unit, &c->unit_tbegin, &c->trk,
                    &c->trk_hits, &c->owner, &c->accv, &c->wonmask, &c->accx, &c->tracks, &c->hits_out,
                    &c->assign, &c->unit_res, &c->scan_tmp, &c->zo_tmp, &c->zo_cnt, &c->kf_chunks, &c->in_cl, &c->in_row,
-                   &c->p2units, &c->p2seg_begin, &c->p2seg_unit, &c->p2seg_nh, &c->p2seg_hb, &c->p2seg_rows,
+                   &c->p2units, &c->p2seg_begin, &c->p2seg_unit, &c->p2seg_nh, &c->p2seg_hb, &c->p2seg_fpos,
+                   &c->p2seg_rows,
                    &c->p2seg_zin, &c->p2seg_zout, &c->p2seg_out, &c->p2zmm, &c->p2unit_nz, &c->p2unit_bbase, &c->p2bin_cnt, &c->p2bin_beg,
                    &c->p2bin_seg, &c->p2bin_rz, &c->p2hrec, &c->p2seg_flag, &c->p2pairs, &c->p2best_b, &c->p2best_a, &c->p2next, &c->p2prev, &c->p2final_of,
                    &c->p2final_start, &c->p2final_nhits, &c->p2final_hbeg, &c->p2finals, &c->p2final_hits,
@@ -1442,7 +1443,8 @@ int p2_ensure(tpcca_ctx *c, int64_t U, int64_t T, int64_t N, int64_t S) {
   } list[] = {
       {&c->p2units, sizeof(P2Unit) * U}, {&c->p2seg_begin, sizeof(int32_t) * (U + 1)},
       {&c->p2seg_unit, sizeof(int32_t) * T}, {&c->p2seg_nh, sizeof(int32_t) * T},
-      {&c->p2seg_hb, sizeof(int64_t) * T}, {&c->p2seg_rows, sizeof(int2) * T},
+      {&c->p2seg_hb, sizeof(int64_t) * T}, {&c->p2seg_fpos, sizeof(int32_t) * T},
+      {&c->p2seg_rows, sizeof(int2) * T},
       {&c->p2seg_zin, sizeof(float) * T}, {&c->p2seg_zout, sizeof(float) * T},
       {&c->p2seg_out, sizeof(P2Out) * T}, {&c->p2zmm, sizeof(int2) * U},
       {&c->p2unit_nz, sizeof(int32_t) * U}, {&c->p2unit_bbase, sizeof(int64_t) * U},
@@ -1461,7 +1463,7 @@ int p2_ensure(tpcca_ctx *c, int64_t U, int64_t T, int64_t N, int64_t S) {
       {&c->p2group_pos, sizeof(int32_t) * T}, {&c->p2vertices, sizeof(tpcca_vertex_t) * T},
       {&c->p2slot_first, sizeof(int32_t) * S}, {&c->p2slot_vbeg, sizeof(int32_t) * S},
       {&c->p2slot_vend, sizeof(int32_t) * S}, {&c->p2flags, (size_t)N},
-      {&c->p2rec, sizeof(int32_t) * 6 * T}, {&c->p2res, sizeof(int32_t) * 3 * N},
+      {&c->p2rec, sizeof(int32_t) * 6 * T}, {&c->p2res, sizeof(int32_t) * 4 * N},
       {&c->p2scan, sizeof(int64_t) * (tiles + 2)}, {&c->p2cnt, sizeof(P2Counts)},
   };
   for (auto &e : list) RCCHK(ensure(c, *e.b, e.bytes, 0));
@@ -1490,6 +1492,7 @@ int p2_ensure(tpcca_ctx *c, int64_t U, int64_t T, int64_t N, int64_t S) {
   Q.next = ptr<int32_t>(c->p2next);
   Q.prev = ptr<int32_t>(c->p2prev);
   Q.final_of = ptr<int32_t>(c->p2final_of);
+  Q.seg_fpos = ptr<int32_t>(c->p2seg_fpos);
   Q.final_start = ptr<int32_t>(c->p2final_start);
   Q.final_nhits = ptr<int32_t>(c->p2final_nhits);
   Q.final_hbeg = ptr<int64_t>(c->p2final_hbeg);
@@ -1724,7 +1727,7 @@ int tpcca_get_compressed(tpcca_ctx_t *c, int32_t slot, int32_t sector, int32_t *
     RCCHK(copy_sync(c, rec, ptr<int32_t>(c->p2rec) + 6 * (int64_t)sb[0], sizeof(int32_t) * 6 * (size_t)*n_seg,
                     hipMemcpyDeviceToHost));
   if (res && r.n_track_hits)
-    RCCHK(copy_sync(c, res, ptr<int32_t>(c->p2res) + 3 * r.hit_begin, sizeof(int32_t) * 3 * (size_t)r.n_track_hits,
+    RCCHK(copy_sync(c, res, ptr<int32_t>(c->p2res) + 4 * r.hit_begin, sizeof(int32_t) * 4 * (size_t)r.n_track_hits,
                     hipMemcpyDeviceToHost));
   return TPCCA_OK;
 }
@@ -1753,6 +1756,7 @@ int tpcca_decompress(tpcca_ctx_t *c, int32_t n_seg, const int32_t *n_hits, const
                      const int32_t *rec, const int32_t *res, int32_t *yq, int32_t *zq, uint8_t *rows) {
   if (!c || n_seg < 0) return TPCCA_EINVAL;
   if (n_seg > 0 && (!n_hits || !hit_begin || !rec || !res || !yq || !zq || !rows)) return TPCCA_EINVAL;
+  if (reinterpret_cast<uintptr_t>(res) & 15) return TPCCA_EINVAL;  // read as 16-B records
   hipSetDevice(c->device);
   const P2Params q = p2_dev(c->p2params);
   hipError_t e = p2_launch_decompress(p2_prop_params(c), q, ptr<float>(c->row_x_d), n_seg, n_hits, hit_begin, rec,

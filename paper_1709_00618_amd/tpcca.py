@@ -477,10 +477,10 @@ class Context:
         if st not in (OK, ECAPACITY):
             _check(st, "tpcca_get_compressed", self.h)
         rec = np.zeros((max(1, ns.value), 6), np.int32)
-        res = np.zeros((max(1, nh.value), 3), np.int32)
+        res = np.zeros((max(1, nh.value), 4), np.int32)  # row step, y, z, 0
         _check(lib().tpcca_get_compressed(self.h, slot, sector, _p(rec), rec.shape[0], _p(res), res.shape[0],
                                           ctypes.byref(ns), ctypes.byref(nh)), "tpcca_get_compressed", self.h)
-        return rec[:ns.value], res[:nh.value]
+        return rec[:ns.value], np.ascontiguousarray(res[:nh.value, :3])
 
     def phase2_view(self) -> Phase2View:
         v = Phase2View()
