@@ -444,8 +444,8 @@ __device__ __forceinline__ int row_of(const RowTab *t, int R, int g) {
 // L2.
 // Staging capacities come in variants (tuning knob link_stage): larger ones
 // fall back to global memory less often, smaller ones let more blocks share
-// a CU's LDS.  Variant 0 takes 19.5 KB of LDS and 70 VGPRs: 7 blocks of 256
-// threads per CU (the registers set the limit).
+// a CU's LDS.  Variant 0 takes 19.5 KB of LDS; the kernel is held to 72
+// VGPRs (seven waves per SIMD), so 7 blocks of 256 threads share a CU.
 template <int kV> struct LinkCaps;
 template <> struct LinkCaps<0> { static constexpr int nbr = 1024, bins = 768; };
 template <> struct LinkCaps<1> { static constexpr int nbr = 1536, bins = 1024; };
@@ -462,15 +462,20 @@ struct LinkBest {
   int u, d;
 };
 
-// One (u, d) pair against the best so far: smaller chi2, ties by cluster IDs.
-// The deviation is formed from coordinate differences, (h - d) - w (u - d),
-// rounded once: differences of nearby hits are exact, so it keeps its
-// precision at the large z' of a time frame.
-__device__ __forceinline__ void link_pair(const Bufs &B, float2 h, float w, float2 cu, float2 cd, int u, int d,
-                                          LinkBest &b) {
+// The straight-line deviation of a (u, d) pair: the deviation is formed
+// from coordinate differences, (h - d) - w (u - d), rounded once:
+// differences of nearby hits are exact, so it keeps its precision at the
+// large z' of a time frame.
+__device__ __forceinline__ float link_c2(float2 h, float w, float2 cu, float2 cd) {
   const float ey = __builtin_fmaf(-(cu.x - cd.x), w, h.x - cd.x);
   const float ez = __builtin_fmaf(-(cu.y - cd.y), w, h.y - cd.y);
-  const float c2 = __builtin_fmaf(ey, ey, ez * ez);
+  return __builtin_fmaf(ey, ey, ez * ez);
+}
+
+// One (u, d) pair against the best so far: smaller chi2, ties by cluster IDs.
+__device__ __forceinline__ void link_pair(const Bufs &B, float2 h, float w, float2 cu, float2 cd, int u, int d,
+                                          LinkBest &b) {
+  const float c2 = link_c2(h, w, cu, cd);
   bool take = c2 < b.c2;
   if (!take && c2 == b.c2 && b.u >= 0) {
     const int iu = B.sid[u], id = B.sid[d], ibu = B.sid[b.u], ibd = B.sid[b.d];
@@ -505,63 +510,80 @@ __device__ __noinline__ LinkBest link_all_pairs(const Bufs &B, float2 h, float l
 }
 
 // Marks the staged hits in [b, e) (at most kMaxScan of them) that lie inside
-// the window around h: bit j of m[p] stands for hit b + 2j + p.  The loop
-// has no branches: lanes of a wave scan in step, two candidates per step
-// (one paired LDS read), and the bit of each step is the same for every
-// lane.  The second read of the last step may touch the entry after the
-// range (the staging arrays hold one spare entry); bits past the range are
-// cleared after the loop.
-struct WinMask {
-  unsigned int m[2];
-};
-
-__device__ __forceinline__ unsigned int low_bits(int n) { return n >= 32 ? ~0u : (1u << n) - 1u; }
-
-__device__ __forceinline__ WinMask window_mask(const float2 *src, int off, int b, int e, float2 h, float ly,
-                                               float lz) {
-  WinMask r{{0u, 0u}};
-  for (int k = 0; b + k < e; k += 2) {
-    const float2 c0 = src[b + k - off], c1 = src[b + k + 1 - off];
-    // bitwise &: both tests are evaluated (no short-circuit branches)
-    const bool w0 = (fabsf(c0.x - h.x) <= ly) & (fabsf(c0.y - h.y) <= lz);
-    const bool w1 = (fabsf(c1.x - h.x) <= ly) & (fabsf(c1.y - h.y) <= lz);
-    const unsigned int bit = 1u << (k >> 1);
-    r.m[0] |= w0 ? bit : 0u;
-    r.m[1] |= w1 ? bit : 0u;
-  }
-  const int n = e - b;  // candidates b + 2j + p exist for j < (n + 1 - p) / 2
-  r.m[0] &= low_bits((n + 1) >> 1);
-  r.m[1] &= low_bits(n >> 1);
-  return r;
+// the window around h: bit k stands for hit b + k.  The loop has no
+// branches: lanes of a wave scan in step, two candidates per step (one
+// paired LDS read), and the bit positions of each step are the same for
+// every lane (the step count is uniform; candidates 32.. go to the high
+// word in a second loop, so no 64-bit shift is needed).  The second read of
+// the last step may touch the entry after the range (the staging arrays
+// hold one spare entry); bits past the range are cleared after the loops.
+__device__ __forceinline__ bool in_window(float2 c, float2 h, float ly, float lz) {
+  // bitwise &: both tests are evaluated (no short-circuit branches)
+  return (fabsf(c.x - h.x) <= ly) & (fabsf(c.y - h.y) <= lz);
 }
 
-// Candidate ranges up to this long take the mask path (two 32-bit masks).
+__device__ __forceinline__ unsigned long long window_mask(const float2 *src, int off, int b, int e, float2 h,
+                                                          float ly, float lz) {
+  unsigned int lo = 0u, hi = 0u;
+  for (int k = 0; k < 32 && b + k < e; k += 2) {
+    const float2 c0 = src[b + k - off], c1 = src[b + k + 1 - off];
+    lo |= (in_window(c0, h, ly, lz) ? 1u << k : 0u) | (in_window(c1, h, ly, lz) ? 2u << k : 0u);
+  }
+  for (int k = 32; b + k < e; k += 2) {
+    const float2 c0 = src[b + k - off], c1 = src[b + k + 1 - off];
+    hi |= (in_window(c0, h, ly, lz) ? 1u << (k - 32) : 0u) | (in_window(c1, h, ly, lz) ? 2u << (k - 32) : 0u);
+  }
+  const int n = e - b;
+  const unsigned long long m = ((unsigned long long)hi << 32) | lo;
+  return n >= 64 ? m : m & ((1ull << n) - 1ull);
+}
+
+// Candidate ranges up to this long take the mask path (one 64-bit mask).
 constexpr int kMaxScan = 64;
 
 // The common path, neighbours staged in LDS: the window hits of each side
 // are marked in a bit mask, then the marked hits are paired (the pair loop
 // runs over the few marked hits only, so lanes with different candidate
 // counts do not multiply their trip counts).  Longer ranges take the full
-// double loop.  Every pair is compared by (chi2, cluster IDs), so the order
-// in which pairs are visited does not change the result.
+// double loop.  The best pair is the smallest (chi2, up ID, down ID): the
+// pair loop compares chi2 alone and notes whether another pair equals the
+// best one's chi2; only then (rare: exact float ties) are the pairs visited
+// again with the cluster IDs read, so that the ID reads stay out of the
+// common loop.  The order of the visits does not change the result.
 __device__ __forceinline__ LinkBest link_hit_lds(const Bufs &B, float2 h, float luy, float luz, float ldy,
                                                  float ldz, float w, int ub, int ue, int db, int de,
                                                  const float2 *s_up, const float2 *s_dn, int u_off, int d_off) {
   if (ue - ub > kMaxScan || de - db > kMaxScan)
     return link_all_pairs<true>(B, h, luy, luz, ldy, ldz, w, ub, ue, db, de, s_up, s_dn, u_off, d_off);
   LinkBest b{__builtin_inff(), -1, -1};
-  const WinMask mu = window_mask(s_up, u_off, ub, ue, h, luy, luz);
-  if ((mu.m[0] | mu.m[1]) == 0u) return b;
-  const WinMask md = window_mask(s_dn, d_off, db, de, h, ldy, ldz);
-  for (int pu = 0; pu < 2; ++pu) {
-    for (unsigned int a = mu.m[pu]; a != 0u; a &= a - 1u) {
-      const int u = ub + 2 * __builtin_ctz(a) + pu;
+  const unsigned long long mu = window_mask(s_up, u_off, ub, ue, h, luy, luz);
+  if (mu == 0ull) return b;
+  const unsigned long long md = window_mask(s_dn, d_off, db, de, h, ldy, ldz);
+  if (md == 0ull) return b;
+  bool tie = false;
+  for (unsigned long long a = mu; a != 0ull; a &= a - 1ull) {
+    const int u = ub + __builtin_ctzll(a);
+    const float2 cu = s_up[u - u_off];
+    for (unsigned long long q = md; q != 0ull; q &= q - 1ull) {
+      const int d = db + __builtin_ctzll(q);
+      const float c2 = link_c2(h, w, cu, s_dn[d - d_off]);
+      const bool better = c2 < b.c2;
+      tie = !better && (tie || c2 == b.c2);
+      if (better) {
+        b.c2 = c2;
+        b.u = u;
+        b.d = d;
+      }
+    }
+  }
+  if (tie) {
+    b = LinkBest{__builtin_inff(), -1, -1};
+    for (unsigned long long a = mu; a != 0ull; a &= a - 1ull) {
+      const int u = ub + __builtin_ctzll(a);
       const float2 cu = s_up[u - u_off];
-      for (int pd = 0; pd < 2; ++pd) {
-        for (unsigned int q = md.m[pd]; q != 0u; q &= q - 1u) {
-          const int d = db + 2 * __builtin_ctz(q) + pd;
-          link_pair(B, h, w, cu, s_dn[d - d_off], u, d, b);
-        }
+      for (unsigned long long q = md; q != 0ull; q &= q - 1ull) {
+        const int d = db + __builtin_ctzll(q);
+        link_pair(B, h, w, cu, s_dn[d - d_off], u, d, b);
       }
     }
   }
@@ -569,7 +591,7 @@ __device__ __forceinline__ LinkBest link_hit_lds(const Bufs &B, float2 h, float 
 }
 
 template <int kV, int kT>
-__global__ __launch_bounds__(kT) void k_links(Bufs B, ParamsDev P, int run) {
+__global__ __launch_bounds__(kT, 7) void k_links(Bufs B, ParamsDev P, int run) {
   constexpr int kNbrCap = LinkCaps<kV>::nbr, kBinCap = LinkCaps<kV>::bins;
   static_assert(kNbrCap < 65536, "bin offsets are 16-bit");
   __shared__ float2 s_up[kNbrCap + 1], s_dn[kNbrCap + 1];  // + the spare entry of window_mask
