@@ -560,21 +560,34 @@ __device__ __forceinline__ LinkBest link_hit_lds(const Bufs &B, float2 h, float 
   if (mu == 0ull) return b;
   const unsigned long long md = window_mask(s_dn, d_off, db, de, h, ldy, ldz);
   if (md == 0ull) return b;
+  // the best pair is kept as bit positions in the two masks until the end
+  const float2 *const su = s_up + (ub - u_off), *const sd = s_dn + (db - d_off);
   bool tie = false;
-  for (unsigned long long a = mu; a != 0ull; a &= a - 1ull) {
-    const int u = ub + __builtin_ctzll(a);
-    const float2 cu = s_up[u - u_off];
-    for (unsigned long long q = md; q != 0ull; q &= q - 1ull) {
-      const int d = db + __builtin_ctzll(q);
-      const float c2 = link_c2(h, w, cu, s_dn[d - d_off]);
-      const bool better = c2 < b.c2;
-      tie = !better && (tie || c2 == b.c2);
-      if (better) {
-        b.c2 = c2;
-        b.u = u;
-        b.d = d;
-      }
+  auto visit = [&](int pu, float2 cu, int pd) {
+    const float c2 = link_c2(h, w, cu, sd[pd]);
+    const bool better = c2 < b.c2;
+    tie = !better && (tie || c2 == b.c2);
+    b.c2 = better ? c2 : b.c2;
+    b.u = better ? pu : b.u;
+    b.d = better ? pd : b.d;
+  };
+  if (__ballot(((mu | md) >> 32) != 0ull) == 0ull) {
+    // every lane's marks fit the low word (the common case): 32-bit loops
+    for (unsigned int a = (unsigned int)mu; a != 0u; a &= a - 1u) {
+      const int pu = __builtin_ctz(a);
+      const float2 cu = su[pu];
+      for (unsigned int q = (unsigned int)md; q != 0u; q &= q - 1u) visit(pu, cu, __builtin_ctz(q));
     }
+  } else {
+    for (unsigned long long a = mu; a != 0ull; a &= a - 1ull) {
+      const int pu = __builtin_ctzll(a);
+      const float2 cu = su[pu];
+      for (unsigned long long q = md; q != 0ull; q &= q - 1ull) visit(pu, cu, __builtin_ctzll(q));
+    }
+  }
+  if (b.u >= 0) {
+    b.u += ub;
+    b.d += db;
   }
   if (tie) {
     b = LinkBest{__builtin_inff(), -1, -1};
