@@ -10,6 +10,33 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Minimum and maximum over the 64 lanes of a wave (all lanes active),
+// returned to every lane, through data-parallel-primitive moves instead of
+// LDS permutes: shifts by 1, 2, 4 and 8 within each row of 16 lanes leave
+// the row's extreme in its lane 15, two row broadcasts carry it to lane 63.
+// A lane whose source lies outside its row, or a row the mask leaves out,
+// receives the identity.
+__device__ __forceinline__ int wave_min_dpp(int v) {
+  constexpr int id = 0x7FFFFFFF;
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ int wave_max_dpp(int v) {
+  constexpr int id = (int)0x80000000;
+  v = max(v, __builtin_amdgcn_update_dpp(id, v, 0x111, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(id, v, 0x112, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(id, v, 0x114, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(id, v, 0x118, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xa, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
 // Block-wide exclusive scan of one value per thread (blockDim.x <= 1024,
 // multiple of 64).  Returns the exclusive prefix; *total gets the sum.
 template <typename T>

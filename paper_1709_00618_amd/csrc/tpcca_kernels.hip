@@ -615,6 +615,14 @@ __global__ __launch_bounds__(kT, 7) void k_links(Bufs B, ParamsDev P, int run) {
   // orders this before any read
   for (int q = threadIdx.x; q <= kNbrCap; q += blockDim.x) s_up[q] = s_dn[q] = make_float2(0.0f, 0.0f);
   const int R = P.n_rows;
+  // the interpolation weight of each inner row, w = dx_down / (dx_down +
+  // dx_up), computed once per block (the same operations as per tile)
+  __shared__ float s_w[kMaxRows + 1];
+  for (int q = 1 + threadIdx.x; q < R - 1; q += blockDim.x) {
+    const float xr = B.row_x[q];
+    const float dxu = B.row_x[q + 1] - xr, dxd = xr - B.row_x[q - 1];
+    s_w[q] = dxd / (dxd + dxu);
+  }
   const RunDev &rd = B.runs[run];
   const int ntile = rd.tile1 - rd.tile0;
   // XCD-aware walk: blocks b with b % 8 == x take the x-th eighth of tiles
@@ -641,7 +649,6 @@ __global__ __launch_bounds__(kT, 7) void k_links(Bufs B, ParamsDev P, int run) {
     const float xr = B.row_x[r];
     const float dxu = B.row_x[r + 1] - xr;
     const float dxd = xr - B.row_x[r - 1];
-    const float w = dxd / (dxd + dxu);
     const float luy = P.wy * dxu, luz = P.wz * dxu, ldy = P.wy * dxd, ldz = P.wz * dxd;
     float2 h = make_float2(0.0f, 0.0f);
     int zmin = 0x7FFFFFFF, zmax = (int)0x80000000;
@@ -649,15 +656,14 @@ __global__ __launch_bounds__(kT, 7) void k_links(Bufs B, ParamsDev P, int run) {
       h = B.yz[g];
       zmin = zmax = ordered_int(h.y);
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      zmin = min(zmin, __shfl_xor(zmin, o, 64));
-      zmax = max(zmax, __shfl_xor(zmax, o, 64));
-    }
+    zmin = wave_min_dpp(zmin);
+    zmax = wave_max_dpp(zmax);
     if ((i & 63) == 0) {
       s_red[i >> 6] = zmin;
       s_red[(kT / 64) + (i >> 6)] = zmax;
     }
-    __syncthreads();
+    __syncthreads();  // also orders the row weights before their first read
+    const float w = s_w[r];
     float zlo = from_ordered(s_red[0]), zhi = from_ordered(s_red[kT / 64]);
     for (int q = 1; q < kT / 64; ++q) {
       zlo = fminf(zlo, from_ordered(s_red[q]));
