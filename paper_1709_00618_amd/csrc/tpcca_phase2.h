@@ -86,6 +86,8 @@ struct P2Bufs {
   uint8_t *flags;                // per global cluster index
   int32_t *rec;                  // 6 per segment
   int32_t *res;                  // 4 per hit (global hit index of hits_out), 16-B aligned
+  int32_t *order;                // processing order of the per-lane kernels (longest first)
+  int32_t *len_hist, *len_cursor; // length-class counts and cursors of that order
   int64_t *scan_tmp;
   P2Counts *cnt;
 };

@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void k_p2_seg_prep(Bufs B, P2Bufs Q, ParamsDev
         const int take = min(__popcll(idle), pend - pnext);
         const int rank = __popcll(idle & below);
         if (g < 0 && rank < take) {
-          g = pnext + rank;
+          g = Q.order[pnext + rank];
           u = p2_unit_of(Q, g);
           const tpcca_track_t &t = p2_track(B, Q, g, u);
           h0 = p2_hit0(B, t, u);
@@ -841,7 +841,7 @@ __global__ __launch_bounds__(256) void k_p2_refit(Bufs B, P2Bufs Q, ParamsDev P,
         const int take = min(__popcll(idle), pend - pnext);
         const int rank = __popcll(idle & below);
         if (phase == kFree && rank < take) {
-          f = pnext + rank;
+          f = Q.order[pnext + rank];
           const int g0 = Q.final_start[f];
           // rows grow along a chain and each link crosses a sector boundary
           // of one side: at most 18 segments
@@ -1120,6 +1120,80 @@ __global__ void k_p2_fill_u8(uint8_t *p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0;
 }
+// ---------------------------------------------------------------- order ---
+// Processing order of the persistent per-lane kernels (segment preparation
+// with compression, final refit): items by descending length, a counting
+// sort over kLenBins length classes.  A wave claims 64 consecutive items of
+// the order, so its lanes get about equally long work and finish together
+// instead of each wave waiting for the longest of 64 items in input order.
+// The order changes no result: each item's outputs depend on that item
+// alone.  Items of one length keep no particular order among themselves
+// (ranks inside a block from LDS atomics, block bases from global ones).
+constexpr int kLenBins = 512;
+constexpr int kLenPer = 4;  // items per thread and pass of the scatter
+
+struct SegLen {  // a segment: its won hits
+  __device__ int count(const P2Bufs &Q) const { return Q.cnt->n_seg; }
+  __device__ int len(const Bufs &B, const P2Bufs &Q, int g) const {
+    return p2_track(B, Q, g, p2_unit_of(Q, g)).n_hits;
+  }
+};
+struct FinLen {  // a final track: its hits
+  __device__ int count(const P2Bufs &Q) const { return Q.cnt->n_final; }
+  __device__ int len(const Bufs &, const P2Bufs &Q, int f) const { return Q.final_nhits[f]; }
+};
+__device__ __forceinline__ int len_bin(int len) { return kLenBins - 1 - min(max(len, 0), kLenBins - 1); }
+
+template <class L>
+__global__ __launch_bounds__(256) void k_p2_len_hist(Bufs B, P2Bufs Q, L l) {
+  __shared__ int32_t h[kLenBins];
+  for (int i = threadIdx.x; i < kLenBins; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const int n = l.count(Q);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    atomicAdd(&h[len_bin(l.len(B, Q, i))], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kLenBins; i += blockDim.x)
+    if (h[i]) atomicAdd(&Q.len_hist[i], h[i]);
+}
+
+// the classes' first positions (exclusive scan of their counts)
+__global__ __launch_bounds__(kLenBins) void k_p2_len_scan(P2Bufs Q) {
+  __shared__ int32_t lds[kLenBins / 64 + 1];
+  int32_t tot;
+  Q.len_cursor[threadIdx.x] = block_exclusive_scan<int32_t>(Q.len_hist[threadIdx.x], lds, &tot);
+}
+
+template <class L>
+__global__ __launch_bounds__(256) void k_p2_len_scatter(Bufs B, P2Bufs Q, L l) {
+  __shared__ int32_t h[kLenBins], base[kLenBins];
+  const int n = l.count(Q);
+  constexpr int span = 256 * kLenPer;
+  for (int c0 = blockIdx.x * span; c0 < n; c0 += gridDim.x * span) {  // uniform per block
+    for (int i = threadIdx.x; i < kLenBins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    int bin[kLenPer], rank[kLenPer];
+#pragma unroll
+    for (int k = 0; k < kLenPer; ++k) {
+      const int i = c0 + k * 256 + (int)threadIdx.x;
+      bin[k] = -1;
+      rank[k] = 0;
+      if (i < n) {
+        bin[k] = len_bin(l.len(B, Q, i));
+        rank[k] = atomicAdd(&h[bin[k]], 1);
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kLenBins; i += blockDim.x)
+      if (h[i]) base[i] = atomicAdd(&Q.len_cursor[i], h[i]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kLenPer; ++k)
+      if (bin[k] >= 0) Q.order[base[bin[k]] + rank[k]] = c0 + k * 256 + (int)threadIdx.x;
+    __syncthreads();  // h and base are refilled by the next pass
+  }
+}
+
 __global__ void k_p2_fill_i32(int32_t *p, int64_t n, int32_t v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -1127,6 +1201,16 @@ __global__ void k_p2_fill_i32(int32_t *p, int64_t n, int32_t v) {
 
 inline int p2_grid(int64_t n, int block, int cap) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((n + block - 1) / block, cap));
+}
+
+// Q.order = items 0..count-1 by descending length (count read on the device;
+// cap bounds it)
+template <class L>
+void p2_len_order(const Bufs &B, const P2Bufs &Q, L l, int64_t cap, hipStream_t s) {
+  k_p2_fill_i32<<<1, kLenBins, 0, s>>>(Q.len_hist, kLenBins, 0);
+  k_p2_len_hist<L><<<p2_grid(cap, 256, 256), 256, 0, s>>>(B, Q, l);
+  k_p2_len_scan<<<1, kLenBins, 0, s>>>(Q);
+  k_p2_len_scatter<L><<<p2_grid(cap, 256 * kLenPer, 2048), 256, 0, s>>>(B, Q, l);
 }
 
 }  // namespace
@@ -1143,6 +1227,7 @@ hipError_t p2_launch_merge(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, c
   k_p2_fill_i32<<<p2_grid(cells, 256, 8192), 256, 0, s>>>(Q.bin_cnt, cells, 0);
   k_p2_seg_index<<<1, 1024, 0, s>>>(B, Q, R);
   k_p2_hits<<<p2_grid(hit_span, 256, 16384), 256, 0, s>>>(B, Q, R);
+  p2_len_order(B, Q, SegLen{}, seg_cap, s);
   k_p2_seg_prep<<<p2_grid(seg_cap, 256, 2048), 256, 0, s>>>(B, Q, P, q);  // persistent
   k_p2_zrange<<<std::min(n_units, 4096), 256, 0, s>>>(Q);
   k_p2_bin_count<<<gs, 256, 0, s>>>(Q);
@@ -1173,6 +1258,7 @@ hipError_t p2_launch_pairs(const Bufs &B, const P2Bufs &Q, const ParamsDev &P, c
               nullptr, &Q.cnt->n_final_hits, s);
   if (e != hipSuccess) return e;
   k_p2_final_hits<<<p2_grid((int64_t)seg_cap * 16, 256, 16384), 256, 0, s>>>(B, Q);
+  p2_len_order(B, Q, FinLen{}, seg_cap, s);
   k_p2_refit<<<p2_grid(seg_cap, 256, 2048), 256, 0, s>>>(B, Q, P, q);  // persistent
   // vertex candidates, compacted with their sort keys
   e = p2_scan(GetCand{Q.finals, q}, PutCand{Q.finals, Q.vkey[0], Q.vval[0]}, &Q.cnt->n_final, seg_cap,

@@ -91,7 +91,7 @@ struct tpcca_ctx {
       p2zmm, p2unit_nz, p2unit_bbase, p2bin_cnt, p2bin_beg, p2bin_seg, p2bin_rz, p2hrec, p2seg_flag, p2pairs, p2best_b, p2best_a, p2next, p2prev, p2final_of, p2final_start,
       p2final_nhits, p2final_hbeg, p2finals, p2final_hits, p2vkey0, p2vkey1, p2vval0, p2vval1, p2gstart,
       p2group_pos, p2vertices, p2slot_first, p2slot_vbeg, p2slot_vend, p2flags, p2rec, p2res, p2scan, p2cnt,
-      p2sort_tmp;
+      p2sort_tmp, p2order, p2lenh;
   P2Bufs P2{};
   bool p2_done = false;
   P2Counts p2c{};
@@ -657,7 +657,7 @@ int tpcca_destroy(tpcca_ctx_t *c) {
                    &c->p2final_start, &c->p2final_nhits, &c->p2final_hbeg, &c->p2finals, &c->p2final_hits,
                    &c->p2vkey0, &c->p2vkey1, &c->p2vval0, &c->p2vval1, &c->p2gstart, &c->p2group_pos,
                    &c->p2vertices, &c->p2slot_first, &c->p2slot_vbeg, &c->p2slot_vend, &c->p2flags, &c->p2rec,
-                   &c->p2res, &c->p2scan, &c->p2cnt, &c->p2sort_tmp};
+                   &c->p2res, &c->p2scan, &c->p2cnt, &c->p2sort_tmp, &c->p2order, &c->p2lenh};
   for (DevBuf *b : all)
     if (b->p) hipFree(b->p);
   for (int k = 0; k < 7; ++k)
@@ -1465,6 +1465,7 @@ int p2_ensure(tpcca_ctx *c, int64_t U, int64_t T, int64_t N, int64_t S) {
       {&c->p2slot_vend, sizeof(int32_t) * S}, {&c->p2flags, (size_t)N},
       {&c->p2rec, sizeof(int32_t) * 6 * T}, {&c->p2res, sizeof(int32_t) * 4 * N},
       {&c->p2scan, sizeof(int64_t) * (tiles + 2)}, {&c->p2cnt, sizeof(P2Counts)},
+      {&c->p2order, sizeof(int32_t) * T}, {&c->p2lenh, sizeof(int32_t) * 2 * 512},
   };
   for (auto &e : list) RCCHK(ensure(c, *e.b, e.bytes, 0));
   P2Bufs &Q = c->P2;
@@ -1513,6 +1514,9 @@ int p2_ensure(tpcca_ctx *c, int64_t U, int64_t T, int64_t N, int64_t S) {
   Q.res = ptr<int32_t>(c->p2res);
   Q.scan_tmp = ptr<int64_t>(c->p2scan);
   Q.cnt = ptr<P2Counts>(c->p2cnt);
+  Q.order = ptr<int32_t>(c->p2order);
+  Q.len_hist = ptr<int32_t>(c->p2lenh);
+  Q.len_cursor = Q.len_hist + 512;
   return TPCCA_OK;
 }
 
