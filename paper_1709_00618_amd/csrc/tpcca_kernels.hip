@@ -664,15 +664,22 @@ __global__ __launch_bounds__(kT, 7) void k_links(Bufs B, ParamsDev P, int run) {
     }
     __syncthreads();  // also orders the row weights before their first read
     const float w = s_w[r];
-    float zlo = from_ordered(s_red[0]), zhi = from_ordered(s_red[kT / 64]);
+    // the tile's z range: the waves' ordered-int extremes combined as
+    // integers, converted once (tile-wide values are kept in scalar
+    // registers, so the bin-table addressing below is scalar)
+    int zlo_o = s_red[0], zhi_o = s_red[kT / 64];
     for (int q = 1; q < kT / 64; ++q) {
-      zlo = fminf(zlo, from_ordered(s_red[q]));
-      zhi = fmaxf(zhi, from_ordered(s_red[(kT / 64) + q]));
+      zlo_o = min(zlo_o, s_red[q]);
+      zhi_o = max(zhi_o, s_red[(kT / 64) + q]);
     }
+    const float zlo = from_ordered(__builtin_amdgcn_readfirstlane(zlo_o));
+    const float zhi = from_ordered(__builtin_amdgcn_readfirstlane(zhi_o));
     // tile-wide bin ranges of the neighbour rows (a superset of every hit's)
     const float tpad = 1e-3f + 1e-6f * fmaxf(fabsf(zlo), fabsf(zhi));
-    const int ublo = zbin(tu, zlo - luz - tpad), ubhi = zbin(tu, zhi + luz + tpad);
-    const int dblo = zbin(td, zlo - ldz - tpad), dbhi = zbin(td, zhi + ldz + tpad);
+    const int ublo = __builtin_amdgcn_readfirstlane(zbin(tu, zlo - luz - tpad));
+    const int ubhi = __builtin_amdgcn_readfirstlane(zbin(tu, zhi + luz + tpad));
+    const int dblo = __builtin_amdgcn_readfirstlane(zbin(td, zlo - ldz - tpad));
+    const int dbhi = __builtin_amdgcn_readfirstlane(zbin(td, zhi + ldz + tpad));
     const int ua = B.binbeg[tu.bin0 + ublo], ue_ = B.binbeg[tu.bin0 + ubhi + 1];
     const int da = B.binbeg[td.bin0 + dblo], de_ = B.binbeg[td.bin0 + dbhi + 1];
     const bool lds = (ue_ - ua) <= kNbrCap && (de_ - da) <= kNbrCap && (ubhi - ublo + 2) <= kBinCap &&
