@@ -207,3 +207,35 @@ def test_phase2_stage_errors(tpcca, row_x):
         assert f.shape[0] == tr.shape[0] and np.all(f["n_seg"] == 1)  # one sector: nothing to merge
     with pytest.raises(tpcca.TpccaError):
         tpcca.Context(row_x).set_phase2_params(max_sinphi=1.5)
+
+
+def test_phase2_without_tracks_and_with_a_tiny_event(tpcca, torch_cuda, row_x):
+    """Degenerate inputs of the second phase: units that yield no track at
+    all (the per-lane loops and their longest-first orders get no items),
+    then a single minimum-bias event of 68 tracks against the oracle."""
+    rng = np.random.default_rng(5)
+    k = 2000
+    cl = np.stack([np.full(k, row_x[40]), rng.uniform(-20, 20, k), rng.uniform(0, 250, k), np.ones(k)],
+                  1).astype(np.float32)
+    row = np.full(k, 40, np.uint8)
+    with tpcca.Context(row_x) as ctx:
+        ctx.load_sector(0, 0, cl, row)
+        ctx.load_sector(0, 1, cl, row)
+        ctx.run_all(0, -1)
+        ctx.phase2()
+        ctx.sync()
+        finals, hits = ctx.get_finals(0)
+        assert finals.shape[0] == 0 and hits.shape[0] == 0
+        assert ctx.get_vertices(0).shape[0] == 0
+    torch = torch_cuda
+    b = tpcgen.minbias_batch(seed=8, n_events=1)
+    print(f"tiny event: {int(b.meta['multiplicity'][0])} tracks, {b.n_clusters} clusters", flush=True)
+    dcl, drow = _dev(torch, b.cl), _dev(torch, b.row)
+    torch.cuda.synchronize()
+    with tpcca.Context(row_x) as ctx:
+        ctx.run_batch(dcl, drow, b.units, device=True, graph=False)
+        ctx.phase2()
+        ctx.sync()
+        s = p2p.compare_slot(ctx, b, row_x, 0)
+    print(f"second phase, tiny event: {s}", flush=True)
+    assert s["finals"] > 0
