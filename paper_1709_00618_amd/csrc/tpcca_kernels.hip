@@ -665,8 +665,8 @@ __global__ __launch_bounds__(kT, 7) void k_links(Bufs B, ParamsDev P, int run) {
     __syncthreads();  // also orders the row weights before their first read
     const float w = s_w[r];
     // the tile's z range: the waves' ordered-int extremes combined as
-    // integers, converted once (tile-wide values are kept in scalar
-    // registers, so the bin-table addressing below is scalar)
+    // integers and converted once, in scalar registers (the tile-wide bin
+    // indices below are made wave-uniform the same way)
     int zlo_o = s_red[0], zhi_o = s_red[kT / 64];
     for (int q = 1; q < kT / 64; ++q) {
       zlo_o = min(zlo_o, s_red[q]);
