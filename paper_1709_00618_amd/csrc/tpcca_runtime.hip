@@ -68,11 +68,20 @@ struct tpcca_ctx {
       tracks, hits_out, assign, unit_res, scan_tmp, zo_tmp, zo_cnt, kf_chunks, in_cl, in_row;
   Bufs B{};
 
-  // graph replay of the batch path
-  hipGraphExec_t gexec[6] = {};  // whole sequence, or the six timed segments
-  RunHost gcap{};
-  int generation = 0;
-  int gen_captured = -1;
+  // graph replay of the batch path: the graphs captured for the last few
+  // launch-capacity buckets, so that batches of recurring sizes (a server
+  // lane's mix of frames) replay without a new capture
+  struct GraphEntry {
+    hipGraphExec_t exec[6] = {};  // whole sequence, or the six timed segments
+    RunHost cap{};                // the capacities the graph was captured for
+    int gen = -1;                 // buffer generation its kernel arguments belong to
+    bool timing = false;          // holds the stage events
+    uint64_t used = 0;            // last replay (least recently used is replaced)
+  };
+  static constexpr int kGraphCache = 8;
+  GraphEntry graphs[kGraphCache];
+  uint64_t graph_clock = 0;
+  int generation = 0;  // bumped when buffers move or launch shapes change
 
   bool timing = false;
   hipEvent_t ev[7] = {};
@@ -80,7 +89,6 @@ struct tpcca_ctx {
   bool have_times = false;
   bool capturing = false;       // a graph capture is in progress
   int64_t graph_fallbacks = 0;  // batches run without a graph after a failed capture
-  bool gtiming = false;         // the captured graph holds stage events
 
   std::string last_error;
 
@@ -99,13 +107,23 @@ struct tpcca_ctx {
 };
 
 // --------------------------------------------------------------- errors ---
-// Destroys the captured batch graphs; the next graph run captures again.
-static void drop_graphs(tpcca_ctx *c) {
-  for (auto &g : c->gexec) {
+// Destroys one cached batch graph.
+static void drop_graph(tpcca_ctx::GraphEntry &e) {
+  for (auto &g : e.exec) {
     if (g) hipGraphExecDestroy(g);
     g = nullptr;
   }
-  c->gen_captured = -1;
+  e.gen = -1;
+}
+
+// Destroys the captured batch graphs; the next graph run captures again.
+static void drop_graphs(tpcca_ctx *c) {
+  for (auto &e : c->graphs) drop_graph(e);
+}
+
+static bool same_capacities(const RunHost &a, const RunHost &b) {
+  return a.u1 == b.u1 && a.c1 == b.c1 && a.cl1 == b.cl1 && a.bin1 == b.bin1 && a.trk_cap == b.trk_cap &&
+         a.tile1 == b.tile1 && a.dense == b.dense;
 }
 
 static int dev_err(tpcca_ctx *c, hipError_t e, const char *what) {
@@ -942,14 +960,24 @@ int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
   capr.bin1 = capB;
   capr.trk_cap = (int32_t)capT;
   capr.tile1 = (int32_t)(capN / link_tile_of(c->P) + capU * (c->R + 2) + 1);
-  const bool reuse = c->gexec[0] && c->gen_captured == c->generation && c->gcap.u1 == capr.u1 &&
-                     c->gcap.c1 == capr.c1 && c->gcap.cl1 == capr.cl1 && c->gcap.bin1 == capr.bin1 &&
-                     c->gcap.trk_cap == capr.trk_cap && c->gcap.tile1 == capr.tile1 &&
-                     c->gcap.dense == capr.dense &&
-                     c->gtiming == c->timing;
-  if (!reuse) {
+  tpcca_ctx::GraphEntry *ge = nullptr;
+  for (auto &e : c->graphs)
+    if (e.exec[0] && e.gen == c->generation && e.timing == c->timing && same_capacities(e.cap, capr)) ge = &e;
+  if (!ge) {
     std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
-    drop_graphs(c);
+    // a free or outdated entry, else the least recently replayed one
+    ge = &c->graphs[0];
+    for (auto &e : c->graphs) {
+      if (!e.exec[0] || e.gen != c->generation) {
+        ge = &e;
+        break;
+      }
+      if (e.used < ge->used) ge = &e;
+    }
+    if (ge->exec[0]) {
+      HIPCHK(c, hipStreamSynchronize(c->stream));  // its last replay has finished
+      drop_graph(*ge);
+    }
     // one graph of the whole sequence, or with timing on one graph per timed
     // segment (HIP events between the replays of the segments)
     const int nseg = c->timing ? 6 : 1;
@@ -976,28 +1004,29 @@ int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
         ++c->graph_fallbacks;
         return launch_stages(c, 0, c->runs[0], 1, 4);
       }
-      e = hipGraphInstantiate(&c->gexec[k], g, nullptr, nullptr, 0);
+      e = hipGraphInstantiate(&ge->exec[k], g, nullptr, nullptr, 0);
       hipGraphDestroy(g);
       if (e != hipSuccess) {
-        c->gexec[k] = nullptr;
+        ge->exec[k] = nullptr;
         drop_graphs(c);  // also the segments captured before
         return dev_err(c, e, "hipGraphInstantiate");
       }
     }
-    c->gcap = capr;
-    c->gtiming = c->timing;
-    c->gen_captured = c->generation;
+    ge->cap = capr;
+    ge->timing = c->timing;
+    ge->gen = c->generation;
   }
-  if (!c->gtiming) {
-    HIPCHK(c, hipGraphLaunch(c->gexec[0], c->stream));
+  ge->used = ++c->graph_clock;
+  if (!ge->timing) {
+    HIPCHK(c, hipGraphLaunch(ge->exec[0], c->stream));
   } else {
     HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
     for (int k = 0; k < 6; ++k) {
-      HIPCHK(c, hipGraphLaunch(c->gexec[k], c->stream));
+      HIPCHK(c, hipGraphLaunch(ge->exec[k], c->stream));
       HIPCHK(c, hipEventRecord(c->ev[k + 1], c->stream));
     }
   }
-  c->have_times = c->gtiming;
+  c->have_times = ge->timing;
   return TPCCA_OK;
 }
 
@@ -1146,7 +1175,7 @@ int tpcca_set_tuning(tpcca_ctx_t *c, const tpcca_tuning_t *t) {
     c->P.hits_per_bin = t->grid_hits_per_bin;
     c->params.grid_hits_per_bin = t->grid_hits_per_bin;
   }
-  c->gen_captured = -1;  // launch shapes changed: capture the graph again
+  c->generation++;  // launch shapes changed: the cached graphs are captured again
   return TPCCA_OK;
 }
 

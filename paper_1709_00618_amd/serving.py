@@ -189,7 +189,7 @@ def _finish(srv, rid):
         raise tpcca.TpccaError(r.status, f"served request {rid}", srv.last_error())
 
 
-def bench_served(row_x, n_tf=48, ring=8, n_streams=2, seed=0, log=print):
+def bench_served(row_x, n_tf=48, ring=8, n_streams=3, seed=0, log=print):
     """Served time frames: sizes log-uniform in [8, 256] events, Poisson
     arrivals equivalent to 50 kHz.  A ring of `ring` distinct frames (built
     from a pool of minimum-bias events shifted to Poisson arrival times) is

@@ -197,16 +197,19 @@ def test_dense_unit_with_an_overfull_row(tpcca, torch_cuda, row_x):
 
 
 def test_graph_replays_track_changing_batches(tpcca, torch_cuda, row_x):
-    """One context, graph replays of different batches, host work between."""
+    """One context, graph replays of different batches, host work between;
+    batches of earlier sizes come back (their graphs are replayed from the
+    context's cache of captured graphs)."""
     torch = torch_cuda
     batches = [tpcgen.minbias_batch(seed=s, n_events=k) for s, k in ((2, 5), (3, 3), (4, 5))]
+    refs = [_parity.oracle_units(b, row_x) for b in batches]
     with tpcca.Context(row_x) as ctx:
-        for b in batches:
-            print(f"replay batch {b.n_clusters} clusters", flush=True)
-            refs = _parity.oracle_units(b, row_x)
+        for i in (0, 1, 2, 0, 1, 1, 2):
+            b = batches[i]
+            print(f"replay batch {i}: {b.n_clusters} clusters", flush=True)
             ctx.run_batch(b.cl, b.row, b.units, device=False, graph=True)
             units, tracks, hits, asg = ctx.get_batch_results()
-            _parity.compare_batch(units, tracks, hits, asg, b, refs)
+            _parity.compare_batch(units, tracks, hits, asg, b, refs[i])
         # every batch ran as its graph, none fell back to plain launches
         assert ctx.work_stats()["graph_fallbacks"] == 0
 
