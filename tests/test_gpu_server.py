@@ -184,3 +184,53 @@ def test_full_queue_returns_ebusy(mods, frames, row_x):
             assert got[u][0].tobytes() == tracks[t0:t0 + nt].tobytes()
             assert np.array_equal(got[u][1], hits[h0:h0 + nh])
             assert np.array_equal(got[u][2], asg[c0:c0 + n])
+
+
+def test_three_lanes_eight_outstanding_equal_the_batch_path(mods, frames, row_x):
+    """The served configuration of the benchmark (three lanes, up to eight
+    frames outstanding, frames of different sizes batched together and
+    graphs replayed from the lanes' caches): every served frame equals the
+    batch path's results for it."""
+    tpcca, serving = mods
+    want = []
+    with tpcca.Context(row_x) as ctx:
+        for t in frames:
+            ctx.run_batch(t.cl, t.row, t.units, graph=True)
+            units, tracks, hits, asg = ctx.get_batch_results()
+            per = []
+            for u in range(t.units.shape[0]):
+                ur = units[u]
+                t0, nt = int(ur["track_begin"]), int(ur["n_tracks"])
+                h0, nh = int(ur["hit_begin"]), int(ur["n_track_hits"])
+                c0, n = int(ur["cluster_begin"]), int(t.units[u, 1])
+                per.append((tracks[t0:t0 + nt].tobytes(), hits[h0:h0 + nh].copy(), asg[c0:c0 + n].copy()))
+            want.append(per)
+    fr = [serving.Frame(t.cl, t.row, t.units, pinned=True) for t in frames]
+    maxc = max(f.n_clusters for f in fr)
+    outs = [serving.Outputs(maxc, 36, pinned=True) for _ in range(8)]
+    order = [0, 1, 2, 2, 0, 1, 1, 0, 2, 0, 0, 2, 1, 2, 0, 1]
+    checked = 0
+    with serving.Server(row_x, n_streams=3, budget_bytes=16 << 30) as srv:
+        free, inflight = list(range(8)), []
+
+        def finish():
+            nonlocal checked
+            rid, oi, k = inflight.pop(0)
+            r = srv.wait(rid, 300)
+            assert r.status == 0 and r.done == 1
+            for (tb, hb, ab), (tg, hg, ag) in zip(want[k], serving.unit_results(fr[k], outs[oi])):
+                assert tg.tobytes() == tb and np.array_equal(hg, hb) and np.array_equal(ag, ab)
+            srv.release(rid)
+            free.append(oi)
+            checked += 1
+
+        for k in order:
+            if not free:
+                finish()
+            oi = free.pop()
+            inflight.append((srv.submit(fr[k], outs[oi]), oi, k))
+        while inflight:
+            finish()
+        st = srv.stats()
+    print(f"served {checked} frames on three lanes in {st.batches_run} batches", flush=True)
+    assert checked == len(order) and st.completed >= len(order)
