@@ -350,13 +350,16 @@ def main():
     if not args.profile:
         mb64 = bench_minbias64(rx, tpcca, torch, args, log, knobs)
 
+    # the headline context is not needed any more: closed before the server
+    # starts, so that its stream does not share a hardware queue with the
+    # lanes' streams (HIP gives a process four by default)
+    ctx.close()
+
     # ------------------------------------------------------------ served
     served = None
     if args.served_tfs > 0:
         from paper_1709_00618_amd import serving
         served = serving.bench_served(rx, n_tf=args.served_tfs, log=log)
-
-    ctx.close()
 
     # ---------------------------------------------------------- roofline
     # dominant kernel: the Kalman fit.  What binds it is the memory system's
