@@ -502,7 +502,12 @@ typedef struct {
    64 GiB); at most max_queue (>= 1) frames wait for a lane.  The geometry
    and parameters are copied.  EINVAL on bad arguments, EDEVICE if the
    device cannot be selected; if a lane cannot create its context, the lanes
-   are stopped and that lane's status (EDEVICE, ENOMEM) is returned. */
+   are stopped and that lane's status (EDEVICE, ENOMEM) is returned.  Each
+   lane launches on a stream of its own; HIP gives a process a few hardware
+   queues (GPU_MAX_HW_QUEUES, 4 by default) and streams beyond them share a
+   queue, so lanes whose streams share one run one after the other: keep
+   the lanes plus the process's other busy streams within that number
+   (three lanes measured best beside the default stream). */
 int tpcca_server_create(const tpcca_geometry_t *geo, const tpcca_params_t *params, int device,
                         size_t budget_bytes, int32_t n_streams, int32_t max_queue,
                         tpcca_server_t **out);
