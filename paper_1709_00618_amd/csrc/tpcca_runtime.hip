@@ -964,7 +964,6 @@ int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
   for (auto &e : c->graphs)
     if (e.exec[0] && e.gen == c->generation && e.timing == c->timing && same_capacities(e.cap, capr)) ge = &e;
   if (!ge) {
-    std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
     // a free or outdated entry, else the least recently replayed one
     ge = &c->graphs[0];
     for (auto &e : c->graphs) {
@@ -974,10 +973,12 @@ int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
       }
       if (e.used < ge->used) ge = &e;
     }
-    if (ge->exec[0]) {
-      HIPCHK(c, hipStreamSynchronize(c->stream));  // its last replay has finished
-      drop_graph(*ge);
-    }
+    // its last replay has finished before it is destroyed (waiting on this
+    // context's own stream, outside the lock that other contexts' captures
+    // take)
+    if (ge->exec[0]) HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::lock_guard<std::recursive_mutex> lock(tpcca::device_ops_lock());
+    if (ge->exec[0]) drop_graph(*ge);
     // one graph of the whole sequence, or with timing on one graph per timed
     // segment (HIP events between the replays of the segments)
     const int nseg = c->timing ? 6 : 1;
