@@ -1472,13 +1472,14 @@ __global__ __launch_bounds__(kBlock) void k_claim(Bufs B, ParamsDev P, int run) 
   }
 }
 
-// The selection kernels give each tracklet a group of kGrp lanes (four
+// The selection kernels give each tracklet a group of lanes (eight
 // neighbouring tracklets of the processing order per wave): the group walks
-// the tracklet's hit slots kGrp at a time, so a wave's trip count follows
-// the lengths of four tracklets rather than of sixty-four.
-constexpr int kGrp = 16;
-// the acceptance pass uses narrower groups: a tracklet that loses its first
-// hits is rejected after fewer owner reads
+// the tracklet's hit slots a group width at a time, so a wave's trip count
+// follows the lengths of eight tracklets rather than of sixty-four (groups
+// of 16 lanes measured 2 % slower in the output pass).  In the acceptance
+// pass a tracklet that loses its first hits is rejected after fewer owner
+// reads.
+constexpr int kGrp = 8;
 constexpr int kWonGrp = 8;
 
 // Count the hits a tracklet won, record which, accept or reject (a tracklet
