@@ -166,7 +166,9 @@ int tpcca_reset(tpcca_ctx_t *ctx);
    device addresses read in place; they must stay valid until tpcca_sync().
    Validation of rows and coordinates happens on the device; a bad cluster
    makes the next stage call's tpcca_sync() return EINVAL.  A (slot, sector)
-   may be loaded once per reset.  Errors: EINVAL, ENOMEM, ESTATE. */
+   may be loaded once per reset.  A unit holds at most 2^24 - 1 clusters (hit
+   slots keep a unit-local index in 24 bits); n beyond that is EINVAL and
+   nothing is read.  Errors: EINVAL, ENOMEM, ESTATE. */
 int tpcca_load_sector(tpcca_ctx_t *ctx, int32_t slot, int32_t sector, const tpcca_cluster_t *cl,
                       const uint8_t *row, int32_t n, int32_t flags);
 

@@ -895,7 +895,10 @@ int tpcca_run_batch(tpcca_ctx_t *c, const tpcca_batch_t *bt) {
   const bool graph = (bt->flags & TPCCA_BATCH_GRAPH) != 0;
   int64_t lo = INT64_MAX, hi = 0, tot = 0;
   for (int u = 0; u < bt->n_units; ++u) {
-    if (bt->n[u] < 0 || bt->begin[u] < 0) return TPCCA_EINVAL;
+    if (bt->n[u] < 0 || bt->n[u] > 0xFFFFFF || bt->begin[u] < 0) {
+      c->last_error = "a unit holds 0 .. 2^24 - 1 clusters at a non-negative offset";
+      return TPCCA_EINVAL;
+    }
     if (bt->n[u] == 0) continue;
     lo = std::min<int64_t>(lo, bt->begin[u]);
     hi = std::max<int64_t>(hi, bt->begin[u] + bt->n[u]);

@@ -387,6 +387,28 @@ def test_invalid_clusters_are_reported(tpcca, row_x):
             ctx.sync()
 
 
+def test_units_beyond_the_24_bit_index_are_refused(tpcca, row_x):
+    """n > 2^24 - 1 is EINVAL before anything is read (the buffers here hold
+    only 64 clusters), and the context stays usable afterwards."""
+    import ctypes
+    b = tpcgen.one_sector(seed=1)
+    cl, row, _, _, _ = b.unit(0)
+    small_cl = np.ascontiguousarray(cl[:64], np.float32)
+    small_row = np.ascontiguousarray(row[:64], np.uint8)
+    with tpcca.Context(row_x) as ctx:
+        st = tpcca.lib().tpcca_load_sector(ctx.h, 0, 0, small_cl.ctypes.data, small_row.ctypes.data, 1 << 24,
+                                           tpcca.MEM_HOST)
+        assert st == tpcca.EINVAL
+        with pytest.raises(tpcca.TpccaError) as ei:
+            ctx.run_batch(small_cl, small_row, [(0, 1 << 24, 0, 0)])
+        assert ei.value.status == tpcca.EINVAL
+        ctx.reset()
+        ctx.load_sector(0, 0, cl, row)
+        ctx.run_all(0, 0)
+        ctx.sync()
+        _parity.compare_unit_stagewise(ctx, 0, 0, cl, row, oracle.run_sector(cl, row, row_x))
+
+
 def test_stage_order_and_arguments(tpcca, row_x):
     b = tpcgen.one_sector(seed=1)
     cl, row, _, _, _ = b.unit(0)
