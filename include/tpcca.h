@@ -4,7 +4,7 @@
  * The library implements the first phase of the online TPC track finder of
  * Rohr, "Tracking performance in high multiplicities environment at ALICE"
  * (LHCP 2017), Sec. 2: per TPC sector, a Cellular Automaton forms links of
- * hits in adjacent pad rows that lie close to a straight line (Fig. 1a) and
+ * hits in adjacent pad rows that are nearly collinear (Fig. 1a) and
  * concatenates them into short track candidates (Fig. 1b); track following
  * fits every candidate with a simplified Kalman filter, extrapolates through
  * the sector and picks up further clusters (Fig. 1c); the last step selects

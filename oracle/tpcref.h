@@ -7,8 +7,8 @@
  *
  * It follows the sector tracker of Rohr, "Tracking performance in high
  * multiplicities environment at ALICE" (LHCP 2017), Sec. 2: a Cellular
- * Automaton forms links of adjacent-row hits lying close to a straight line
- * and concatenates them into short candidates (Fig. 1a, 1b); track following
+ * Automaton links hits of adjacent rows that are nearly collinear with one
+ * another and joins the links into short candidates (Fig. 1a, 1b); track following
  * fits each candidate with a simplified Kalman filter, extrapolates through
  * the sector and picks up clusters (Fig. 1c); finally good tracks are
  * selected and every cluster is assigned to at most one track.  The paper
