@@ -1482,6 +1482,24 @@ __global__ __launch_bounds__(kBlock) void k_claim(Bufs B, ParamsDev P, int run) 
 constexpr int kGrp = 8;
 constexpr int kWonGrp = 8;
 
+// The block's contiguous piece [x, y) of the processing order [0, n): the
+// order is cut into one slice per XCD (block b runs on XCD b mod 8) and each
+// block of a slice takes a contiguous piece of it, so that the blocks
+// resident on an XCD work on neighbouring tracklets (one or two sectors at a
+// time, whose owner words, IDs and assignment lines then stay in that XCD's
+// L2) instead of strides spread over the whole run.  The pieces partition
+// [0, n) for any grid size.
+__device__ __forceinline__ int2 order_piece(int n) {
+  const int nb = (int)gridDim.x;
+  const int nsl = nb < kXcds ? nb : kXcds;
+  const int x = (int)blockIdx.x % nsl, j = (int)blockIdx.x / nsl;
+  const int nbx = (nb - x + nsl - 1) / nsl;  // blocks of slice x
+  const int s0 = (int)((int64_t)n * x / nsl), s1 = (int)((int64_t)n * (x + 1) / nsl);
+  const int per = (s1 - s0 + nbx - 1) / nbx;
+  const int lo = (int)min((int64_t)s1, (int64_t)s0 + (int64_t)j * per);
+  return make_int2(lo, min(s1, lo + per));
+}
+
 // Count the hits a tracklet won, record which, accept or reject (a tracklet
 // that has already lost too many hits is rejected without reading the rest).
 template <int kG>
@@ -1490,8 +1508,8 @@ __global__ __launch_bounds__(kBlock) void k_won(Bufs B, ParamsDev P, int run) {
   const int R = P.n_rows;
   const int lane = threadIdx.x & 63;
   const int gl = lane & (kG - 1), g0 = lane & ~(kG - 1);
-  const int ng = (gridDim.x * blockDim.x) / kG;
-  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / kG; i < rd.n_trk; i += ng) {
+  const int2 pc = order_piece(rd.n_trk);
+  for (int i = pc.x + (int)threadIdx.x / kG; i < pc.y; i += (int)blockDim.x / kG) {
     const int t = B.kf_order[rd.trk0 + i];
     const int tl = t - rd.trk0;
     const tpcca_tracklet_t &o = B.trk[t];
@@ -1631,8 +1649,8 @@ __global__ __launch_bounds__(kBlock) void k_output(Bufs B, ParamsDev P, int run)
   const int R = P.n_rows;
   const int lane = threadIdx.x & 63;
   const int gl = lane & (kGrp - 1), g0 = lane & ~(kGrp - 1);
-  const int ng = (gridDim.x * blockDim.x) / kGrp;
-  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / kGrp; i < rd.n_trk; i += ng) {
+  const int2 pc = order_piece(rd.n_trk);
+  for (int i = pc.x + (int)threadIdx.x / kGrp; i < pc.y; i += (int)blockDim.x / kGrp) {
     const int t = B.kf_order[rd.trk0 + i];
     const int tl = t - rd.trk0;
     if (B.accv[tl] == 0) continue;
