@@ -1486,9 +1486,9 @@ constexpr int kWonGrp = 8;
 // order is cut into one slice per XCD (block b runs on XCD b mod 8) and each
 // block of a slice takes a contiguous piece of it, so that the blocks
 // resident on an XCD work on neighbouring tracklets (one or two sectors at a
-// time, whose owner words, IDs and assignment lines then stay in that XCD's
-// L2) instead of strides spread over the whole run.  The pieces partition
-// [0, n) for any grid size.
+// time, whose owner words are then shared in that XCD's L2) instead of
+// strides spread over the whole run.  The pieces partition [0, n) for any
+// grid size.
 __device__ __forceinline__ int2 order_piece(int n) {
   const int nb = (int)gridDim.x;
   const int nsl = nb < kXcds ? nb : kXcds;
@@ -1649,8 +1649,10 @@ __global__ __launch_bounds__(kBlock) void k_output(Bufs B, ParamsDev P, int run)
   const int R = P.n_rows;
   const int lane = threadIdx.x & 63;
   const int gl = lane & (kGrp - 1), g0 = lane & ~(kGrp - 1);
-  const int2 pc = order_piece(rd.n_trk);
-  for (int i = pc.x + (int)threadIdx.x / kGrp; i < pc.y; i += (int)blockDim.x / kGrp) {
+  // a grid-stride walk: its scattered assignment stores, not its reads, set
+  // its time, and contiguous pieces per XCD measured slower here
+  const int ng = (gridDim.x * blockDim.x) / kGrp;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / kGrp; i < rd.n_trk; i += ng) {
     const int t = B.kf_order[rd.trk0 + i];
     const int tl = t - rd.trk0;
     if (B.accv[tl] == 0) continue;
