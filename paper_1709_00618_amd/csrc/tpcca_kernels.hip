@@ -776,14 +776,32 @@ __global__ __launch_bounds__(kBlock) void k_starts_compact(Bufs B, int run) {
   }
 }
 
+// The block's contiguous piece [x, y) of a run-ordered list [0, n) (start
+// hits, tracklets): the list is cut into one slice per XCD (block b runs on
+// XCD b mod 8) and each block of a slice takes a contiguous piece of it, so
+// that the blocks resident on an XCD work on neighbouring items (one or two
+// sectors at a time, whose links or owner words are then shared in that
+// XCD's L2) instead of strides spread over the whole run.  The pieces
+// partition [0, n) for any grid size.
+__device__ __forceinline__ int2 order_piece(int n) {
+  const int nb = (int)gridDim.x;
+  const int nsl = nb < kXcds ? nb : kXcds;
+  const int x = (int)blockIdx.x % nsl, j = (int)blockIdx.x / nsl;
+  const int nbx = (nb - x + nsl - 1) / nsl;  // blocks of slice x
+  const int s0 = (int)((int64_t)n * x / nsl), s1 = (int)((int64_t)n * (x + 1) / nsl);
+  const int per = (s1 - s0 + nbx - 1) / nbx;
+  const int lo = (int)min((int64_t)s1, (int64_t)s0 + (int64_t)j * per);
+  return make_int2(lo, min(s1, lo + per));
+}
+
 // Chains: follow the cleaned up links from every start hit; a chain of at
 // least min_chain hits marks its start in cluster-ID order (flag = sorted
 // index + 1) and records (last hit, length).  Thread per start hit of the
 // run's list, so that every resident lane chases a chain.
 __global__ __launch_bounds__(kBlock) void k_chain(Bufs B, ParamsDev P, int run) {
   const RunDev &rd = B.runs[run];
-  const int ns = rd.n_starts;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns; k += gridDim.x * blockDim.x) {
+  const int2 pc = order_piece(rd.n_starts);
+  for (int k = pc.x + (int)threadIdx.x; k < pc.y; k += (int)blockDim.x) {
     const int2 st = B.starts[rd.cl0 + k];
     const int g = st.x;
     int n = 1, last = g, nx = B.upc[g];
@@ -1481,24 +1499,6 @@ __global__ __launch_bounds__(kBlock) void k_claim(Bufs B, ParamsDev P, int run) 
 // reads.
 constexpr int kGrp = 8;
 constexpr int kWonGrp = 8;
-
-// The block's contiguous piece [x, y) of the processing order [0, n): the
-// order is cut into one slice per XCD (block b runs on XCD b mod 8) and each
-// block of a slice takes a contiguous piece of it, so that the blocks
-// resident on an XCD work on neighbouring tracklets (one or two sectors at a
-// time, whose owner words are then shared in that XCD's L2) instead of
-// strides spread over the whole run.  The pieces partition [0, n) for any
-// grid size.
-__device__ __forceinline__ int2 order_piece(int n) {
-  const int nb = (int)gridDim.x;
-  const int nsl = nb < kXcds ? nb : kXcds;
-  const int x = (int)blockIdx.x % nsl, j = (int)blockIdx.x / nsl;
-  const int nbx = (nb - x + nsl - 1) / nsl;  // blocks of slice x
-  const int s0 = (int)((int64_t)n * x / nsl), s1 = (int)((int64_t)n * (x + 1) / nsl);
-  const int per = (s1 - s0 + nbx - 1) / nbx;
-  const int lo = (int)min((int64_t)s1, (int64_t)s0 + (int64_t)j * per);
-  return make_int2(lo, min(s1, lo + per));
-}
 
 // Count the hits a tracklet won, record which, accept or reject (a tracklet
 // that has already lost too many hits is rejected without reading the rest).
