@@ -65,4 +65,24 @@ __device__ T block_exclusive_scan(T v, T *lds /* >= 16 */, T *total) {
   return res;
 }
 
+// The block's contiguous piece [x, y) of a run-ordered list [0, n) (start
+// hits, tracklets, blocks of track hits): the list is cut into one slice per
+// XCD (block b runs on XCD b mod 8) and each block of a slice takes a
+// contiguous piece of it, so that the blocks resident on an XCD work on
+// neighbouring items (one or two sectors at a time, whose links, owner words
+// or clusters are then shared in that XCD's L2) instead of strides spread
+// over the whole run.  The pieces partition [0, n) for any grid size.  (The
+// cleaning and row-scatter passes measured no gain from it: their accesses
+// are local already.)
+__device__ __forceinline__ int2 order_piece(int n) {
+  const int nb = (int)gridDim.x;
+  const int nsl = nb < 8 ? nb : 8;  // the chip's eight XCDs
+  const int x = (int)blockIdx.x % nsl, j = (int)blockIdx.x / nsl;
+  const int nbx = (nb - x + nsl - 1) / nsl;  // blocks of slice x
+  const int s0 = (int)((int64_t)n * x / nsl), s1 = (int)((int64_t)n * (x + 1) / nsl);
+  const int per = (s1 - s0 + nbx - 1) / nbx;
+  const int lo = (int)min((int64_t)s1, (int64_t)s0 + (int64_t)j * per);
+  return make_int2(lo, min(s1, lo + per));
+}
+
 }  // namespace tpcca

@@ -235,7 +235,9 @@ __global__ __launch_bounds__(256) void k_p2_hits(Bufs B, P2Bufs Q, int R) {
   const int U = Q.n_units;
   const int64_t h_lo = B.unit_res[0].hit_begin;
   const int64_t h_hi = B.unit_res[U - 1].hit_begin + B.unit_res[U - 1].n_track_hits;
-  for (int64_t hb = h_lo + blockIdx.x * (int64_t)blockDim.x; hb < h_hi; hb += (int64_t)gridDim.x * blockDim.x) {
+  const int2 pc = order_piece((int)((h_hi - h_lo + blockDim.x - 1) / blockDim.x));
+  for (int ck = pc.x; ck < pc.y; ++ck) {
+    const int64_t hb = h_lo + (int64_t)ck * blockDim.x;
     const int64_t h = hb + threadIdx.x;
     // unit whose hit range holds the block's first hit (ranges ascend with
     // the unit; runs leave gaps), found once per block
