@@ -512,7 +512,8 @@ __device__ __forceinline__ void p2_candidates(const P2Bufs &Q, const P2Params &q
 
 __global__ __launch_bounds__(256) void k_p2_pair_count(P2Bufs Q, P2Params q, int R, int32_t *count) {
   const int n = Q.cnt->n_seg;
-  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
+  const int2 pc = order_piece(n);
+  for (int a = pc.x + (int)threadIdx.x; a < pc.y; a += (int)blockDim.x) {
     int c = 0;
     p2_candidates(Q, q, R, a, [&](int) { ++c; });
     count[a] = c;
@@ -521,7 +522,8 @@ __global__ __launch_bounds__(256) void k_p2_pair_count(P2Bufs Q, P2Params q, int
 
 __global__ __launch_bounds__(256) void k_p2_pair_fill(P2Bufs Q, P2Params q, int R, const int64_t *begin, int2 *pairs) {
   const int n = Q.cnt->n_seg;
-  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
+  const int2 pc = order_piece(n);
+  for (int a = pc.x + (int)threadIdx.x; a < pc.y; a += (int)blockDim.x) {
     int64_t w = begin[a];
     p2_candidates(Q, q, R, a, [&](int i) { pairs[w++] = make_int2(a, Q.bin_seg[i]); });
   }
