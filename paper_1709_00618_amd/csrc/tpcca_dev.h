@@ -74,15 +74,22 @@ __device__ T block_exclusive_scan(T v, T *lds /* >= 16 */, T *total) {
 // over the whole run.  The pieces partition [0, n) for any grid size.  (The
 // cleaning and row-scatter passes measured no gain from it: their accesses
 // are local already.)
-__device__ __forceinline__ int2 order_piece(int n) {
+template <typename I>
+__device__ __forceinline__ void order_range(I n, I &lo, I &hi) {
   const int nb = (int)gridDim.x;
   const int nsl = nb < 8 ? nb : 8;  // the chip's eight XCDs
   const int x = (int)blockIdx.x % nsl, j = (int)blockIdx.x / nsl;
   const int nbx = (nb - x + nsl - 1) / nsl;  // blocks of slice x
-  const int s0 = (int)((int64_t)n * x / nsl), s1 = (int)((int64_t)n * (x + 1) / nsl);
-  const int per = (s1 - s0 + nbx - 1) / nbx;
-  const int lo = (int)min((int64_t)s1, (int64_t)s0 + (int64_t)j * per);
-  return make_int2(lo, min(s1, lo + per));
+  const I s0 = (I)((int64_t)n * x / nsl), s1 = (I)((int64_t)n * (x + 1) / nsl);
+  const I per = (s1 - s0 + nbx - 1) / nbx;
+  const int64_t l = (int64_t)s0 + (int64_t)j * per;
+  lo = l < (int64_t)s1 ? (I)l : s1;
+  hi = lo + per < s1 ? lo + per : s1;
+}
+__device__ __forceinline__ int2 order_piece(int n) {
+  int lo, hi;
+  order_range(n, lo, hi);
+  return make_int2(lo, hi);
 }
 
 }  // namespace tpcca

@@ -535,8 +535,9 @@ __global__ __launch_bounds__(256) void k_p2_pair_fill(P2Bufs Q, P2Params q, int 
 // key).
 __global__ __launch_bounds__(256) void k_p2_pair_eval(Bufs B, P2Bufs Q, ParamsDev P, P2Params q, const int2 *pairs,
                                                       int64_t n_pairs) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_pairs;
-       k += (int64_t)gridDim.x * blockDim.x) {
+  int64_t k0, k1;
+  order_range(n_pairs, k0, k1);
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
     const int2 pr = pairs[k];
     const int a = pr.x, b = pr.y;
     const int ua = Q.seg_unit[a], ub = Q.seg_unit[b];
